@@ -1,0 +1,403 @@
+"""Seeded synthetic inputs: the script profiles, error injection, batches, traces.
+
+This module only draws random code points and strings.  It holds none of the
+transcoding arithmetic: code points are serialized to UTF-8 / UTF-16LE with
+Python's own codecs, and truncation to an exact byte length goes through the codecs
+as well (decode with ``errors="ignore"`` drops a trailing partial character).  Both
+the GPU tests and the oracle tests draw their inputs here; the expected values
+always come from the oracle.
+
+The profiles stand in for the paper's "lipsum" corpus (section 8.1), which is not
+available: code points are i.i.d. per profile with the mixes below.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# (weight, lo, hi) code-point ranges, inclusive.  Weights within a profile sum to 1.
+# "bmp3" is U+0800..FFFF without the surrogate block, handled in _draw_range.
+PROFILES: Dict[str, List[Tuple[float, int, int]]] = {
+    # 64 KiB mixed buffer: 40 % ASCII, 25 % 2-byte, 25 % 3-byte, 10 % 4-byte
+    "mixed4": [(0.40, 0x20, 0x7E), (0.25, 0x80, 0x7FF), (0.25, 0x800, 0xFFFF), (0.10, 0x10000, 0x10FFFF)],
+    "ascii": [(0.95, 0x20, 0x7E), (0.05, 0xA0, 0xFF)],
+    # Latin / Cyrillic / Arabic: 40 % ASCII, 60 % uniform over three 2-byte blocks
+    "latin": [(0.40, 0x20, 0x7E), (0.20, 0xC0, 0xFF), (0.20, 0x400, 0x4FF), (0.20, 0x600, 0x6FF)],
+    "cjk": [(0.90, 0x4E00, 0x9FFF), (0.10, 0x20, 0x7E)],
+    "emoji": [(0.30, 0x1F300, 0x1FAFF), (0.70, 0x20, 0x7E)],
+}
+SCRIPT_PROFILES = ("ascii", "latin", "cjk", "emoji")
+PROFILE_IDS = {"mixed4": 0, "ascii": 1, "latin": 2, "cjk": 3, "emoji": 4}
+DIR_8TO16 = 0
+DIR_16TO8 = 1
+
+# Approximate UTF-8 / UTF-16 bytes per character, used only to size the draws.
+_APPROX_BPC = {"mixed4": (2.05, 2.2), "ascii": (1.05, 2.0), "latin": (1.6, 2.0),
+               "cjk": (2.8, 2.0), "emoji": (1.9, 2.6)}
+
+
+def rng_for(*key: int) -> np.random.Generator:
+    """PCG64 generator seeded from a SeedSequence over the given integers."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(key))))
+
+
+def _draw_range(rng: np.random.Generator, lo: int, hi: int, k: int) -> np.ndarray:
+    if lo == 0x800 and hi == 0xFFFF:
+        # U+0800..FFFF without U+D800..DFFF: 61,440 values
+        v = rng.integers(0, 0xFFFF - 0x800 + 1 - 0x800, size=k, dtype=np.int64) + 0x800
+        v = v + np.where(v >= 0xD800, 0x800, 0)
+        return v
+    return rng.integers(lo, hi + 1, size=k, dtype=np.int64)
+
+
+def draw_codepoints(profile: str, k: int, rng: np.random.Generator) -> np.ndarray:
+    """k i.i.d. code points of the profile, as uint32."""
+    ranges = PROFILES[profile]
+    w = np.array([r[0] for r in ranges], dtype=np.float64)
+    which = rng.choice(len(ranges), size=k, p=w / w.sum())
+    out = np.empty(k, dtype=np.int64)
+    for j, (_, lo, hi) in enumerate(ranges):
+        idx = np.nonzero(which == j)[0]
+        out[idx] = _draw_range(rng, lo, hi, idx.size)
+    return out.astype(np.uint32)
+
+
+def cps_to_str(cps: np.ndarray) -> str:
+    return np.ascontiguousarray(cps, dtype="<u4").tobytes().decode("utf-32-le")
+
+
+def _ascii_pad(rng: np.random.Generator, k: int) -> bytes:
+    return rng.integers(0x20, 0x7F, size=k, dtype=np.uint8).tobytes()
+
+
+def utf8_buffer(profile: str, n_bytes: int, rng: np.random.Generator) -> np.ndarray:
+    """Exactly n_bytes of valid UTF-8: i.i.d. characters of the profile, cut at the
+    last whole character, then padded with printable ASCII."""
+    if n_bytes == 0:
+        return np.zeros(0, dtype=np.uint8)
+    bpc = _APPROX_BPC[profile][0]
+    k = int(n_bytes / bpc * 1.02) + 16
+    b = cps_to_str(draw_codepoints(profile, k, rng)).encode("utf-8")
+    while len(b) < n_bytes:
+        b += cps_to_str(draw_codepoints(profile, k // 4 + 16, rng)).encode("utf-8")
+    cut = b[:n_bytes].decode("utf-8", errors="ignore").encode("utf-8")
+    cut += _ascii_pad(rng, n_bytes - len(cut))
+    return np.frombuffer(cut, dtype=np.uint8).copy()
+
+
+def utf16_buffer(profile: str, n_words: int, rng: np.random.Generator) -> np.ndarray:
+    """Exactly n_words of valid UTF-16LE (never splitting a surrogate pair)."""
+    if n_words == 0:
+        return np.zeros(0, dtype=np.uint16)
+    bpc = _APPROX_BPC[profile][1]
+    k = int(2 * n_words / bpc * 1.02) + 16
+    b = cps_to_str(draw_codepoints(profile, k, rng)).encode("utf-16-le")
+    while len(b) < 2 * n_words:
+        b += cps_to_str(draw_codepoints(profile, k // 4 + 16, rng)).encode("utf-16-le")
+    cut = b[: 2 * n_words].decode("utf-16-le", errors="ignore").encode("utf-16-le")
+    pad = np.frombuffer(_ascii_pad(rng, n_words - len(cut) // 2), dtype=np.uint8).astype("<u2")
+    out = np.concatenate([np.frombuffer(cut, dtype="<u2"), pad])
+    return out.astype(np.uint16)
+
+
+def config_buffer(profile: str, direction: int, n_bytes: int, config: int = 2) -> np.ndarray:
+    """Input for one (config, profile, direction): uint8 for UTF-8, uint16 for UTF-16."""
+    rng = rng_for(0, config, PROFILE_IDS[profile], direction)
+    if direction == DIR_8TO16:
+        return utf8_buffer(profile, n_bytes, rng)
+    return utf16_buffer(profile, n_bytes // 2, rng)
+
+
+def config1_buffer() -> np.ndarray:
+    """The 64 KiB all-valid mixed UTF-8 buffer, seed 0."""
+    return utf8_buffer("mixed4", 65536, rng_for(0))
+
+
+# ---------------------------------------------------------------- error injection
+
+UTF8_KINDS = ("stray", "overlong2", "overlong3", "overlong4", "surrogate", "too_large",
+              "bad_byte", "truncated")
+UTF16_KINDS = ("unpaired_high", "lone_low")
+
+
+def utf8_error_item(kind: str, rng: np.random.Generator) -> bytes:
+    """Byte sequence of one injected UTF-8 error (it is invalid at its first byte
+    when placed at a character boundary and followed by a character start)."""
+    def cont(lo=0x80, hi=0xBF):
+        return int(rng.integers(lo, hi + 1))
+
+    if kind == "stray":
+        return bytes([cont()])
+    if kind == "overlong2":
+        return bytes([int(rng.integers(0xC0, 0xC2)), cont()])
+    if kind == "overlong3":
+        return bytes([0xE0, cont(0x80, 0x9F), cont()])
+    if kind == "overlong4":
+        return bytes([0xF0, cont(0x80, 0x8F), cont(), cont()])
+    if kind == "surrogate":
+        return bytes([0xED, cont(0xA0, 0xBF), cont()])
+    if kind == "too_large":
+        return bytes([0xF4, cont(0x90, 0xBF), cont(), cont()])
+    if kind == "bad_byte":
+        return bytes([int(rng.integers(0xF5, 0xF8)), cont(), cont(), cont()])
+    if kind == "truncated":
+        L = int(rng.integers(2, 5))
+        lead = {2: int(rng.integers(0xC2, 0xE0)), 3: int(rng.integers(0xE1, 0xED)),
+                4: int(rng.integers(0xF1, 0xF4))}[L]
+        k = int(rng.integers(0, L - 1))  # fewer continuation bytes than needed
+        return bytes([lead] + [cont() for _ in range(k)])
+    raise ValueError(kind)
+
+
+def utf16_error_item(kind: str, rng: np.random.Generator) -> List[int]:
+    if kind == "unpaired_high":
+        return [int(rng.integers(0xD800, 0xDC00))]
+    if kind == "lone_low":
+        return [int(rng.integers(0xDC00, 0xE000))]
+    raise ValueError(kind)
+
+
+@dataclass
+class Injected:
+    data: np.ndarray          # uint8 (UTF-8) or uint16 (UTF-16) input
+    positions: np.ndarray     # offsets (input units) of the injected items, ascending
+    kinds: List[str]
+
+
+def inject_utf8(profile: str, n_bytes: int, rate: float, rng: np.random.Generator,
+                kinds: Sequence[str] = UTF8_KINDS) -> Injected:
+    """n_bytes of the profile with about round(rate * n_bytes) error items placed at
+    character boundaries chosen uniformly, each followed by at least one whole
+    character; the length stays n_bytes (ASCII padding at the end)."""
+    bpc = _APPROX_BPC[profile][0]
+    k = int(n_bytes / bpc * 1.05) + 64
+    cps = draw_codepoints(profile, k, rng)
+    n_err = max(1, int(round(rate * n_bytes))) if rate > 0 else 0
+    at = np.sort(rng.choice(k, size=min(n_err, k), replace=False)) if n_err else np.zeros(0, np.int64)
+    parts: List[bytes] = []
+    pos: List[int] = []
+    knd: List[str] = []
+    off = 0
+    prev = 0
+    last_end = 0
+    for a in at.tolist():
+        if pos and a <= prev:
+            continue  # keep a whole character between two items
+        seg = cps_to_str(cps[prev:a]).encode("utf-8")
+        kd = kinds[int(rng.integers(0, len(kinds)))]
+        item = utf8_error_item(kd, rng)
+        if off + len(seg) + len(item) > n_bytes:
+            break
+        parts.append(seg)
+        off += len(seg)
+        parts.append(item)
+        pos.append(off)
+        knd.append(kd)
+        off += len(item)
+        last_end = off
+        prev = a + 1
+    parts.append(cps_to_str(cps[prev:]).encode("utf-8"))
+    b = b"".join(parts)
+    if len(b) > n_bytes:
+        tail = b[last_end:n_bytes].decode("utf-8", errors="ignore").encode("utf-8")
+        b = b[:last_end] + tail
+    b += _ascii_pad(rng, n_bytes - len(b))
+    return Injected(np.frombuffer(b, dtype=np.uint8).copy(), np.array(pos, dtype=np.int64), knd)
+
+
+def inject_utf16(profile: str, n_words: int, rate: float, rng: np.random.Generator,
+                 kinds: Sequence[str] = UTF16_KINDS) -> Injected:
+    """n_words of the profile with unpaired surrogates injected at character
+    boundaries, each followed by at least one whole character."""
+    bpc = _APPROX_BPC[profile][1]
+    k = int(2 * n_words / bpc * 1.05) + 64
+    cps = draw_codepoints(profile, k, rng)
+    n_err = max(1, int(round(rate * n_words))) if rate > 0 else 0
+    at = np.sort(rng.choice(k, size=min(n_err, k), replace=False)) if n_err else np.zeros(0, np.int64)
+    parts: List[np.ndarray] = []
+    pos: List[int] = []
+    knd: List[str] = []
+    off = 0
+    prev = 0
+    last_end = 0
+    for a in at.tolist():
+        if pos and a <= prev:
+            continue
+        seg = np.frombuffer(cps_to_str(cps[prev:a]).encode("utf-16-le"), dtype="<u2")
+        kd = kinds[int(rng.integers(0, len(kinds)))]
+        item = np.array(utf16_error_item(kd, rng), dtype="<u2")
+        if off + seg.size + item.size > n_words:
+            break
+        parts.append(seg)
+        off += seg.size
+        parts.append(item)
+        pos.append(off)
+        knd.append(kd)
+        off += item.size
+        last_end = off
+        prev = a + 1
+    parts.append(np.frombuffer(cps_to_str(cps[prev:]).encode("utf-16-le"), dtype="<u2"))
+    w = np.concatenate(parts).astype(np.uint16)
+    if w.size > n_words:
+        tail = w[last_end:n_words].astype("<u2").tobytes().decode("utf-16-le", errors="ignore")
+        w = np.concatenate([w[:last_end], np.frombuffer(tail.encode("utf-16-le"), dtype="<u2")]).astype(np.uint16)
+    if w.size < n_words:
+        pad = rng.integers(0x20, 0x7F, size=n_words - w.size).astype(np.uint16)
+        w = np.concatenate([w, pad])
+    return Injected(w, np.array(pos, dtype=np.int64), knd)
+
+
+# ---------------------------------------------------------------- batches and traces
+
+@dataclass
+class Batch:
+    arena: np.ndarray        # uint8 input arena
+    in_off: np.ndarray       # uint64 byte offsets into arena
+    in_len: np.ndarray       # uint64 lengths in input units (bytes or words)
+    direction: np.ndarray    # uint32, 0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8
+    profile: np.ndarray      # uint8 profile id per string
+    err_pos: np.ndarray      # int64 injected error offset (input units) or -1
+
+
+def lognormal_lengths(rng: np.random.Generator, k: int, median: float, sigma: float,
+                      lo: int, hi: int) -> np.ndarray:
+    z = rng.standard_normal(k)
+    L = np.exp(math.log(median) + sigma * z)
+    return np.clip(np.rint(L), lo, hi).astype(np.int64)
+
+
+def make_batch(n_strings: int, seed_key: Sequence[int] = (0, 4), median: float = 256.0,
+               sigma: float = 2.0, lo: int = 8, hi: int = 4 << 20, err_frac: float = 0.005,
+               align_utf8: int = 1) -> Batch:
+    """Many independent strings of log-normal byte length, mixed profiles and
+    directions, a fraction carrying one injected error.  UTF-8 strings start at
+    arbitrary byte offsets (align_utf8 = 1); UTF-16 strings at even offsets."""
+    rng = rng_for(*seed_key)
+    lens = lognormal_lengths(rng, n_strings, median, sigma, lo, hi)
+    dirs = rng.integers(0, 2, size=n_strings).astype(np.uint32)
+    profs = rng.integers(0, len(SCRIPT_PROFILES), size=n_strings)
+    has_err = rng.random(n_strings) < err_frac
+    pieces: List[np.ndarray] = []
+    in_off = np.zeros(n_strings, dtype=np.uint64)
+    in_len = np.zeros(n_strings, dtype=np.uint64)
+    err_pos = np.full(n_strings, -1, dtype=np.int64)
+    off = 0
+    for i in range(n_strings):
+        prof = SCRIPT_PROFILES[int(profs[i])]
+        L = int(lens[i])
+        srng = rng_for(*seed_key, 1, i)
+        if dirs[i] == DIR_8TO16:
+            pad = int(srng.integers(0, 16)) if align_utf8 == 1 else 0
+            if has_err[i]:
+                inj = inject_utf8(prof, L, 1.0 / max(L, 1), srng)
+                data = inj.data
+                err_pos[i] = int(inj.positions[0]) if inj.positions.size else -1
+            else:
+                data = utf8_buffer(prof, L, srng)
+            raw = data.view(np.uint8)
+            in_len[i] = raw.size
+        else:
+            pad = 2 * int(srng.integers(0, 8))
+            nw = L // 2
+            if has_err[i] and nw > 0:
+                inj = inject_utf16(prof, nw, 1.0 / max(nw, 1), srng)
+                data = inj.data
+                err_pos[i] = int(inj.positions[0]) if inj.positions.size else -1
+            else:
+                data = utf16_buffer(prof, nw, srng)
+            raw = data.astype("<u2").view(np.uint8)
+            in_len[i] = data.size
+            if off % 2:
+                pieces.append(np.zeros(1, dtype=np.uint8))
+                off += 1
+        if pad:
+            pieces.append(np.zeros(pad, dtype=np.uint8))
+            off += pad
+        in_off[i] = off
+        pieces.append(raw)
+        off += raw.size
+    pieces.append(np.zeros(64, dtype=np.uint8))
+    arena = np.concatenate(pieces)
+    return Batch(arena, in_off, in_len, dirs, profs.astype(np.uint8), err_pos)
+
+
+@dataclass
+class Trace:
+    arrival_s: np.ndarray     # float64 arrival times, ascending
+    size_bytes: np.ndarray    # int64 request input sizes
+    direction: np.ndarray     # uint32
+    profile: np.ndarray       # uint8
+
+
+def poisson_trace(rate_per_s: float, duration_s: float, seed_key: Sequence[int] = (0, 5),
+                  median: float = 1024.0, sigma: float = 2.5, lo: int = 8,
+                  hi: int = 16 << 20) -> Trace:
+    rng = rng_for(*seed_key, int(rate_per_s))
+    k = rng.poisson(rate_per_s * duration_s)
+    t = np.sort(rng.uniform(0.0, duration_s, size=k))
+    sizes = lognormal_lengths(rng, k, median, sigma, lo, hi)
+    dirs = rng.integers(0, 2, size=k).astype(np.uint32)
+    profs = rng.integers(0, len(SCRIPT_PROFILES), size=k).astype(np.uint8)
+    return Trace(t, sizes, dirs, profs)
+
+
+def tile_edge_cases(tile_sizes: Sequence[int], n_bytes: int, rng: np.random.Generator,
+                    direction: int) -> List[Tuple[np.ndarray, Optional[int]]]:
+    """Inputs with a truncated sequence / unpaired high surrogate ending exactly at
+    k*T - 1 for each tile size T, plus negative controls (valid characters straddling
+    k*T).  Returns (data, injected_offset or None)."""
+    cases: List[Tuple[np.ndarray, Optional[int]]] = []
+    for T in tile_sizes:
+        if direction == DIR_8TO16:
+            base = utf8_buffer("mixed4", n_bytes, rng)
+            k = max(1, (n_bytes // T) // 2)
+            edge = k * T
+            if edge >= n_bytes:
+                continue
+            b = bytearray(base.tobytes())
+            # make b[edge-1] a lead byte of a 3-byte form with no continuations after it
+            # by rebuilding the region around the edge from whole characters
+            left = bytes(b[: edge - 1]).decode("utf-8", errors="ignore").encode("utf-8")
+            left += b"A" * (edge - 1 - len(left))
+            item = bytes([0xE2])
+            right = b"B" + bytes(b[edge + 1:]).decode("utf-8", errors="ignore").encode("utf-8")
+            data = (left + item + right)[:n_bytes]
+            data += b"C" * (n_bytes - len(data))
+            cases.append((np.frombuffer(data, dtype=np.uint8).copy(), edge - 1))
+            # negative control: a 4-byte character straddling the edge
+            ctrl = (left[:-2] if len(left) >= 2 else left) + b"\xf0\x9d\x92\xaa"
+            ctrl += bytes(b[len(ctrl):]).decode("utf-8", errors="ignore").encode("utf-8")
+            ctrl = ctrl[:n_bytes].decode("utf-8", errors="ignore").encode("utf-8")
+            ctrl += b"D" * (n_bytes - len(ctrl))
+            cases.append((np.frombuffer(ctrl, dtype=np.uint8).copy(), None))
+        else:
+            nw = n_bytes // 2
+            base = utf16_buffer("emoji", nw, rng)
+            Tw = T // 2
+            k = max(1, (nw // Tw) // 2)
+            edge = k * Tw
+            if edge >= nw:
+                continue
+            w = base.copy()
+            # a lone high surrogate at edge-1 followed by a non-surrogate
+            if 0xDC00 <= w[edge - 1] < 0xE000:
+                pass
+            if 0xD800 <= w[edge - 2] < 0xDC00:
+                w[edge - 2] = 0x41
+            w[edge - 1] = 0xD83D
+            w[edge] = 0x42
+            if edge + 1 < nw and 0xDC00 <= w[edge + 1] < 0xE000:
+                w[edge + 1] = 0x43
+            cases.append((w, edge - 1))
+            c = base.copy()
+            if 0xD800 <= c[edge - 2] < 0xDC00:
+                c[edge - 2] = 0x41
+            if edge + 1 < nw and 0xDC00 <= c[edge + 1] < 0xE000:
+                c[edge + 1] = 0x43
+            c[edge - 1] = 0xD83D
+            c[edge] = 0xDE00
+            cases.append((c, None))
+    return cases
