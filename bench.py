@@ -1,0 +1,211 @@
+"""Benchmark: validating transcode input GB/s on one MI355X.
+
+Workload (one step): four 256 MiB buffers, one per synthetic script profile
+(ASCII-heavy, Latin/Cyrillic/Arabic, CJK, emoji), each transcoded in both directions
+with full validation (8 calls, 2 GiB of input).  Inputs are resident in HBM before
+the timed region; each (profile, direction) rotates over several device copies so
+that no call finds its input in the 256 MB Infinity Cache.
+
+Prints ONE JSON line (rank 0).  `value` = input bytes of the step / step time.
+`roofline` describes the dominant kernel (most device time in the step): algorithmic
+bytes (input + output) / its average duration measured with HIP events on the
+launch stream, against the 8 TB/s HBM peak.  `cpu_baseline` times the scalar oracle
+on a bounded sample of the same inputs on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MIB = 1 << 20
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size-mib", type=int, default=256, help="bytes per buffer (MiB)")
+    ap.add_argument("--rotate", type=int, default=3, help="device copies per input")
+    ap.add_argument("--cpu-sample-mib", type=int, default=64, help="oracle sample per case (MiB)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profiles", default="ascii,latin,cjk,emoji")
+    ap.add_argument("--tile", type=int, default=0, help="override tile bytes (4096 or 8192)")
+    ap.add_argument("--seg", type=int, default=0, help="override tiles per segment")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2212_05098_amd as utfx
+    from paper_2212_05098_amd import synth
+
+    torch.cuda.set_device(0)
+    ctx = utfx.Context()
+    if args.tile or args.seg:
+        for op in range(6):
+            t, sg, _ = ctx.get_tuning(op)
+            ctx.set_tuning(op, args.tile or t, args.seg or sg)
+    nbytes = args.size_mib * MIB
+    profiles = args.profiles.split(",")
+    cases = []  # (profile, direction, host_input, [device copies], device_output, in_bytes, out_bytes)
+    for prof in profiles:
+        for d in (synth.DIR_8TO16, synth.DIR_16TO8):
+            t0 = time.time()
+            host = synth.config_buffer(prof, d, nbytes, config=2)
+            src = torch.from_numpy(host.view(np.uint8).copy()).cuda()
+            copies = [src] + [src.clone() for _ in range(args.rotate - 1)]
+            if d == synth.DIR_8TO16:
+                copies = copies
+                out = torch.empty(nbytes, dtype=torch.int16, device="cuda")  # n words
+            else:
+                copies = [c.view(torch.int16) for c in copies]
+                out = torch.empty(3 * (nbytes // 2), dtype=torch.uint8, device="cuda")
+            cases.append([prof, d, host, copies, out, nbytes, 0])
+            log("generated %s dir=%d in %.1fs" % (prof, d, time.time() - t0))
+    res = utfx.result_tensor(len(cases) * 2)
+
+    def call(i, rot):
+        prof, d, host, copies, out, nb, _ = cases[i]
+        src = copies[rot % len(copies)]
+        r = res[24 * i:24 * i + 24]
+        if d == synth.DIR_8TO16:
+            st = ctx.utf8_to_utf16le_async(src, out, r)
+        else:
+            st = ctx.utf16le_to_utf8_async(src, out, r)
+        if st != utfx.OK:
+            raise RuntimeError("launch failed: %d %s" % (st, ctx.last_error()))
+
+    # correctness of the timed configuration (results only; parity tests cover bytes)
+    for i in range(len(cases)):
+        call(i, 0)
+    torch.cuda.synchronize()
+    rs = utfx.results_from_tensor(res)
+    for i, c in enumerate(cases):
+        if rs[i].status != utfx.OK:
+            raise RuntimeError("case %s/%d failed: %r" % (c[0], c[1], rs[i]))
+        c[6] = rs[i].count * (2 if c[1] == synth.DIR_8TO16 else 1)
+        log("case %s dir=%d in=%d out=%d" % (c[0], c[1], c[5], c[6]))
+
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        for i in range(len(cases)):
+            call(i, w)
+    torch.cuda.synchronize()
+
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for i in range(len(cases)):
+            ev[s][i][0].record(stream)
+            call(i, s + 1)
+            ev[s][i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rs = utfx.results_from_tensor(res)
+    assert all(r.status == utfx.OK for r in rs[: len(cases)])
+
+    step_s = (t1 - t0) / args.steps
+    in_bytes = sum(c[5] for c in cases)
+    per_case = []
+    for i, c in enumerate(cases):
+        ms = [ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]
+        avg = sum(ms) / len(ms)
+        per_case.append({
+            "profile": c[0], "dir": "utf8->utf16le" if c[1] == 0 else "utf16le->utf8",
+            "in_bytes": c[5], "out_bytes": c[6], "ms_avg": round(avg, 4), "ms_min": round(min(ms), 4),
+            "in_GBps": round(c[5] / (avg * 1e6), 1),
+            "hbm_frac": round((c[5] + c[6]) / (avg * 1e6) / HBM_PEAK_GBS, 4),
+        })
+    dom = max(range(len(cases)), key=lambda i: per_case[i]["ms_avg"])
+    dc = per_case[dom]
+    achieved = (dc["in_bytes"] + dc["out_bytes"]) / (dc["ms_avg"] * 1e6)
+    kernel = "k_u8_to_u16" if cases[dom][1] == 0 else "k_u16_to_u8"
+    for pc in per_case:
+        log("%-6s %-14s %8.3f ms  in %7.1f GB/s  hbm %.3f" % (pc["profile"], pc["dir"], pc["ms_avg"],
+                                                               pc["in_GBps"], pc["hbm_frac"]))
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+
+        sample = args.cpu_sample_mib * MIB
+        tot_in = 0
+        tot_t = 0.0
+        for c in cases:
+            host = c[2]
+            if c[1] == synth.DIR_8TO16:
+                part = host[:sample]
+                part = np.frombuffer(bytes(part).decode("utf-8", errors="ignore").encode("utf-8"), np.uint8)
+                best = None
+                for _ in range(2):
+                    ta = time.perf_counter()
+                    O.utf8_to_utf16le(part)
+                    tb = time.perf_counter()
+                    best = tb - ta if best is None else min(best, tb - ta)
+                tot_in += part.size
+            else:
+                part = host[: sample // 2]
+                if part.size and 0xD800 <= part[-1] < 0xDC00:
+                    part = part[:-1]
+                best = None
+                for _ in range(2):
+                    ta = time.perf_counter()
+                    O.utf16le_to_utf8(part)
+                    tb = time.perf_counter()
+                    best = tb - ta if best is None else min(best, tb - ta)
+                tot_in += 2 * part.size
+            tot_t += best
+        cpu = {"value": round(tot_in / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "first %d MiB of each of the 8 (profile, direction) inputs, best of 2, "
+                         "single thread" % args.cpu_sample_mib}
+
+    out = {
+        "metric": "validated transcode input GB/s (% HBM peak); batched p50/p99 latency at load",
+        "value": round(in_bytes / step_s / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8/u16 (integer, bit-exact)",
+        "data": "synthetic",
+        "config": {"workload": "four %d MiB buffers (ascii, latin, cjk, emoji profiles), each transcoded "
+                               "UTF-8->UTF-16LE and UTF-16LE->UTF-8 with validation" % args.size_mib,
+                   "buffers": len(cases), "bytes_per_buffer": nbytes, "rotate": args.rotate,
+                   "tuning": {"utf8->utf16le": list(ctx.get_tuning(0)), "utf16le->utf8": list(ctx.get_tuning(1))}},
+        "roofline": {"bound": "hbm", "kernel": kernel, "case": "%s %s" % (dc["profile"], dc["dir"]),
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+        "per_case": per_case,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

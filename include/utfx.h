@@ -1,0 +1,185 @@
+/*
+ * utfx.h -- validating UTF-8 <-> UTF-16LE transcoding on AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of Clausecker & Lemire, "Transcoding Unicode Characters
+ * with AVX-512 Instructions": validating transcoding that, on the first encoding
+ * error, transcodes the characters before it and stops, reporting where (sections
+ * 6.4 and 7.4), with the output length reported to the caller (section 7.5).  Each
+ * direction also has a validate-only call and an output-length query.
+ *
+ * Memory: every data pointer passed to these calls (in, out, results, item tables,
+ * arenas) is a DEVICE pointer (for example a torch tensor's data_ptr()).  The caller
+ * owns all of them; the library never allocates on a call.  The context owns its
+ * workspace (a status word per tile, a few counters), a device result slot and a
+ * pinned host copy of it.
+ *
+ * Threading: one context per HIP stream.  Calls on a context run in stream order;
+ * synchronous calls block the calling thread until their own result is on the host.
+ * Two contexts may run concurrently on different streams.
+ *
+ * Alignment: UTF-8 input and output may start at any byte address.  UTF-16 pointers
+ * must be 2-byte aligned (else UTFX_E_INVALID_ARG).  Lengths are in code units: bytes
+ * for UTF-8, 16-bit words for UTF-16.
+ *
+ * Result (every call): see utfx_result.  Precedence: argument error, then the
+ * earliest encoding error, then UTFX_E_OUTPUT_TOO_SMALL, then UTFX_OK.  n = 0 is OK
+ * with count 0.
+ */
+#ifndef UTFX_H
+#define UTFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct utfx_ctx utfx_ctx;
+
+typedef enum {
+  UTFX_OK = 0,
+  /* UTF-8 error kinds.  The paper reports a position only; the kind is the first
+   * validation rule of section 6.4 that the character starting at the offset breaks,
+   * checked as: byte type, continuation bytes present, shortest form, surrogate,
+   * U+10FFFF bound. */
+  UTFX_E_STRAY_CONT = 1,   /* continuation byte where a character must start (rule 3) */
+  UTFX_E_MISSING_CONT = 2, /* lead byte not followed by its continuation bytes, including
+                              by the end of the input (rule 2) */
+  UTFX_E_OVERLONG = 3,     /* C0/C1, or a 3- or 4-byte form below its minimum (rule 4) */
+  UTFX_E_TOO_LARGE = 4,    /* F4 form above U+10FFFF (rule 5) */
+  UTFX_E_SURROGATE = 5,    /* UTF-8: encoded U+D800..DFFF (rule 6); UTF-16: a high surrogate
+                              not followed by a low one, or a low one not preceded by a high
+                              one (sections 2.1 and 7.4) */
+  UTFX_E_BAD_BYTE = 6,     /* byte F5..FF (rule 1) */
+  UTFX_E_OUTPUT_TOO_SMALL = 16, /* input valid, but the output needs more than cap units */
+  UTFX_E_INVALID_ARG = 17,      /* null pointer with n > 0, misaligned UTF-16 pointer,
+                                   n above UTFX_MAX_UNITS, bad batch descriptor */
+  UTFX_E_DEVICE = 18            /* HIP runtime failure or a watchdog trip; see
+                                   utfx_last_error() */
+} utfx_status;
+
+/* 24-byte call result.
+ *   status   utfx_status
+ *   count    OK: units written (transcode), n (validate), output length (length query);
+ *            encoding error: offset, in input units, of the first invalid unit;
+ *            OUTPUT_TOO_SMALL: output units the input needs
+ *   written  transcode: output units of the valid prefix in[0:count]; those are in
+ *            out[0:min(written, cap)].  On OUTPUT_TOO_SMALL it is 0.
+ *            validate and length query: equal to count.
+ * Output beyond `written` is unspecified (but nothing is stored at or beyond cap). */
+typedef struct {
+  int32_t status;
+  uint32_t reserved;
+  uint64_t count;
+  uint64_t written;
+} utfx_result;
+
+/* Largest n accepted by any call (input units). */
+#define UTFX_MAX_UNITS (((uint64_t)1) << 35)
+
+/* ---- context ------------------------------------------------------------------- */
+
+/* Creates a context bound to `hip_stream` (a hipStream_t; NULL = the default stream)
+ * on the current device.  Allocates the workspace once.  Returns UTFX_OK or
+ * UTFX_E_DEVICE.  *ctx is NULL on failure. */
+utfx_status utfx_create(utfx_ctx **ctx, void *hip_stream);
+/* Destroys the context after draining its stream.  NULL is a no-op. */
+void utfx_destroy(utfx_ctx *ctx);
+/* Text of the last error on this context ("" if none).  Valid until the next call. */
+const char *utfx_last_error(const utfx_ctx *ctx);
+/* Rebinds the context to another stream (work already queued stays where it is). */
+utfx_status utfx_set_stream(utfx_ctx *ctx, void *hip_stream);
+
+/* Tunables of one operation, picked by the autotuner.  op is a utfx_op.
+ * tile_bytes: input bytes one workgroup handles per step (4096 or 8192: 16 bytes per
+ *             thread, so 256 or 512 threads);
+ * tiles_per_segment: steps per workgroup (1..256); a workgroup owns one segment of
+ *             tile_bytes * tiles_per_segment input bytes and performs one cross-
+ *             segment look-back for it;
+ * wgs_per_cu: resident workgroups per compute unit of the batched kernel's persistent
+ *             grid (1..16; ignored by the single-buffer kernels).
+ * Returns UTFX_E_INVALID_ARG for an unsupported value. */
+typedef enum {
+  UTFX_OP_UTF8_TO_UTF16 = 0,
+  UTFX_OP_UTF16_TO_UTF8 = 1,
+  UTFX_OP_VALIDATE_UTF8 = 2,
+  UTFX_OP_VALIDATE_UTF16 = 3,
+  UTFX_OP_LENGTH_UTF8 = 4,
+  UTFX_OP_LENGTH_UTF16 = 5,
+  UTFX_OP_BATCH = 6,
+  UTFX_OP_COUNT_ = 7
+} utfx_op;
+utfx_status utfx_set_tuning(utfx_ctx *ctx, int op, uint32_t tile_bytes, uint32_t tiles_per_segment,
+                            uint32_t wgs_per_cu);
+utfx_status utfx_get_tuning(const utfx_ctx *ctx, int op, uint32_t *tile_bytes, uint32_t *tiles_per_segment,
+                            uint32_t *wgs_per_cu);
+
+/* ---- output-length queries (no validation) -------------------------------------- */
+/* The per-unit length formula summed: UTF-16 words per UTF-8 byte = 1 for each
+ * non-continuation byte plus 1 for each byte F0..FF (section 6.2: output words per
+ * character); UTF-8 bytes per UTF-16 word = 1 below U+0080, 2 below U+0800, 2 for each
+ * surrogate, else 3 (section 7.3).  Exact for valid input and an upper bound of what
+ * the transcode stores otherwise, so cap = length is always large enough. */
+utfx_result utfx_utf16_length_from_utf8(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes);
+utfx_result utfx_utf8_length_from_utf16le(utfx_ctx *ctx, const uint16_t *in, size_t n_words);
+
+/* ---- validation (section 6.4 rules 1-6; sections 2.1 and 7.4 surrogate pairing) -- */
+utfx_result utfx_validate_utf8(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes);
+utfx_result utfx_validate_utf16le(utfx_ctx *ctx, const uint16_t *in, size_t n_words);
+
+/* ---- validating transcode (sections 6 and 7) ------------------------------------- */
+/* out has room for cap units.  The transcode stores out[0:written] of the valid
+ * prefix and may store unspecified values in out[written:cap] after an error. */
+utfx_result utfx_utf8_to_utf16le(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                 uint16_t *out, size_t cap_words);
+utfx_result utfx_utf16le_to_utf8(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                 uint8_t *out, size_t cap_bytes);
+
+/* ---- asynchronous twins ----------------------------------------------------------
+ * Same operations, queued on the context's stream; the result is stored to the
+ * device pointer d_result when the work completes.  The return value reports only
+ * argument errors and launch failures (UTFX_OK if queued).  Nothing is queued when
+ * the arguments are invalid. */
+utfx_status utfx_utf16_length_from_utf8_async(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                              utfx_result *d_result);
+utfx_status utfx_utf8_length_from_utf16le_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                                utfx_result *d_result);
+utfx_status utfx_validate_utf8_async(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                     utfx_result *d_result);
+utfx_status utfx_validate_utf16le_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                        utfx_result *d_result);
+utfx_status utfx_utf8_to_utf16le_async(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                       uint16_t *out, size_t cap_words, utfx_result *d_result);
+utfx_status utfx_utf16le_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                       uint8_t *out, size_t cap_bytes, utfx_result *d_result);
+
+/* ---- batched: many independent strings in one persistent launch ---------------- */
+/* One string.  in_off/out_off are byte offsets into the arenas; in_len is in input
+ * units and out_cap in output units; dir 0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8.
+ * Offsets of UTF-16 data (the input of dir 1, the output of dir 0) must be even.
+ * Each item gets the same result as the single-buffer call on its bytes. */
+typedef struct {
+  uint64_t in_off;
+  uint64_t in_len;
+  uint64_t out_off;
+  uint64_t out_cap;
+  uint32_t dir;
+  uint32_t pad;
+} utfx_item;
+
+/* Plans and runs the batch: d_items (device, n_items entries) describe the strings,
+ * d_results (device, n_items entries) receive one result each.  The per-string tile
+ * table is built on the device, so the call issues a fixed sequence of kernels that
+ * can be captured into a HIP graph and replayed with new contents of the same
+ * buffers.  max_in_units bounds every in_len (used to size the plan); the call fails
+ * with UTFX_E_INVALID_ARG if an item exceeds it or if the plan does not fit the
+ * context's workspace.  Returns UTFX_OK if queued. */
+utfx_status utfx_batch_run(utfx_ctx *ctx, const uint8_t *in_arena, uint8_t *out_arena,
+                           const utfx_item *d_items, uint32_t n_items, uint64_t max_in_units,
+                           utfx_result *d_results);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UTFX_H */

@@ -1,0 +1,325 @@
+"""Validating UTF-8 <-> UTF-16LE transcoding on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over libutfx.so (C ABI in include/utfx.h).  Every step of the
+computation runs in the library's HIP kernels; this module only marshals pointers
+and sizes.  PyTorch supplies device memory and streams.  There is no fallback: if
+libutfx.so is missing or cannot be loaded, every call raises.
+
+The operations are those of Clausecker & Lemire, "Transcoding Unicode Characters with
+AVX-512 Instructions": validating transcoding that stops at the first encoding error
+and reports where (sections 6.4, 7.4), validation alone, and output-length queries.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import NamedTuple, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIBRARY = os.path.join(HERE, "libutfx.so")
+HEADER = os.path.join(ROOT, "include", "utfx.h")
+
+OK = 0
+E_STRAY_CONT = 1
+E_MISSING_CONT = 2
+E_OVERLONG = 3
+E_TOO_LARGE = 4
+E_SURROGATE = 5
+E_BAD_BYTE = 6
+E_OUTPUT_TOO_SMALL = 16
+E_INVALID_ARG = 17
+E_DEVICE = 18
+
+OP_UTF8_TO_UTF16 = 0
+OP_UTF16_TO_UTF8 = 1
+OP_VALIDATE_UTF8 = 2
+OP_VALIDATE_UTF16 = 3
+OP_LENGTH_UTF8 = 4
+OP_LENGTH_UTF16 = 5
+OP_BATCH = 6
+
+DIR_8TO16 = 0
+DIR_16TO8 = 1
+
+
+class CResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_uint32),
+        ("count", ctypes.c_uint64),
+        ("written", ctypes.c_uint64),
+    ]
+
+
+class Result(NamedTuple):
+    status: int
+    count: int
+    written: int
+
+
+class UtfxError(RuntimeError):
+    pass
+
+
+def exported_functions():
+    """Names of the functions include/utfx.h declares."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(utfx_[a-z0-9_]+)\s*\(", text)))
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libutfx.so (build it first with paper_2212_05098_amd.build.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBRARY):
+        raise UtfxError("libutfx.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIBRARY)
+    P = ctypes.c_void_p
+    Z = ctypes.c_size_t
+    U32 = ctypes.c_uint32
+    U64 = ctypes.c_uint64
+    I = ctypes.c_int
+    sigs = {
+        "utfx_create": (I, [ctypes.POINTER(P), P]),
+        "utfx_destroy": (None, [P]),
+        "utfx_last_error": (ctypes.c_char_p, [P]),
+        "utfx_set_stream": (I, [P, P]),
+        "utfx_set_tuning": (I, [P, I, U32, U32, U32]),
+        "utfx_get_tuning": (I, [P, I, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32)]),
+        "utfx_utf16_length_from_utf8": (CResult, [P, P, Z]),
+        "utfx_utf8_length_from_utf16le": (CResult, [P, P, Z]),
+        "utfx_validate_utf8": (CResult, [P, P, Z]),
+        "utfx_validate_utf16le": (CResult, [P, P, Z]),
+        "utfx_utf8_to_utf16le": (CResult, [P, P, Z, P, Z]),
+        "utfx_utf16le_to_utf8": (CResult, [P, P, Z, P, Z]),
+        "utfx_utf16_length_from_utf8_async": (I, [P, P, Z, P]),
+        "utfx_utf8_length_from_utf16le_async": (I, [P, P, Z, P]),
+        "utfx_validate_utf8_async": (I, [P, P, Z, P]),
+        "utfx_validate_utf16le_async": (I, [P, P, Z, P]),
+        "utfx_utf8_to_utf16le_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_utf16le_to_utf8_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_batch_run": (I, [P, P, P, P, U32, U64, P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _res(r: CResult) -> Result:
+    return Result(int(r.status), int(r.count), int(r.written))
+
+
+def _ptr_len(t, unit: int):
+    """(device pointer, length in `unit`-byte code units) of a CUDA tensor."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor on the GPU")
+    if not t.is_cuda:
+        raise UtfxError("tensor must live on the GPU (no CPU path)")
+    if not t.is_contiguous():
+        raise UtfxError("tensor must be contiguous")
+    nbytes = t.numel() * t.element_size()
+    if nbytes % unit:
+        raise UtfxError("tensor byte size is not a multiple of the code unit")
+    return t.data_ptr(), nbytes // unit
+
+
+class Context:
+    """One library context bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None):
+        import torch
+
+        self._lib = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self._lib.utfx_create(ctypes.byref(h), ctypes.c_void_p(stream.cuda_stream))
+        if st != OK:
+            raise UtfxError("utfx_create failed with status %d" % st)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.utfx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def last_error(self) -> str:
+        return (self._lib.utfx_last_error(self._h) or b"").decode()
+
+    def set_tuning(self, op: int, tile_bytes: int, tiles_per_segment: int = 8, wgs_per_cu: int = 4):
+        st = self._lib.utfx_set_tuning(self._h, op, tile_bytes, tiles_per_segment, wgs_per_cu)
+        if st != OK:
+            raise UtfxError("bad tuning %r" % ((op, tile_bytes, tiles_per_segment, wgs_per_cu),))
+
+    def get_tuning(self, op: int):
+        """(tile_bytes, tiles_per_segment, wgs_per_cu) of an operation."""
+        t = ctypes.c_uint32()
+        s = ctypes.c_uint32()
+        w = ctypes.c_uint32()
+        self._lib.utfx_get_tuning(self._h, op, ctypes.byref(t), ctypes.byref(s), ctypes.byref(w))
+        return int(t.value), int(s.value), int(w.value)
+
+    # ---- synchronous calls ------------------------------------------------------
+    def utf16_length_from_utf8(self, src) -> Result:
+        p, n = _ptr_len(src, 1)
+        return _res(self._lib.utfx_utf16_length_from_utf8(self._h, p, n))
+
+    def utf8_length_from_utf16le(self, src) -> Result:
+        p, n = _ptr_len(src, 2)
+        return _res(self._lib.utfx_utf8_length_from_utf16le(self._h, p, n))
+
+    def validate_utf8(self, src) -> Result:
+        p, n = _ptr_len(src, 1)
+        return _res(self._lib.utfx_validate_utf8(self._h, p, n))
+
+    def validate_utf16le(self, src) -> Result:
+        p, n = _ptr_len(src, 2)
+        return _res(self._lib.utfx_validate_utf16le(self._h, p, n))
+
+    def utf8_to_utf16le(self, src, dst) -> Result:
+        p, n = _ptr_len(src, 1)
+        q, cap = _ptr_len(dst, 2)
+        return _res(self._lib.utfx_utf8_to_utf16le(self._h, p, n, q, cap))
+
+    def utf16le_to_utf8(self, src, dst) -> Result:
+        p, n = _ptr_len(src, 2)
+        q, cap = _ptr_len(dst, 1)
+        return _res(self._lib.utfx_utf16le_to_utf8(self._h, p, n, q, cap))
+
+    # raw-pointer forms (for sub-ranges and misaligned views)
+    def raw(self, name: str, *args):
+        fn = getattr(self._lib, name)
+        r = fn(self._h, *args)
+        return _res(r) if isinstance(r, CResult) else int(r)
+
+    # ---- asynchronous calls: result goes to a device tensor of 24 bytes ----------
+    def utf8_to_utf16le_async(self, src, dst, d_result) -> int:
+        p, n = _ptr_len(src, 1)
+        q, cap = _ptr_len(dst, 2)
+        return int(self._lib.utfx_utf8_to_utf16le_async(self._h, p, n, q, cap, d_result.data_ptr()))
+
+    def utf16le_to_utf8_async(self, src, dst, d_result) -> int:
+        p, n = _ptr_len(src, 2)
+        q, cap = _ptr_len(dst, 1)
+        return int(self._lib.utfx_utf16le_to_utf8_async(self._h, p, n, q, cap, d_result.data_ptr()))
+
+    def validate_utf8_async(self, src, d_result) -> int:
+        p, n = _ptr_len(src, 1)
+        return int(self._lib.utfx_validate_utf8_async(self._h, p, n, d_result.data_ptr()))
+
+    def validate_utf16le_async(self, src, d_result) -> int:
+        p, n = _ptr_len(src, 2)
+        return int(self._lib.utfx_validate_utf16le_async(self._h, p, n, d_result.data_ptr()))
+
+    def utf16_length_from_utf8_async(self, src, d_result) -> int:
+        p, n = _ptr_len(src, 1)
+        return int(self._lib.utfx_utf16_length_from_utf8_async(self._h, p, n, d_result.data_ptr()))
+
+    def utf8_length_from_utf16le_async(self, src, d_result) -> int:
+        p, n = _ptr_len(src, 2)
+        return int(self._lib.utfx_utf8_length_from_utf16le_async(self._h, p, n, d_result.data_ptr()))
+
+    def batch_run(self, in_arena, out_arena, d_items, n_items: int, max_in_units: int, d_results) -> int:
+        return int(
+            self._lib.utfx_batch_run(
+                self._h,
+                in_arena.data_ptr(),
+                out_arena.data_ptr(),
+                d_items.data_ptr(),
+                n_items,
+                max_in_units,
+                d_results.data_ptr(),
+            )
+        )
+
+
+def results_from_tensor(t) -> list:
+    """Decode a device or host tensor of utfx_result records (24 bytes each)."""
+    import numpy as np
+
+    b = t.detach().cpu().contiguous().view(-1).numpy().view(np.uint8)
+    rec = np.dtype([("status", "<i4"), ("reserved", "<u4"), ("count", "<u8"), ("written", "<u8")])
+    a = b.view(rec)
+    return [Result(int(x["status"]), int(x["count"]), int(x["written"])) for x in a]
+
+
+def result_tensor(n: int = 1, device="cuda"):
+    """Device buffer for n utfx_result records."""
+    import torch
+
+    return torch.zeros(n * 24, dtype=torch.uint8, device=device)
+
+
+_default_ctx: Optional[Context] = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def utf16_length_from_utf8(src) -> Result:
+    return default_context().utf16_length_from_utf8(src)
+
+
+def utf8_length_from_utf16le(src) -> Result:
+    return default_context().utf8_length_from_utf16le(src)
+
+
+def validate_utf8(src) -> Result:
+    return default_context().validate_utf8(src)
+
+
+def validate_utf16le(src) -> Result:
+    return default_context().validate_utf16le(src)
+
+
+def utf8_to_utf16le(src, dst=None):
+    """Returns (Result, dst).  dst defaults to n words (always large enough)."""
+    import torch
+
+    if dst is None:
+        dst = torch.empty(max(src.numel() * src.element_size(), 1), dtype=torch.int16, device=src.device)
+    return default_context().utf8_to_utf16le(src, dst), dst
+
+
+def utf16le_to_utf8(src, dst=None):
+    """Returns (Result, dst).  dst defaults to 3n bytes (always large enough)."""
+    import torch
+
+    if dst is None:
+        n = (src.numel() * src.element_size()) // 2
+        dst = torch.empty(max(3 * n, 1), dtype=torch.uint8, device=src.device)
+    return default_context().utf16le_to_utf8(src, dst), dst

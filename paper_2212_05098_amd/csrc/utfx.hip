@@ -1,0 +1,417 @@
+// utfx.hip -- host runtime and C ABI of libutfx.so (see include/utfx.h).
+//
+// The context owns a device workspace (a 64-byte header of counters and a status
+// word per tile for the look-back), a device result slot and a pinned host copy of
+// it.  A call checks its arguments, sizes the grid, launches one kernel on the
+// context's stream and, for the synchronous entry points, copies the 24-byte result
+// back.  Kernels reset the workspace counters themselves (the last workgroup of every
+// launch does it), so no call issues a memset and launches can be graph-captured.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "utfx.h"
+#include "utfx_kernels.hpp"
+#include "utfx_batch.hpp"
+
+using namespace utfx_dev;
+
+static_assert(sizeof(utfx_result) == 24, "utfx_result layout");
+static_assert(sizeof(Result) == sizeof(utfx_result), "device result layout");
+static_assert(sizeof(WsHeader) == 64, "workspace header layout");
+
+struct utfx_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cus = 256;
+  WsHeader* ws = nullptr;                 // device header
+  unsigned long long* status = nullptr;   // device status words
+  uint64_t cap_tiles = 0;
+  Result* d_result = nullptr;             // device result slot of synchronous calls
+  Result* h_result = nullptr;             // pinned host copy
+  uint64_t launches = 0;                  // launches since the status words were cleared
+  uint32_t tile_bytes[UTFX_OP_COUNT_];
+  uint32_t seg_tiles[UTFX_OP_COUNT_];
+  uint32_t wgs_per_cu[UTFX_OP_COUNT_];
+  BatchWs batch;                          // batched-path workspace
+  char err[256];
+};
+
+namespace {
+
+constexpr uint64_t kInitialTiles = 1ull << 20;
+constexpr uint64_t kEpochClearEvery = 1ull << 24;  // well inside the 25-bit epoch space
+
+utfx_result mkres(int32_t st, uint64_t count, uint64_t written) {
+  utfx_result r;
+  r.status = st;
+  r.reserved = 0;
+  r.count = count;
+  r.written = written;
+  return r;
+}
+
+void set_err(utfx_ctx* c, const char* what, hipError_t e) {
+  if (!c) return;
+  snprintf(c->err, sizeof(c->err), "%s: %s", what, hipGetErrorString(e));
+}
+
+void set_msg(utfx_ctx* c, const char* what) {
+  if (!c) return;
+  snprintf(c->err, sizeof(c->err), "%s", what);
+}
+
+// (Re)initialises the header and clears every status word.  Synchronous.
+utfx_status init_ws(utfx_ctx* c) {
+  hipError_t e = hipMemsetAsync(c->status, 0, c->cap_tiles * sizeof(unsigned long long), c->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, c->stream, c->ws);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    set_err(c, "workspace init", e);
+    return UTFX_E_DEVICE;
+  }
+  c->launches = 0;
+  return UTFX_OK;
+}
+
+utfx_status alloc_ws(utfx_ctx* c, uint64_t tiles) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(WsHeader) + tiles * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    set_err(c, "workspace allocation", e);
+    return UTFX_E_DEVICE;
+  }
+  c->ws = reinterpret_cast<WsHeader*>(p);
+  c->status = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(p) + sizeof(WsHeader));
+  c->cap_tiles = tiles;
+  return init_ws(c);
+}
+
+// Makes room for `tiles` status words.  Growing synchronises the stream once; a
+// workload of a fixed size never grows again.
+utfx_status ensure_tiles(utfx_ctx* c, uint64_t tiles) {
+  if (c->launches >= kEpochClearEvery) {
+    utfx_status s = init_ws(c);
+    if (s != UTFX_OK) return s;
+  }
+  if (tiles <= c->cap_tiles) return UTFX_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    set_err(c, "stream sync", e);
+    return UTFX_E_DEVICE;
+  }
+  (void)hipFree(c->ws);
+  c->ws = nullptr;
+  c->status = nullptr;
+  uint64_t want = c->cap_tiles;
+  while (want < tiles) want *= 2;
+  return alloc_ws(c, want);
+}
+
+bool valid_tile(uint32_t t) { return t == 4096 || t == 8192; }
+
+// Common launch geometry: base rounded down to 16 bytes, misalignment in units,
+// tiles covering logical positions [-mis, n + extra).
+utfx_status prep(utfx_ctx* c, int op, const void* in, uint64_t n, uint32_t unit, uint64_t extra,
+                 void* result, Launch& L, uint32_t& wg) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(in);
+  L.base = reinterpret_cast<const uint8_t*>(a & ~static_cast<uintptr_t>(15));
+  L.mis = (a & 15) / unit;
+  L.n = n;
+  wg = c->tile_bytes[op] / 16;
+  L.seg = c->seg_tiles[op];
+  L.pad_ = 0;
+  const uint64_t per_seg = static_cast<uint64_t>(wg) * (16 / unit) * L.seg;
+  L.ntiles = (L.mis + n + extra + per_seg - 1) / per_seg;
+  utfx_status s = ensure_tiles(c, L.ntiles);
+  if (s != UTFX_OK) return s;
+  L.ws = c->ws;
+  L.status = c->status;
+  L.result = result;
+  L.out = nullptr;
+  L.cap = 0;
+  return UTFX_OK;
+}
+
+template <template <int> class K>
+struct Launcher;
+
+#define UTFX_DEFINE_LAUNCH(NAME, KERNEL)                                                         \
+  hipError_t NAME(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {                 \
+    switch (wg) {                                                                               \
+      case 256: hipLaunchKernelGGL(KERNEL<256>, dim3((uint32_t)grid), dim3(256), 0, s, L); break; \
+      default: hipLaunchKernelGGL(KERNEL<512>, dim3((uint32_t)grid), dim3(512), 0, s, L); break; \
+    }                                                                                           \
+    return hipGetLastError();                                                                   \
+  }
+
+UTFX_DEFINE_LAUNCH(launch_len8, k_len8)
+UTFX_DEFINE_LAUNCH(launch_len16, k_len16)
+UTFX_DEFINE_LAUNCH(launch_val8, k_validate8)
+UTFX_DEFINE_LAUNCH(launch_val16, k_validate16)
+UTFX_DEFINE_LAUNCH(launch_u8u16, k_u8_to_u16)
+UTFX_DEFINE_LAUNCH(launch_u16u8, k_u16_to_u8)
+UTFX_DEFINE_LAUNCH(launch_fin_u8u16, k_fin_u8u16)
+UTFX_DEFINE_LAUNCH(launch_fin_u16u8, k_fin_u16u8)
+
+// One-workgroup finalisation that follows every main launch on the same stream.
+hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s);
+
+__global__ void k_store_result(Result* r, int32_t st, uint64_t count, uint64_t written) {
+  if (threadIdx.x == 0) {
+    r->status = st;
+    r->reserved = 0;
+    r->count = count;
+    r->written = written;
+  }
+}
+
+utfx_status store_result_async(utfx_ctx* c, void* d_result, int32_t st, uint64_t count, uint64_t written) {
+  hipLaunchKernelGGL(k_store_result, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<Result*>(d_result), st,
+                     count, written);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_err(c, "result launch", e);
+    return UTFX_E_DEVICE;
+  }
+  return UTFX_OK;
+}
+
+enum Kind { LEN8, LEN16, VAL8, VAL16, U8U16, U16U8 };
+
+hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
+  switch (kind) {
+    case LEN8:
+    case LEN16:
+      hipLaunchKernelGGL(k_fin_len<512>, dim3(1), dim3(512), 0, s, L);
+      return hipGetLastError();
+    case VAL8:
+      hipLaunchKernelGGL(k_fin_validate8, dim3(1), dim3(64), 0, s, L);
+      return hipGetLastError();
+    case VAL16:
+      hipLaunchKernelGGL(k_fin_validate16, dim3(1), dim3(64), 0, s, L);
+      return hipGetLastError();
+    case U8U16:
+      return launch_fin_u8u16(wg, 1, L, s);
+    default:
+      return launch_fin_u16u8(wg, 1, L, s);
+  }
+}
+
+utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, uint64_t cap, void* d_result) {
+  if (!c) return UTFX_E_INVALID_ARG;
+  c->err[0] = 0;
+  const bool in16 = (kind == LEN16 || kind == VAL16 || kind == U16U8);
+  const bool out16 = (kind == U8U16);
+  const bool has_out = (kind == U8U16 || kind == U16U8);
+  if (!d_result) {
+    set_msg(c, "null result pointer");
+    return UTFX_E_INVALID_ARG;
+  }
+  if (n > 0 && !in) {
+    set_msg(c, "null input with n > 0");
+    return UTFX_E_INVALID_ARG;
+  }
+  if (n > UTFX_MAX_UNITS) {
+    set_msg(c, "input longer than UTFX_MAX_UNITS");
+    return UTFX_E_INVALID_ARG;
+  }
+  if (in16 && (reinterpret_cast<uintptr_t>(in) & 1)) {
+    set_msg(c, "UTF-16 input not 2-byte aligned");
+    return UTFX_E_INVALID_ARG;
+  }
+  if (has_out && cap > 0 && !out) {
+    set_msg(c, "null output with cap > 0");
+    return UTFX_E_INVALID_ARG;
+  }
+  if (out16 && (reinterpret_cast<uintptr_t>(out) & 1)) {
+    set_msg(c, "UTF-16 output not 2-byte aligned");
+    return UTFX_E_INVALID_ARG;
+  }
+  if (n == 0) return store_result_async(c, d_result, UTFX_OK, 0, 0);
+
+  int op = 0;
+  uint32_t unit = in16 ? 2 : 1;
+  uint64_t extra = 0;
+  switch (kind) {
+    case LEN8: op = UTFX_OP_LENGTH_UTF8; break;
+    case LEN16: op = UTFX_OP_LENGTH_UTF16; break;
+    case VAL8: op = UTFX_OP_VALIDATE_UTF8; extra = 1; break;
+    case VAL16: op = UTFX_OP_VALIDATE_UTF16; extra = 1; break;
+    case U8U16: op = UTFX_OP_UTF8_TO_UTF16; extra = 1; break;
+    case U16U8: op = UTFX_OP_UTF16_TO_UTF8; extra = 1; break;
+  }
+  Launch L;
+  uint32_t wg = 0;
+  utfx_status s = prep(c, op, in, n, unit, extra, d_result, L, wg);
+  if (s != UTFX_OK) return s;
+  L.out = out;
+  L.cap = cap;
+  if (L.ntiles > 0x7FFFFFFFull) {
+    set_msg(c, "grid too large");
+    return UTFX_E_INVALID_ARG;
+  }
+  hipError_t e = hipSuccess;
+  switch (kind) {
+    case LEN8: e = launch_len8(wg, L.ntiles, L, c->stream); break;
+    case LEN16: e = launch_len16(wg, L.ntiles, L, c->stream); break;
+    case VAL8: e = launch_val8(wg, L.ntiles, L, c->stream); break;
+    case VAL16: e = launch_val16(wg, L.ntiles, L, c->stream); break;
+    case U8U16: e = launch_u8u16(wg, L.ntiles, L, c->stream); break;
+    case U16U8: e = launch_u16u8(wg, L.ntiles, L, c->stream); break;
+  }
+  if (e == hipSuccess) e = launch_fin(kind, wg, L, c->stream);
+  if (e != hipSuccess) {
+    set_err(c, "kernel launch", e);
+    return UTFX_E_DEVICE;
+  }
+  c->launches++;
+  return UTFX_OK;
+}
+
+utfx_result run_sync(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, uint64_t cap) {
+  if (!c) return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  utfx_status s = run(c, kind, in, n, out, cap, c->d_result);
+  if (s != UTFX_OK) return mkres(s, 0, 0);
+  hipError_t e = hipMemcpyAsync(c->h_result, c->d_result, sizeof(Result), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    set_err(c, "synchronise", e);
+    return mkres(UTFX_E_DEVICE, 0, 0);
+  }
+  utfx_result r;
+  memcpy(&r, c->h_result, sizeof(r));
+  if (r.status == UTFX_E_DEVICE) {
+    set_msg(c, "look-back watchdog fired; workspace reinitialised");
+    init_ws(c);
+  }
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
+  if (!out) return UTFX_E_INVALID_ARG;
+  *out = nullptr;
+  utfx_ctx* c = new (std::nothrow) utfx_ctx();
+  if (!c) return UTFX_E_DEVICE;
+  c->err[0] = 0;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < UTFX_OP_COUNT_; ++i) {
+    c->tile_bytes[i] = 8192;
+    c->seg_tiles[i] = 8;
+    c->wgs_per_cu[i] = 4;
+  }
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+      c->num_cus = cus;
+  }
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_result), sizeof(Result));
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(Result), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    utfx_destroy(c);
+    return UTFX_E_DEVICE;
+  }
+  if (alloc_ws(c, kInitialTiles) != UTFX_OK || batch_ws_init(c->batch) != hipSuccess) {
+    utfx_destroy(c);
+    return UTFX_E_DEVICE;
+  }
+  *out = c;
+  return UTFX_OK;
+}
+
+void utfx_destroy(utfx_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  batch_ws_free(c->batch);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->d_result) (void)hipFree(c->d_result);
+  if (c->h_result) (void)hipHostFree(c->h_result);
+  delete c;
+}
+
+const char* utfx_last_error(const utfx_ctx* c) { return c ? c->err : "null context"; }
+
+utfx_status utfx_set_stream(utfx_ctx* c, void* hip_stream) {
+  if (!c) return UTFX_E_INVALID_ARG;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return UTFX_OK;
+}
+
+utfx_status utfx_set_tuning(utfx_ctx* c, int op, uint32_t tile_bytes, uint32_t tiles_per_segment,
+                            uint32_t wgs_per_cu) {
+  if (!c || op < 0 || op >= UTFX_OP_COUNT_ || !valid_tile(tile_bytes) || tiles_per_segment < 1 ||
+      tiles_per_segment > 256 || wgs_per_cu < 1 || wgs_per_cu > 16)
+    return UTFX_E_INVALID_ARG;
+  c->tile_bytes[op] = tile_bytes;
+  c->seg_tiles[op] = tiles_per_segment;
+  c->wgs_per_cu[op] = wgs_per_cu;
+  return UTFX_OK;
+}
+
+utfx_status utfx_get_tuning(const utfx_ctx* c, int op, uint32_t* tile_bytes, uint32_t* tiles_per_segment,
+                            uint32_t* wgs_per_cu) {
+  if (!c || op < 0 || op >= UTFX_OP_COUNT_) return UTFX_E_INVALID_ARG;
+  if (tile_bytes) *tile_bytes = c->tile_bytes[op];
+  if (tiles_per_segment) *tiles_per_segment = c->seg_tiles[op];
+  if (wgs_per_cu) *wgs_per_cu = c->wgs_per_cu[op];
+  return UTFX_OK;
+}
+
+utfx_result utfx_utf16_length_from_utf8(utfx_ctx* c, const uint8_t* in, size_t n) {
+  return run_sync(c, LEN8, in, n, nullptr, 0);
+}
+utfx_result utfx_utf8_length_from_utf16le(utfx_ctx* c, const uint16_t* in, size_t n) {
+  return run_sync(c, LEN16, in, n, nullptr, 0);
+}
+utfx_result utfx_validate_utf8(utfx_ctx* c, const uint8_t* in, size_t n) {
+  return run_sync(c, VAL8, in, n, nullptr, 0);
+}
+utfx_result utfx_validate_utf16le(utfx_ctx* c, const uint16_t* in, size_t n) {
+  return run_sync(c, VAL16, in, n, nullptr, 0);
+}
+utfx_result utfx_utf8_to_utf16le(utfx_ctx* c, const uint8_t* in, size_t n, uint16_t* out, size_t cap) {
+  return run_sync(c, U8U16, in, n, out, cap);
+}
+utfx_result utfx_utf16le_to_utf8(utfx_ctx* c, const uint16_t* in, size_t n, uint8_t* out, size_t cap) {
+  return run_sync(c, U16U8, in, n, out, cap);
+}
+
+utfx_status utfx_utf16_length_from_utf8_async(utfx_ctx* c, const uint8_t* in, size_t n, utfx_result* r) {
+  return run(c, LEN8, in, n, nullptr, 0, r);
+}
+utfx_status utfx_utf8_length_from_utf16le_async(utfx_ctx* c, const uint16_t* in, size_t n, utfx_result* r) {
+  return run(c, LEN16, in, n, nullptr, 0, r);
+}
+utfx_status utfx_validate_utf8_async(utfx_ctx* c, const uint8_t* in, size_t n, utfx_result* r) {
+  return run(c, VAL8, in, n, nullptr, 0, r);
+}
+utfx_status utfx_validate_utf16le_async(utfx_ctx* c, const uint16_t* in, size_t n, utfx_result* r) {
+  return run(c, VAL16, in, n, nullptr, 0, r);
+}
+utfx_status utfx_utf8_to_utf16le_async(utfx_ctx* c, const uint8_t* in, size_t n, uint16_t* out, size_t cap,
+                                       utfx_result* r) {
+  return run(c, U8U16, in, n, out, cap, r);
+}
+utfx_status utfx_utf16le_to_utf8_async(utfx_ctx* c, const uint16_t* in, size_t n, uint8_t* out, size_t cap,
+                                       utfx_result* r) {
+  return run(c, U16U8, in, n, out, cap, r);
+}
+
+utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, uint8_t* out_arena, const utfx_item* d_items,
+                           uint32_t n_items, uint64_t max_in_units, utfx_result* d_results) {
+  if (!c) return UTFX_E_INVALID_ARG;
+  c->err[0] = 0;
+  return batch_run(c->batch, c->stream, c->num_cus, c->tile_bytes[UTFX_OP_BATCH], c->wgs_per_cu[UTFX_OP_BATCH],
+                   in_arena, out_arena, d_items, n_items, max_in_units, d_results, c->err, sizeof(c->err));
+}
+
+}  // extern "C"

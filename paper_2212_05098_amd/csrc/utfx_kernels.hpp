@@ -1,0 +1,1076 @@
+// utfx_kernels.hpp -- gfx950 kernels for validating UTF-8 <-> UTF-16LE transcoding.
+//
+// One kernel family per operation: output-length query (reduction), validate
+// (first-error minimum) and transcode (one look-back per segment + LDS-staged
+// coalesced stores), each followed by a one-workgroup finalisation kernel.  What is
+// computed follows Clausecker & Lemire: the UTF-8 byte classes of Table 1, the six
+// validation rules of section 6.4, the bit layout of Figure 1(a), the surrogate
+// arithmetic of sections 6.2 and 7.2, and the abort-at-first-error contract of
+// sections 6.4 and 7.4.  How it is computed is GPU-specific:
+//   * a workgroup owns a segment of `seg` tiles; a tile is one 16-byte chunk per
+//     thread, classified SWAR-style (four bytes per 32-bit operation);
+//   * the paper's serial "advance by the bytes consumed" chain becomes, per segment,
+//     a cheap counting pass (the per-byte output-length formula), one decoupled
+//     look-back across segments, and a per-tile workgroup scan; the segment is read
+//     twice, the second time from cache;
+//   * the paper's compress instruction becomes a scatter into LDS followed by
+//     coalesced 16-byte stores.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "utfx_device.hpp"
+
+namespace utfx_dev {
+
+// ================================================================ UTF-8 loading
+
+// 16 bytes at grid position q0 (aligned).  Bytes outside the input read as 0 (NUL),
+// the padding convention of section 6.3: a NUL is not a continuation byte, so a
+// truncated sequence at the end fails like any other missing continuation.
+__device__ __forceinline__ void load8(const Launch& L, uint64_t q0, uint32_t x[4]) {
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  if (q0 >= lo && q0 + 16 <= hi) {
+    uint4 v = *reinterpret_cast<const uint4*>(L.base + q0);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else {
+    x[0] = x[1] = x[2] = x[3] = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      uint64_t q = q0 + i;
+      if (q >= lo && q < hi) x[i >> 2] |= (uint32_t)L.base[q] << (8 * (i & 3));
+    }
+  }
+}
+
+// The 4 bytes before grid position q0 (q0 is a multiple of 16).
+__device__ __forceinline__ uint32_t load8_prev(const Launch& L, uint64_t q0) {
+  if (q0 == 0) return 0;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const uint64_t q = q0 - 4;
+  if (q >= lo && q + 4 <= hi) return *reinterpret_cast<const uint32_t*>(L.base + q);
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (q + i >= lo && q + i < hi) r |= (uint32_t)L.base[q + i] << (8 * i);
+  }
+  return r;
+}
+
+// Byte masks (0xFF per byte) of the chunk's grid positions in [lo, hi).
+__device__ __forceinline__ void range_masks(uint64_t q0, uint64_t lo, uint64_t hi, uint32_t m[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint64_t q = q0 + 4 * k + i;
+      r |= (q >= lo && q < hi) ? (0xFFu << (8 * i)) : 0u;
+    }
+    m[k] = r;
+  }
+}
+
+// ================================================================ UTF-8 classification
+
+// Byte classes of Table 1, looked up by the top three bits of each byte with one
+// v_perm (an 8-entry byte table).  Flag bits of a class byte:
+//   bit 7  ASCII (00..7F)              bit 3  continuation (80..BF)
+//   bit 6  2-byte lead (C0..DF)        bit 2  any lead >= C0
+//   bit 5  lead >= E0 (3/4-byte)       bit 4  lead >= F0, added by add_f0
+// The bit positions are chosen so that "class of the byte d positions back" lands on
+// bit 7 after a byte shift by d and a bit shift by d (or by 5 for bit 2).
+constexpr uint32_t LUT8_LO = 0x80808080u;  // top bits 000..011: ASCII
+constexpr uint32_t LUT8_HI = 0x24440808u;  // 100, 101: continuation; 110: 2-byte lead; 111: >= E0
+
+__device__ __forceinline__ uint32_t cls_lut(uint32_t v) { return perm(LUT8_HI, LUT8_LO, (v >> 5) & 0x07070707u); }
+// bit 4 for bytes >= F0: a >= E0 byte whose own bit 4 is set
+__device__ __forceinline__ uint32_t f0_bits(uint32_t C, uint32_t v) { return (C >> 1) & v & 0x10101010u; }
+
+// One thread's 16-byte chunk with the 4 bytes before it, and their classes.
+struct Chunk8 {
+  uint32_t x[4];
+  uint32_t xp;
+  uint32_t C[4];
+  uint32_t Cp;
+};
+
+// Wave-uniform content class: 0 = ASCII only, 1 = no byte >= E0, 2 = no byte >= F0,
+// 3 = general.  Lower classes skip work that cannot matter for the wave's bytes.
+// For class 3 the >= F0 bits are merged into the class bytes.
+__device__ __forceinline__ int classify8(Chunk8& c) {
+  c.Cp = cls_lut(c.xp);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c.C[k] = cls_lut(c.x[k]);
+  const uint32_t orc = c.Cp | c.C[0] | c.C[1] | c.C[2] | c.C[3];
+  const uint32_t fp = f0_bits(c.Cp, c.xp), f0 = f0_bits(c.C[0], c.x[0]), f1 = f0_bits(c.C[1], c.x[1]),
+                 f2 = f0_bits(c.C[2], c.x[2]), f3 = f0_bits(c.C[3], c.x[3]);
+  const uint32_t orf = fp | f0 | f1 | f2 | f3;
+  int m = __any(orf != 0) ? 3 : (__any((orc & 0x20202020u) != 0) ? 2 : (__any((orc & 0x0C0C0C0Cu) != 0) ? 1 : 0));
+  m = __builtin_amdgcn_readfirstlane(m);
+  if (m == 3) {
+    c.Cp |= fp;
+    c.C[0] |= f0;
+    c.C[1] |= f1;
+    c.C[2] |= f2;
+    c.C[3] |= f3;
+  }
+  return m;
+}
+
+// Per-chunk analysis, and (DECODE) the UTF-16 words of the chunk.
+//
+// E: bit-7 flag per position that emits one UTF-16 word.  A character emits at its
+// last byte, and a 4-byte character also at its third byte (the high surrogate):
+// the end mask of section 6.1 in its exact form, where a lead of length L marks the
+// position L-1 after it, so E = ascii | lead2 shifted 1 | lead>=E0 shifted 2 |
+// lead>=F0 shifted 3.  It depends only on the bytes at or before the position, so
+// each character of a valid prefix is counted exactly where its words belong.
+//
+// det: some position in [0, n] shows that a rule is broken nearby:
+//   * continuation bytes must be exactly where the leads' lengths put them: the
+//     mismatched-continuation check of section 6.4 (expected: >=C0 one back, >=E0
+//     two back, >=F0 three back; compared with "is a continuation");
+//   * C0/C1 leads (overlong 2-byte forms, section 6.4);
+//   * the second-byte ranges that make 3/4-byte forms overlong, surrogates or larger
+//     than U+10FFFF (the range check of section 6.4), on the lead and the next byte.
+// Every invalid byte j makes some position in [j, j+3] detect, and every detection
+// at p has an invalid byte in [p-3, p]; the exact first error is then found by a
+// scalar check of the chunk (locate8).
+//
+// W[2k], W[2k+1]: the words of positions (4k, 4k+1) and (4k+2, 4k+3) as 16-bit lane
+// pairs.  Each position gathers its last, second-last and third-last bytes with the
+// tag bits stripped (section 6.2) and sums them as s + 64*s1 + 4096*s2 (mod 2^16);
+// s1 counts only at continuation positions and s2 only after a 3/4-byte lead.  The
+// sum is assembled bytewise: low byte s | s1<<6, high byte s1>>2 | s2<<4.  The third
+// byte of a 4-byte character becomes (sum >> 4) + 0xD7C0 and the fourth sum | 0xDC00
+// (the surrogate fix-up of section 6.2, where 0xD7C0 = 0xD800 - 0x40).
+template <int CLS, bool DECODE, bool FULL>
+__device__ __forceinline__ void process8(const Chunk8& c, const uint32_t inE[4], const uint32_t inD[4],
+                                         uint32_t E[4], uint32_t& count, uint32_t& det, uint32_t W[8]) {
+  count = 0;
+  det = 0;
+  uint32_t sp = 0;
+  if (DECODE && CLS != 0) sp = c.xp & ~(bytemask(c.xp) & 0xC0C0C0C0u);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t v = c.x[k];
+    const uint32_t vp = (k == 0) ? c.xp : c.x[k - 1];
+    const uint32_t Ck = c.C[k];
+    const uint32_t Cq = (k == 0) ? c.Cp : c.C[k - 1];
+    uint32_t e;
+    if (CLS == 0) {
+      e = HI;
+      if (DECODE) {
+        W[2 * k] = zx_lo(v);
+        W[2 * k + 1] = zx_hi(v);
+      }
+    } else {
+      const uint32_t S1 = abyte(Ck, Cq, 3);
+      uint32_t S2 = 0, S3 = 0, u = 0;
+      if (CLS >= 2) {
+        S2 = abyte(Ck, Cq, 2);
+        u = S2 << 2;
+        if (CLS == 3) {
+          S3 = abyte(Ck, Cq, 1);
+          u |= S3 << 3;
+        }
+      }
+      e = (Ck | (S1 << 1) | u) & HI;
+      const uint32_t cov = (S1 << 5) | u;
+      uint32_t d = ((Ck << 4) ^ cov) & HI;
+      // C0/C1: a 2-byte lead whose payload bits 4..1 are zero (zero test lands on bit 6,
+      // the 2-byte-lead flag)
+      d |= ~((v & 0x1E1E1E1Eu) + 0x3F3F3F3Fu) & Ck & 0x40404040u;
+      if (CLS >= 2) {
+        // second byte after a 3-byte lead E0..EF: the bad pairs are E0 80..9F and ED A0..BF,
+        // i.e. lead nibble 0 when the next byte's bit 5 is clear and 0xD when it is set:
+        // (lead ^ (bit5 ? 0xD : 0)) & 0xF == 0.  The zero test lands on bit 5, the
+        // lead>=E0 flag of the byte one back.
+        const uint32_t y1 = abyte(v, vp, 3);
+        const uint32_t k13 = perm(0u, 0x00000D00u, (v >> 5) & 0x01010101u);
+        const uint32_t u = (y1 ^ k13) & 0x0F0F0F0Fu;
+        uint32_t lead3 = S1;
+        if (CLS == 3) lead3 &= ~(S1 << 1);  // exclude >= F0 leads
+        d |= ~(u + 0x1F1F1F1Fu) & lead3 & 0x20202020u;
+        if (CLS == 3) {
+          // after a 4-byte lead F0..FF: with c = bits 5..4 of the next byte, v4 = 4a + c
+          // (a = lead & 0xF) is bad exactly when v4 == 0 (F0 80..8F) or v4 >= 17
+          // (F4 90.., F5..FF)
+          const uint32_t a = y1 & 0x0F0F0F0Fu;
+          const uint32_t cc = (v >> 4) & 0x03030303u;
+          const uint32_t v4 = (a << 2) + cc;
+          d |= ((v4 + 0x6F6F6F6Fu) | ~(v4 + 0x7F7F7F7Fu)) & (S1 << 3) & HI;
+        }
+      }
+      det |= FULL ? d : (d & inD[k]);
+      if (DECODE) {
+        const uint32_t M1 = bytemask(v);                   // non-ASCII positions
+        const uint32_t s = v & ~(M1 & 0xC0C0C0C0u);        // tag bits stripped
+        const uint32_t s1 = abyte(s, sp, 3) & M1;          // second-last byte
+        const uint32_t lo = s | ((s1 & 0x03030303u) << 6);
+        uint32_t hi;
+        if (CLS >= 2) {
+          // third-last byte after a 3/4-byte lead; only its low nibble survives
+          const uint32_t s2 = abyte(v, vp, 2) & bytemask(S2 << 2);
+          hi = ((s1 >> 2) & 0x0F0F0F0Fu) | ((s2 << 4) & 0xF0F0F0F0u);
+        } else {
+          hi = (s1 >> 2) & 0x0F0F0F0Fu;
+        }
+        uint32_t wl = perm(hi, lo, 0x05010400u);
+        uint32_t wh = perm(hi, lo, 0x07030602u);
+        if (CLS == 3) {
+          const uint32_t fh = S2 << 3;  // >= F0 two back: the high surrogate
+          const uint32_t fl = S3 << 3;  // >= F0 three back: the low surrogate
+          const us2 hl = (as_us2(wl) >> (us2)(4)) + (us2)(0xD7C0);
+          const us2 hh = (as_us2(wh) >> (us2)(4)) + (us2)(0xD7C0);
+          const uint32_t mhl = lanemask_lo(fh), mhh = lanemask_hi(fh);
+          wl = (as_u32(hl) & mhl) | (wl & ~mhl);
+          wh = (as_u32(hh) & mhh) | (wh & ~mhh);
+          wl |= lanemask_lo(fl) & 0xDC00DC00u;
+          wh |= lanemask_hi(fl) & 0xDC00DC00u;
+        }
+        W[2 * k] = wl;
+        W[2 * k + 1] = wh;
+        sp = s;
+      }
+    }
+    if (!FULL) e &= inE[k];
+    E[k] = e;
+    count += __builtin_popcount(e);
+  }
+}
+
+// Dispatch on the wave's content class and on whether the chunk lies wholly inside
+// the input (then no range masks are applied at all).
+template <bool DECODE>
+__device__ __forceinline__ void process8_any(int cls, bool full, const Chunk8& c, const uint32_t inE[4],
+                                             const uint32_t inD[4], uint32_t E[4], uint32_t& cnt, uint32_t& det,
+                                             uint32_t W[8]) {
+  if (full) {
+    switch (cls) {
+      case 0: process8<0, DECODE, true>(c, inE, inD, E, cnt, det, W); break;
+      case 1: process8<1, DECODE, true>(c, inE, inD, E, cnt, det, W); break;
+      case 2: process8<2, DECODE, true>(c, inE, inD, E, cnt, det, W); break;
+      default: process8<3, DECODE, true>(c, inE, inD, E, cnt, det, W); break;
+    }
+  } else {
+    switch (cls) {
+      case 0: process8<0, DECODE, false>(c, inE, inD, E, cnt, det, W); break;
+      case 1: process8<1, DECODE, false>(c, inE, inD, E, cnt, det, W); break;
+      case 2: process8<2, DECODE, false>(c, inE, inD, E, cnt, det, W); break;
+      default: process8<3, DECODE, false>(c, inE, inD, E, cnt, det, W); break;
+    }
+  }
+}
+
+// Output words per byte (the length-query formula): one per non-continuation byte
+// and one more per byte >= F0.  Counts only positions whose mask byte is set.
+__device__ __forceinline__ uint32_t len8_count(const uint32_t x[4], bool full, const uint32_t m[4]) {
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t v = x[k];
+    const uint32_t nc = (~v | (v << 1)) & HI;  // not a continuation byte
+    const uint32_t f0 = v & (v << 1) & (v << 2) & (v << 3) & HI;
+    if (full) cnt += __builtin_popcount(nc) + __builtin_popcount(f0);
+    else cnt += __builtin_popcount(nc & m[k]) + __builtin_popcount(f0 & m[k]);
+  }
+  return cnt;
+}
+
+// Emit offsets of one byte (bit o set: the byte's character emits a word at the
+// byte's position + o): ASCII 0; 2-byte lead 1; 3-byte lead 2; 4-byte lead 2 and 3.
+__device__ __forceinline__ uint32_t emit_offsets(uint32_t b) {
+  if (b < 0x80) return 1u;
+  if (b < 0xC0) return 0u;
+  if (b < 0xE0) return 2u;
+  if (b < 0xF0) return 4u;
+  return 12u;
+}
+
+// ================================================================ UTF-8 error location
+
+// Kind of the first rule broken by the character starting at in[i] (i < n): the
+// order of the checks follows the scalar decoder (byte type, continuation bytes,
+// shortest form / surrogate / U+10FFFF via the second-byte ranges).
+__device__ int32_t utf8_kind_at(const uint8_t* in, uint64_t n, uint64_t i) {
+  const uint32_t b0 = in[i];
+  if (b0 < 0x80) return ST_OK;
+  if (b0 < 0xC0) return ST_STRAY_CONT;
+  if (b0 < 0xC2) return ST_OVERLONG;
+  if (b0 >= 0xF5) return ST_BAD_BYTE;
+  const int k = b0 >= 0xF0 ? 3 : (b0 >= 0xE0 ? 2 : 1);
+  for (int d = 1; d <= k; ++d) {
+    if (i + d >= n || (in[i + d] & 0xC0) != 0x80) return ST_MISSING_CONT;
+  }
+  const uint32_t b1 = in[i + 1];
+  if (b0 == 0xE0 && b1 < 0xA0) return ST_OVERLONG;
+  if (b0 == 0xF0 && b1 < 0x90) return ST_OVERLONG;
+  if (b0 == 0xED && b1 >= 0xA0) return ST_SURROGATE;
+  if (b0 == 0xF4 && b1 >= 0x90) return ST_TOO_LARGE;
+  return ST_OK;
+}
+
+// Is byte j (< n) the first byte of an invalid character or a stray continuation?
+__device__ bool utf8_flag_at(const uint8_t* in, uint64_t n, uint64_t j) {
+  const uint32_t b = in[j];
+  if ((b & 0xC0) == 0x80) {
+    bool cov = (j >= 1 && in[j - 1] >= 0xC0) || (j >= 2 && in[j - 2] >= 0xE0) ||
+               (j >= 3 && in[j - 3] >= 0xF0);
+    return !cov;
+  }
+  return utf8_kind_at(in, n, j) != ST_OK;
+}
+
+// Exact first invalid byte among logical positions [p_lo, p_hi) clipped to [0, n),
+// or NO_ERR.  Used only for chunks whose analysis detected something.
+__device__ uint64_t locate8(const uint8_t* in, uint64_t n, int64_t p_lo, int64_t p_hi) {
+  if (p_lo < 0) p_lo = 0;
+  if (p_hi > (int64_t)n) p_hi = (int64_t)n;
+  for (int64_t j = p_lo; j < p_hi; ++j) {
+    if (utf8_flag_at(in, n, (uint64_t)j)) return (uint64_t)j;
+  }
+  return NO_ERR;
+}
+
+// ================================================================ UTF-16 side
+
+// 8 words at grid position q0 (in words, a multiple of 8).  Words outside the input
+// read as 0.
+__device__ __forceinline__ void load16(const Launch& L, uint64_t q0, uint32_t x[4]) {
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const uint16_t* b = reinterpret_cast<const uint16_t*>(L.base);
+  if (q0 >= lo && q0 + 8 <= hi) {
+    uint4 v = *reinterpret_cast<const uint4*>(b + q0);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else {
+    x[0] = x[1] = x[2] = x[3] = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      uint64_t q = q0 + i;
+      if (q >= lo && q < hi) x[i >> 1] |= (uint32_t)b[q] << (16 * (i & 1));
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t load16_prev(const Launch& L, uint64_t q0) {
+  if (q0 == 0) return 0;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const uint64_t q = q0 - 1;
+  const uint16_t* b = reinterpret_cast<const uint16_t*>(L.base);
+  return (q >= lo && q < hi) ? (uint32_t)b[q] : 0u;
+}
+
+__device__ __forceinline__ bool is_hi(uint32_t w) { return (w & 0xFC00u) == 0xD800u; }
+__device__ __forceinline__ bool is_lo(uint32_t w) { return (w & 0xFC00u) == 0xDC00u; }
+
+// UTF-8 bytes per UTF-16 word (section 7.3: 1, 2 or 3 bytes; each half of a surrogate
+// pair accounts for 2 of the pair's 4 bytes).
+__device__ __forceinline__ uint32_t len16(uint32_t w) {
+  return w < 0x80u ? 1u : ((w < 0x800u || (w & 0xF800u) == 0xD800u) ? 2u : 3u);
+}
+
+// UTF-8 bytes of one word, little-endian in a dword (Figure 1(a)).  The 3-byte form
+// [E0|w>>12, 80|(w>>6 & 3F), 80|(w & 3F)] is built once; the 2-byte form is its last
+// two bytes with the lead tag raised from 80 to C0, and ASCII is the word itself.  A
+// high surrogate emits the first two bytes of its character, which depend on it alone:
+// with u = (hi & 0x3FF) + 0x40 = code point >> 10 they are F0|u>>8 and 80|(u>>2 & 3F).
+// A low surrogate emits the last two, using the two low bits of the high one.
+template <bool SURR>
+__device__ __forceinline__ uint32_t enc16(uint32_t w, uint32_t prev, uint32_t c) {
+  const uint32_t t3 = 0x008080E0u | (w >> 12) | ((w << 2) & 0x3F00u) | ((w << 16) & 0x3F0000u);
+  uint32_t r = (c == 3) ? t3 : ((c == 2) ? ((t3 >> 8) | 0x40u) : w);
+  if (SURR) {
+    const uint32_t u = (w & 0x3FFu) + 0x40u;
+    const uint32_t th = (0xF0u | (u >> 8)) | ((0x80u | ((u >> 2) & 0x3Fu)) << 8);
+    const uint32_t tl = 0x8080u | ((prev & 3u) << 4) | ((w >> 6) & 0xFu) | ((w & 0x3Fu) << 8);
+    r = is_hi(w) ? th : r;
+    r = is_lo(w) ? tl : r;
+  }
+  return r;
+}
+
+// Two words at a time (16-bit lanes of a dword), for chunks wholly inside the input
+// in waves without surrogates.  Output bytes per word: 1 + [w >= 0x80] + [w >= 0x800].
+__device__ __forceinline__ uint32_t pk_len16(uint32_t X) {
+  const us2 w = as_us2(X);
+  const us2 one = (us2)(1);
+  const us2 a = __builtin_elementwise_min(w >> (us2)(7), one);
+  const us2 b = __builtin_elementwise_min(w >> (us2)(11), one);
+  return as_u32(a + b + one);
+}
+
+// UTF-8 bytes of the two words of X (little-endian in a dword each), given their
+// lengths c (1..3).  The 3-byte form [E0|w>>12, 80|(w>>6 & 3F), 80|(w & 3F)] is built
+// lane-wise and spread to bytes with v_perm; the 2-byte form is its last two bytes
+// with the lead tag raised to C0; ASCII is the word itself.
+__device__ __forceinline__ void pk_enc16(uint32_t X, uint32_t c_lo, uint32_t c_hi, uint32_t& v_lo, uint32_t& v_hi) {
+  const us2 w = as_us2(X);
+  const uint32_t p0 = as_u32(w >> (us2)(12)) | 0x00E000E0u;
+  const uint32_t p1 = (as_u32(w >> (us2)(6)) & 0x003F003Fu) | 0x00800080u;
+  const uint32_t p2 = (X & 0x003F003Fu) | 0x00800080u;
+  const uint32_t q12 = p1 | (p2 << 8);          // bytes: p1.lo, p2.lo, p1.hi, p2.hi
+  const uint32_t q12c = q12 | 0x00400040u;      // p1 with the 2-byte lead tag C0
+  const uint32_t t3l = perm(q12, p0, 0x0C050400u), t3h = perm(q12, p0, 0x0C070602u);
+  const uint32_t t2l = perm(q12c, 0u, 0x0C0C0504u), t2h = perm(q12c, 0u, 0x0C0C0706u);
+  v_lo = c_lo == 3 ? t3l : (c_lo == 2 ? t2l : (X & 0xFFFFu));
+  v_hi = c_hi == 3 ? t3h : (c_hi == 2 ? t2h : (X >> 16));
+}
+
+// Does any of the chunk's words (or the word before it) lie in U+D800..DFFF?
+__device__ __forceinline__ bool any_surrogate(const uint32_t x[4], uint32_t wp) {
+  uint32_t m = ((wp & 0xF800u) == 0xD800u) ? 1u : 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t z = (x[k] ^ 0xD800D800u) & 0xF800F800u;
+    m |= ((z & 0xFFFFu) == 0u || (z >> 16) == 0u) ? 1u : 0u;
+  }
+  return m != 0;
+}
+
+// Exact first unpaired surrogate among [p_lo, p_hi) clipped to [0, n) (sections 2.1, 7.4).
+__device__ uint64_t locate16(const uint16_t* in, uint64_t n, int64_t p_lo, int64_t p_hi) {
+  if (p_lo < 0) p_lo = 0;
+  if (p_hi > (int64_t)n) p_hi = (int64_t)n;
+  for (int64_t j = p_lo; j < p_hi; ++j) {
+    const uint32_t w = in[j];
+    if (is_hi(w) && ((uint64_t)j + 1 >= n || !is_lo(in[j + 1]))) return (uint64_t)j;
+    if (is_lo(w) && (j == 0 || !is_hi(in[j - 1]))) return (uint64_t)j;
+  }
+  return NO_ERR;
+}
+
+// Per chunk of 8 words: output bytes per word (0 outside the input) and detection of
+// unpaired surrogates: position p detects when "p is a low surrogate" differs from
+// "p-1 is a high surrogate" (the sequencing check of section 7.4, with the carry of
+// the previous chunk taken from the neighbouring word).  Returns whether any word of
+// the chunk or its predecessor is a surrogate.
+template <bool FULL>
+__device__ __forceinline__ bool analyze16(const uint32_t x[4], uint32_t wp, uint64_t q0, uint64_t lo, uint64_t hi,
+                                          uint32_t len[8], uint32_t& cnt, bool& det) {
+  cnt = 0;
+  uint32_t d = 0, sur = (wp & 0xF800u) == 0xD800u ? 1u : 0u;
+  uint32_t prev = wp;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+    const uint32_t s = (w & 0xF800u) == 0xD800u ? 1u : 0u;
+    uint32_t c = 1u + (w >= 0x80u ? 1u : 0u) + (w >= 0x800u ? 1u : 0u) - s;
+    uint32_t dd = (is_lo(w) != is_hi(prev)) ? 1u : 0u;
+    if (!FULL) {
+      const uint64_t q = q0 + j;
+      c = (q >= lo && q < hi) ? c : 0u;
+      dd = (q >= lo && q <= hi) ? dd : 0u;
+    }
+    len[j] = c;
+    cnt += c;
+    d |= dd;
+    sur |= s;
+    prev = w;
+  }
+  det = d != 0;
+  return sur != 0;
+}
+
+// ================================================================ shared plumbing
+
+// Segment i is workgroup i.  Workgroups are dispatched in increasing order on each
+// XCD, so every predecessor a look-back waits for has been dispatched or will be once
+// smaller workgroups on its XCD finish; each of those waits only on smaller segments,
+// so every wait ends.  (The look-back watchdog bounds each wait regardless.)  No fences
+// and no single-address counters in the per-segment path: cross-segment data goes
+// through self-contained 64-bit status words, and the result is assembled by a
+// separate one-workgroup finalisation kernel after the launch boundary.
+
+__device__ __forceinline__ uint32_t ld_fault(WsHeader* ws) {
+  return __hip_atomic_load(&ws->fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Finalisation epilogue (one thread): make the workspace ready for the next launch.
+__device__ __forceinline__ void reset_ws(WsHeader* ws) {
+  st_agent(&ws->err, NO_ERR);
+  st_agent(&ws->acc, 0);
+  const uint32_t ep = __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&ws->epoch, (ep + 1) & EPOCH_MASK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void write_result(void* r, int32_t st, uint64_t count, uint64_t written) {
+  Result* res = reinterpret_cast<Result*>(r);
+  res->status = st;
+  res->reserved = 0;
+  res->count = count;
+  res->written = written;
+}
+
+__device__ __forceinline__ uint32_t cur_epoch(WsHeader* ws) {
+  return __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Coalesced store of a tile's staged output.  Stage element PAD + l (0 <= l < total)
+// goes to out[base + l].  Output is written in 16-byte chunks aligned to the
+// destination; a chunk's bytes are gathered from the stage with dword reads and a
+// byte funnel shift.  Elements at or beyond cap are never stored.
+template <int WG, typename U, uint32_t PAD>
+__device__ __forceinline__ void store_stage(const U* stage, uint32_t total, U* out, uint64_t base, uint64_t cap) {
+  constexpr uint32_t PER = 16 / sizeof(U);
+  static_assert(PAD >= PER && PAD % PER == 0, "stage padding");
+  const uint32_t d = (uint32_t)((((uintptr_t)out / sizeof(U)) + base) & (PER - 1));
+  const uint32_t nch = (d + total + PER - 1) / PER;
+  const int64_t g_first = (int64_t)base - (int64_t)d;
+  const uint32_t* s32 = reinterpret_cast<const uint32_t*>(stage);
+  for (uint32_t k = threadIdx.x; k < nch; k += WG) {
+    const int64_t g0 = g_first + (int64_t)(k * PER);
+    const uint32_t l0 = k * PER;  // chunk covers stage elements PAD + l0 - d .. + PER
+    if (l0 >= d && l0 + PER <= d + total && g0 + (int64_t)PER <= (int64_t)cap) {
+      const uint32_t b0 = (PAD + l0 - d) * sizeof(U);
+      const uint32_t w0 = b0 >> 2, sh = b0 & 3;
+      uint32_t v0 = s32[w0], v1 = s32[w0 + 1], v2 = s32[w0 + 2], v3 = s32[w0 + 3], v4 = s32[w0 + 4];
+      uint4 o;
+      o.x = abyte(v1, v0, sh);
+      o.y = abyte(v2, v1, sh);
+      o.z = abyte(v3, v2, sh);
+      o.w = abyte(v4, v3, sh);
+      *reinterpret_cast<uint4*>(out + g0) = o;
+    } else {
+#pragma unroll
+      for (uint32_t i = 0; i < PER; ++i) {
+        const uint32_t l = l0 + i;  // element index relative to d
+        const int64_t g = g0 + (int64_t)i;
+        if (l >= d && l < d + total && g >= 0 && g < (int64_t)cap) out[g] = stage[PAD + l - d];
+      }
+    }
+  }
+}
+
+// Loads chunk q0 of a UTF-8 input with its halo and range masks.
+template <int WG>
+__device__ __forceinline__ bool chunk8(const Launch& L, uint64_t q0, const uint32_t x[4], Chunk8& c,
+                                       uint32_t inE[4], uint32_t inD[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c.x[k] = x[k];
+  c.xp = __shfl_up(x[3], 1, 64);
+  if ((threadIdx.x & 63) == 0) c.xp = load8_prev(L, q0);
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const bool full = q0 >= lo && q0 + 16 <= hi;
+  if (!full) {
+    range_masks(q0, lo, hi, inE);
+    range_masks(q0, lo, hi + 1, inD);
+  }
+  return full;
+}
+
+// ================================================================ length queries
+
+// Section 6.2 / 7.3 output-length formula, summed; no validation.  Each segment
+// stores its partial sum in its status word; k_fin_len adds them up.
+template <int WG>
+__global__ void __launch_bounds__(WG) k_len8(Launch L) {
+  constexpr uint64_t T = 16ull * WG;
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  const uint64_t seg = blockIdx.x;
+  const uint64_t q00 = seg * L.seg * T + 16ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  uint32_t x[4], xn[4], m[4];
+  load8(L, q00, x);
+  uint32_t acc = 0;
+  for (uint32_t s = 0; s < L.seg; ++s) {
+    const uint64_t q0 = q00 + s * T;
+    if (s + 1 < L.seg) load8(L, q0 + T, xn);
+    const bool full = q0 >= lo && q0 + 16 <= hi;
+    if (!full) range_masks(q0, lo, hi, m);
+    acc += len8_count(x, full, m);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = xn[k];
+  }
+  const uint64_t sum = block_sum_u64<WG>(acc, lds);
+  if (threadIdx.x == 0) L.status[seg] = sum;
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_len16(Launch L) {
+  constexpr uint64_t TW = 8ull * WG;
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  const uint64_t seg = blockIdx.x;
+  const uint64_t q00 = seg * L.seg * TW + 8ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  uint32_t x[4], xn[4];
+  load16(L, q00, x);
+  uint32_t acc = 0;
+  for (uint32_t s = 0; s < L.seg; ++s) {
+    const uint64_t q0 = q00 + s * TW;
+    if (s + 1 < L.seg) load16(L, q0 + TW, xn);
+    const bool full = q0 >= lo && q0 + 8 <= hi;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+      acc += (full || (q0 + j >= lo && q0 + j < hi)) ? len16(w) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = xn[k];
+  }
+  const uint64_t sum = block_sum_u64<WG>(acc, lds);
+  if (threadIdx.x == 0) L.status[seg] = sum;
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_fin_len(Launch L) {
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  uint64_t s = 0;
+  for (uint64_t t = threadIdx.x; t < L.ntiles; t += WG) s += L.status[t];
+  s = block_sum_u64<WG>(s, lds);
+  if (threadIdx.x == 0) {
+    write_result(L.result, ld_fault(L.ws) ? ST_DEVICE : ST_OK, s, s);
+    reset_ws(L.ws);
+  }
+}
+
+// ================================================================ validation
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_validate8(Launch L) {
+  constexpr uint64_t T = 16ull * WG;
+  const uint64_t seg = blockIdx.x;
+  const uint64_t q00 = seg * L.seg * T + 16ull * threadIdx.x;
+  uint32_t x[4], xn[4], inE[4], inD[4], E[4], W[8], cnt, det;
+  Chunk8 c;
+  load8(L, q00, x);
+  for (uint32_t s = 0; s < L.seg; ++s) {
+    const uint64_t q0 = q00 + s * T;
+    if (s + 1 < L.seg) load8(L, q0 + T, xn);
+    const bool full = chunk8<WG>(L, q0, x, c, inE, inD);
+    const int cls = classify8(c);
+    process8_any<false>(cls, full, c, inE, inD, E, cnt, det, W);
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
+      const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
+      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = xn[k];
+  }
+}
+
+__global__ void k_fin_validate8(Launch L) {
+  if (threadIdx.x == 0) {
+    const uint64_t err = ld_agent(&L.ws->err);
+    if (ld_fault(L.ws)) write_result(L.result, ST_DEVICE, 0, 0);
+    else if (err != NO_ERR) write_result(L.result, utf8_kind_at(L.base + L.mis, L.n, err), err, err);
+    else write_result(L.result, ST_OK, L.n, L.n);
+    reset_ws(L.ws);
+  }
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_validate16(Launch L) {
+  constexpr uint64_t TW = 8ull * WG;
+  const uint64_t seg = blockIdx.x;
+  const uint64_t q00 = seg * L.seg * TW + 8ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  uint32_t x[4], xn[4], len[8], cnt;
+  bool det;
+  load16(L, q00, x);
+  for (uint32_t s = 0; s < L.seg; ++s) {
+    const uint64_t q0 = q00 + s * TW;
+    if (s + 1 < L.seg) load16(L, q0 + TW, xn);
+    uint32_t wp = __shfl_up(x[3] >> 16, 1, 64);
+    if ((threadIdx.x & 63) == 0) wp = load16_prev(L, q0);
+    if (q0 >= lo && q0 + 8 <= hi) analyze16<true>(x, wp, q0, lo, hi, len, cnt, det);
+    else analyze16<false>(x, wp, q0, lo, hi, len, cnt, det);
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
+      const uint16_t* in = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
+      const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
+      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = xn[k];
+  }
+}
+
+__global__ void k_fin_validate16(Launch L) {
+  if (threadIdx.x == 0) {
+    const uint64_t err = ld_agent(&L.ws->err);
+    if (ld_fault(L.ws)) write_result(L.result, ST_DEVICE, 0, 0);
+    else if (err != NO_ERR) write_result(L.result, ST_SURROGATE, err, err);
+    else write_result(L.result, ST_OK, L.n, L.n);
+    reset_ws(L.ws);
+  }
+}
+
+// ================================================================ UTF-8 -> UTF-16LE
+
+// Words a UTF-8 segment emits (positions [a, m) with m = min(segment end, n)), from
+// the per-byte counts of the segment plus the boundary bytes: characters whose words
+// fall across the segment's start or end (thread 0 only).
+__device__ __forceinline__ int64_t seg_boundary8(const Launch& L, int64_t a, int64_t m) {
+  const uint8_t* in = L.base + L.mis;
+  int64_t corr = 0;
+  const int64_t a0 = a > 0 ? a : 0;
+  // bytes just before the segment whose words land inside it
+  for (int64_t j = a0 - 3; j < a0; ++j) {
+    if (j < 0) continue;
+    const uint32_t off = emit_offsets(in[j]);
+    for (int o = 0; o < 4; ++o)
+      if ((off >> o) & 1) corr += (j + o >= a0 && j + o < m) ? 1 : 0;
+  }
+  // bytes at the end of the segment whose words land beyond it
+  for (int64_t j = m - 3; j < m; ++j) {
+    if (j < a0) continue;
+    const uint32_t off = emit_offsets(in[j]);
+    for (int o = 0; o < 4; ++o)
+      if ((off >> o) & 1) corr -= (j + o >= m) ? 1 : 0;
+  }
+  return corr;
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
+  constexpr uint32_t T = 16u * WG;
+  constexpr uint32_t PAD = 8;
+  constexpr uint32_t SSZ = PAD + T + 16;  // stage words per buffer
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  __shared__ uint32_t scan_scratch[WG / 64];
+  __shared__ __attribute__((aligned(16))) uint16_t stage[2 * SSZ];
+  const uint64_t seg = blockIdx.x;
+  const uint32_t epoch = cur_epoch(L.ws);
+  const uint64_t SEGB = (uint64_t)L.seg * T;
+  const uint64_t q00 = seg * SEGB + 16ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  uint32_t x[4], xn[4];
+  uint64_t seg_total = 0;  // meaningful in thread 0
+
+  // pass 1: words this segment emits
+  {
+    uint32_t m[4];
+    load8(L, q00, x);
+    uint32_t acc = 0;
+    for (uint32_t s = 0; s < L.seg; ++s) {
+      const uint64_t q0 = q00 + s * T;
+      if (s + 1 < L.seg) load8(L, q0 + T, xn);
+      const bool full = q0 >= lo && q0 + 16 <= hi;
+      if (!full) range_masks(q0, lo, hi, m);
+      acc += len8_count(x, full, m);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = xn[k];
+    }
+    const uint64_t sum = block_sum_u64<WG>(acc, lds);
+    if (threadIdx.x == 0) {
+      const int64_t a = (int64_t)(seg * SEGB) - (int64_t)L.mis;
+      int64_t mend = a + (int64_t)SEGB;
+      if (mend > (int64_t)L.n) mend = (int64_t)L.n;
+      seg_total = (uint64_t)((int64_t)sum + seg_boundary8(L, a, mend));
+      publish_aggregate(L.status, seg, seg_total, epoch);
+    }
+  }
+
+  // pass 2: transcode tile by tile (the segment is re-read from cache)
+  uint64_t running = 0;
+  uint32_t buf = 0;
+  load8(L, q00, x);
+  for (uint32_t s = 0; s < L.seg; ++s) {
+    const uint64_t q0 = q00 + s * T;
+    if (s + 1 < L.seg) load8(L, q0 + T, xn);
+    Chunk8 c;
+    uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
+    const bool full = chunk8<WG>(L, q0, x, c, inE, inD);
+    const int cls = classify8(c);
+    process8_any<true>(cls, full, c, inE, inD, E, cnt, det, W);
+    uint32_t total;
+    const uint32_t local = block_excl_scan<WG>(cnt, total, scan_scratch);
+
+    // Scatter: position e writes at the running index of emitted words.  In a chunk
+    // wholly inside the input, a non-emitting position writes a placeholder at the
+    // slot of the next emit, which that emit then overwrites: inside a valid prefix
+    // at most two positions in a row do not emit, so only the last two positions of
+    // a chunk can lack a later emit in the chunk, and those write only real words.
+    // Past the first error every slot is at or beyond `written`.  Chunks that
+    // straddle the start or end of the input write real words only.
+    uint16_t* st = stage + buf * SSZ;
+    uint32_t idx = PAD + local;
+    if (full) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = 4 * k + i;
+          const uint32_t pair = W[2 * k + (i >> 1)];
+          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+          const uint32_t bit = (E[k] >> (8 * i + 7)) & 1u;
+          if (e < 14 || bit) st[idx] = word;
+          idx += bit;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t pair = W[2 * k + (i >> 1)];
+          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+          const uint32_t bit = (E[k] >> (8 * i + 7)) & 1u;
+          if (bit) st[idx] = word;
+          idx += bit;
+        }
+      }
+    }
+    if (s == 0) {
+      // the look-back runs after the first tile's work, when predecessors are likely done
+      if (threadIdx.x < 64) {
+        const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+        if (threadIdx.x == 0) lds[WG / 64] = b;
+      }
+    }
+    __syncthreads();
+    if (s == 0) running = lds[WG / 64];
+    store_stage<WG, uint16_t, PAD>(st, total, reinterpret_cast<uint16_t*>(L.out), running, L.cap);
+    running += total;
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
+      const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
+      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+    }
+    buf ^= 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = xn[k];
+  }
+}
+
+// Words emitted before logical position `off` (the output length of the valid prefix
+// when off is the first error): the segment's exclusive prefix plus the words emitted
+// inside the segment before off.
+template <int WG>
+__device__ uint64_t prefix_words8(const Launch& L, uint64_t off, unsigned long long* lds) {
+  constexpr uint64_t T = 16ull * WG;
+  const uint64_t SEGB = (uint64_t)L.seg * T;
+  const uint64_t qoff = off + L.mis;
+  const uint64_t seg = qoff / SEGB;
+  uint32_t acc = 0;
+  uint32_t x[4];
+  for (uint64_t q0b = seg * SEGB; q0b < qoff + 1; q0b += T) {
+    const uint64_t q0 = q0b + 16ull * threadIdx.x;
+    load8(L, q0, x);
+    Chunk8 c;
+    uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
+    chunk8<WG>(L, q0, x, c, inE, inD);
+    range_masks(q0, L.mis, qoff, inE);  // positions before off (and inside the input)
+    range_masks(q0, L.mis, L.mis + L.n + 1, inD);
+    const int cls = classify8(c);
+    process8_any<false>(cls, false, c, inE, inD, E, cnt, det, W);
+    acc += cnt;
+  }
+  const uint64_t s = block_sum_u64<WG>(acc, lds);
+  const uint64_t before = seg ? tile_inclusive(L.status, seg - 1) : 0;
+  return before + s;
+}
+
+// Result of a UTF-8 -> UTF-16LE launch: error kind and the words of the valid prefix,
+// or the total (checked against cap).
+template <int WG>
+__global__ void __launch_bounds__(WG) k_fin_u8u16(Launch L) {
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  const uint64_t err = ld_agent(&L.ws->err);
+  const bool fault = ld_fault(L.ws) != 0;
+  uint64_t written = 0;
+  if (!fault && err != NO_ERR) written = prefix_words8<WG>(L, err, lds);
+  if (threadIdx.x == 0) {
+    const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
+    if (fault) write_result(L.result, ST_DEVICE, 0, 0);
+    else if (err != NO_ERR) write_result(L.result, utf8_kind_at(L.base + L.mis, L.n, err), err, written);
+    else if (tot > L.cap) write_result(L.result, ST_OUTPUT_TOO_SMALL, tot, 0);
+    else write_result(L.result, ST_OK, tot, tot);
+    reset_ws(L.ws);
+  }
+}
+
+// ================================================================ UTF-16LE -> UTF-8
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
+  constexpr uint32_t TW = 8u * WG;  // words per tile
+  constexpr uint32_t PAD = 16;
+  constexpr uint32_t SSZ = PAD + 3 * TW + 32;  // stage bytes per buffer
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  __shared__ uint32_t scan_scratch[WG / 64];
+  __shared__ __attribute__((aligned(16))) uint8_t stage[2 * SSZ];
+  const uint64_t seg = blockIdx.x;
+  const uint32_t epoch = cur_epoch(L.ws);
+  const uint64_t SEGW = (uint64_t)L.seg * TW;
+  const uint64_t q00 = seg * SEGW + 8ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  uint32_t x[4], xn[4];
+  uint64_t seg_total = 0;  // meaningful in thread 0
+
+  // pass 1: bytes this segment emits (each word's bytes belong to its own position)
+  {
+    load16(L, q00, x);
+    uint32_t acc = 0;
+    for (uint32_t s = 0; s < L.seg; ++s) {
+      const uint64_t q0 = q00 + s * TW;
+      if (s + 1 < L.seg) load16(L, q0 + TW, xn);
+      if (q0 >= lo && q0 + 8 <= hi && !any_surrogate(x, 0u)) {
+        const uint32_t l = pk_len16(x[0]) + pk_len16(x[1]) + pk_len16(x[2]) + pk_len16(x[3]);
+        acc += (l & 0xFFFFu) + (l >> 16);
+      } else if (q0 >= lo && q0 + 8 <= hi) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += len16((x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+          acc += (q0 + j >= lo && q0 + j < hi) ? len16(w) : 0u;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = xn[k];
+    }
+    const uint64_t sum = block_sum_u64<WG>(acc, lds);
+    if (threadIdx.x == 0) {
+      seg_total = sum;
+      publish_aggregate(L.status, seg, seg_total, epoch);
+    }
+  }
+
+  // pass 2: transcode tile by tile
+  uint64_t running = 0;
+  uint32_t buf = 0;
+  load16(L, q00, x);
+  for (uint32_t s = 0; s < L.seg; ++s) {
+    const uint64_t q0 = q00 + s * TW;
+    if (s + 1 < L.seg) load16(L, q0 + TW, xn);
+    uint32_t wp = __shfl_up(x[3] >> 16, 1, 64);
+    if ((threadIdx.x & 63) == 0) wp = load16_prev(L, q0);
+    uint32_t len[8], cnt;
+    bool det = false;
+    const bool full = q0 >= lo && q0 + 8 <= hi;
+    // wave-uniform choice: no surrogate anywhere in the wave's chunks (nor before them)
+    const bool simple = !__any(!full || any_surrogate(x, wp));
+    uint32_t L4[4];
+    if (simple) {
+      cnt = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        L4[k] = pk_len16(x[k]);
+        cnt += (L4[k] & 0xFFFFu) + (L4[k] >> 16);
+      }
+    } else if (full) {
+      analyze16<true>(x, wp, q0, lo, hi, len, cnt, det);
+    } else {
+      analyze16<false>(x, wp, q0, lo, hi, len, cnt, det);
+    }
+    uint32_t total;
+    const uint32_t local = block_excl_scan<WG>(cnt, total, scan_scratch);
+
+    // Scatter: in a chunk wholly inside the input every word writes three bytes at
+    // the running offset, and the unused ones are overwritten by the following words
+    // (each later word adds at least one byte); the last two words of the chunk write
+    // only their own bytes.  Chunks that straddle the start or end of the input
+    // write only real bytes.
+    uint8_t* st = stage + buf * SSZ;
+    uint32_t o = PAD + local;
+    if (simple) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t cl = L4[k] & 0xFFFFu, ch = L4[k] >> 16;
+        uint32_t vl, vh;
+        pk_enc16(x[k], cl, ch, vl, vh);
+        const bool last = (k == 3);  // words 6 and 7 write only their own bytes
+        st[o] = (uint8_t)vl;
+        if (!last || cl >= 2) st[o + 1] = (uint8_t)(vl >> 8);
+        if (!last || cl >= 3) st[o + 2] = (uint8_t)(vl >> 16);
+        o += cl;
+        st[o] = (uint8_t)vh;
+        if (!last || ch >= 2) st[o + 1] = (uint8_t)(vh >> 8);
+        if (!last || ch >= 3) st[o + 2] = (uint8_t)(vh >> 16);
+        o += ch;
+      }
+    } else {
+      uint32_t prev = wp;
+      const bool wave_sur = __any(any_surrogate(x, wp));
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+        const uint32_t cj = len[j];
+        const uint32_t v = wave_sur ? enc16<true>(w, prev, cj) : enc16<false>(w, prev, cj);
+        const bool spare = full && j < 6;
+        if (spare || cj >= 1) st[o] = (uint8_t)v;
+        if (spare || cj >= 2) st[o + 1] = (uint8_t)(v >> 8);
+        if (spare || cj >= 3) st[o + 2] = (uint8_t)(v >> 16);
+        o += cj;
+        prev = w;
+      }
+    }
+    if (s == 0) {
+      if (threadIdx.x < 64) {
+        const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+        if (threadIdx.x == 0) lds[WG / 64] = b;
+      }
+    }
+    __syncthreads();
+    if (s == 0) running = lds[WG / 64];
+    store_stage<WG, uint8_t, PAD>(st, total, reinterpret_cast<uint8_t*>(L.out), running, L.cap);
+    running += total;
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
+      const uint16_t* in = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
+      const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
+      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+    }
+    buf ^= 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = xn[k];
+  }
+}
+
+template <int WG>
+__device__ uint64_t prefix_bytes16(const Launch& L, uint64_t off, unsigned long long* lds) {
+  constexpr uint64_t TW = 8ull * WG;
+  const uint64_t SEGW = (uint64_t)L.seg * TW;
+  const uint64_t qoff = off + L.mis;
+  const uint64_t seg = qoff / SEGW;
+  uint32_t acc = 0;
+  uint32_t x[4];
+  for (uint64_t q0b = seg * SEGW; q0b < qoff + 1; q0b += TW) {
+    const uint64_t q0 = q0b + 8ull * threadIdx.x;
+    load16(L, q0, x);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+      acc += (q0 + j >= L.mis && q0 + j < qoff) ? len16(w) : 0u;
+    }
+  }
+  const uint64_t s = block_sum_u64<WG>(acc, lds);
+  const uint64_t before = seg ? tile_inclusive(L.status, seg - 1) : 0;
+  return before + s;
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_fin_u16u8(Launch L) {
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  const uint64_t err = ld_agent(&L.ws->err);
+  const bool fault = ld_fault(L.ws) != 0;
+  uint64_t written = 0;
+  if (!fault && err != NO_ERR) written = prefix_bytes16<WG>(L, err, lds);
+  if (threadIdx.x == 0) {
+    const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
+    if (fault) write_result(L.result, ST_DEVICE, 0, 0);
+    else if (err != NO_ERR) write_result(L.result, ST_SURROGATE, err, written);
+    else if (tot > L.cap) write_result(L.result, ST_OUTPUT_TOO_SMALL, tot, 0);
+    else write_result(L.result, ST_OK, tot, tot);
+    reset_ws(L.ws);
+  }
+}
+
+// Workspace initialisation (called once per context, outside any capture).
+__global__ void k_ws_init(WsHeader* ws) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ws->spare0 = 0;
+    ws->spare1 = 0;
+    ws->err = NO_ERR;
+    ws->acc = 0;
+    ws->epoch = 1;
+    ws->fault = 0;
+  }
+}
+
+}  // namespace utfx_dev

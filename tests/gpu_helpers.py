@@ -1,0 +1,95 @@
+"""Helpers shared by the GPU tests: device upload, oracle comparison, progress notes."""
+import sys
+
+import numpy as np
+
+import oracle as O
+
+
+def note(msg):
+    """Name the case on the real stderr before a GPU step (survives a crashed run)."""
+    sys.__stderr__.write("[gpu-case] %s\n" % msg)
+    sys.__stderr__.flush()
+
+
+def dev_u8(a, pad_front=0, pad_back=0):
+    """Upload bytes; returns (tensor_view, backing).  pad_front shifts the start
+    address by that many bytes (misalignment tests)."""
+    import torch
+
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    back = torch.zeros(pad_front + a.size + pad_back + 16, dtype=torch.uint8, device="cuda")
+    if a.size:
+        back[pad_front:pad_front + a.size] = torch.from_numpy(a.copy()).cuda()
+    return back[pad_front:pad_front + a.size], back
+
+
+def dev_u16(w, pad_front_words=0, pad_back=0):
+    """Upload UTF-16 words as an int16 tensor view (2-byte aligned, shifted by
+    pad_front_words words)."""
+    import torch
+
+    w = np.ascontiguousarray(w, dtype=np.uint16)
+    back = torch.zeros(pad_front_words + w.size + pad_back + 8, dtype=torch.int16, device="cuda")
+    if w.size:
+        back[pad_front_words:pad_front_words + w.size] = torch.from_numpy(w.view(np.int16).copy()).cuda()
+    return back[pad_front_words:pad_front_words + w.size], back
+
+
+def host_u16(t):
+    return t.cpu().numpy().view(np.uint16)
+
+
+def host_u8(t):
+    return t.cpu().numpy().view(np.uint8)
+
+
+def check_u8_to_u16(ctx, data, cap=None, in_shift=0, out_shift=0, guard=64):
+    """Run the GPU transcode and the oracle on the same bytes; compare status, count,
+    written, out[:written] and that nothing at or beyond cap changed."""
+    import torch
+
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    n = data.size
+    cap = n if cap is None else cap
+    src, _ = dev_u8(data, pad_front=in_shift)
+    fill = 0x5A5A
+    out_back = torch.full((out_shift + cap + guard,), fill - 0x10000 if fill > 0x7FFF else fill,
+                          dtype=torch.int16, device="cuda")
+    dst = out_back[out_shift:out_shift + cap]
+    r = ctx.utf8_to_utf16le(src, dst)
+    want, ref = O.utf8_to_utf16le(data, cap=cap)
+    assert tuple(r) == tuple(want), (r, want)
+    got = host_u16(out_back)
+    w = min(r.written, cap)
+    assert np.array_equal(got[out_shift:out_shift + w], ref[:w])
+    assert np.all(got[:out_shift] == fill) and np.all(got[out_shift + cap:] == fill)
+    v = ctx.validate_utf8(src)
+    vw = O.validate_utf8(data)
+    assert tuple(v) == tuple(vw), (v, vw)
+    ln = ctx.utf16_length_from_utf8(src)
+    assert tuple(ln) == tuple(O.utf16_length_from_utf8(data))
+    return r
+
+
+def check_u16_to_u8(ctx, words, cap=None, in_shift=0, out_shift=0, guard=64):
+    import torch
+
+    words = np.ascontiguousarray(words, dtype=np.uint16)
+    n = words.size
+    cap = 3 * n if cap is None else cap
+    src, _ = dev_u16(words, pad_front_words=in_shift)
+    out_back = torch.full((out_shift + cap + guard,), 0xA5, dtype=torch.uint8, device="cuda")
+    dst = out_back[out_shift:out_shift + cap]
+    r = ctx.utf16le_to_utf8(src, dst)
+    want, ref = O.utf16le_to_utf8(words, cap=cap)
+    assert tuple(r) == tuple(want), (r, want)
+    got = host_u8(out_back)
+    w = min(r.written, cap)
+    assert np.array_equal(got[out_shift:out_shift + w], ref[:w])
+    assert np.all(got[:out_shift] == 0xA5) and np.all(got[out_shift + cap:] == 0xA5)
+    v = ctx.validate_utf16le(src)
+    assert tuple(v) == tuple(O.validate_utf16le(words))
+    ln = ctx.utf8_length_from_utf16le(src)
+    assert tuple(ln) == tuple(O.utf8_length_from_utf16le(words))
+    return r

@@ -1,0 +1,74 @@
+"""CPU-side checks of the C-ABI library: it builds for gfx950, loads, exports every
+function include/utfx.h declares, and its status codes match the oracle's copy.
+No compute call is made here (there may be no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2212_05098_amd as utfx
+from paper_2212_05098_amd import build as B
+import oracle as O
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    if not os.path.exists(B.LIB):
+        B.build()
+    return B.LIB
+
+
+def test_library_exports_every_declared_function(libpath):
+    names = utfx.exported_functions()
+    assert len(names) >= 19
+    L = ctypes.CDLL(libpath)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header(libpath):
+    L = utfx.lib()
+    for n in utfx.exported_functions():
+        assert getattr(L, n).argtypes is not None, n
+
+
+def _enum(path, prefix):
+    text = open(path).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"\b%s([A-Z_]+)\s*=\s*(\d+)" % prefix, text)}
+
+
+def test_status_codes_match_oracle_copy():
+    lib_codes = _enum(os.path.join(os.path.dirname(B.LIB), "..", "include", "utfx.h"), "UTFX_E_")
+    lib_codes["OK"] = 0
+    ora_codes = _enum(O.HEADER, "UTFX_REF_E_")
+    ora_codes["OK"] = 0
+    for k, v in ora_codes.items():
+        assert lib_codes[k] == v, k
+    assert utfx.E_OUTPUT_TOO_SMALL == lib_codes["OUTPUT_TOO_SMALL"]
+    assert utfx.E_DEVICE == lib_codes["DEVICE"]
+
+
+def test_result_struct_layout():
+    assert ctypes.sizeof(utfx.CResult) == 24
+    assert utfx.CResult.count.offset == 8 and utfx.CResult.written.offset == 16
+
+
+def test_product_path_never_touches_the_oracle():
+    """The library and its binding share nothing with oracle/ and never load it."""
+    pkg = os.path.dirname(utfx.__file__)
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")) and f != "synth.py":
+                text = open(os.path.join(root, f)).read()
+                assert "oracle" not in text.lower(), os.path.join(root, f)
+    text = open(os.path.join(pkg, "synth.py")).read()
+    assert "import oracle" not in text and "from oracle" not in text
+
+
+def test_no_cpu_fallback_without_gpu():
+    """Without a GPU tensor the binding refuses instead of computing on the host."""
+    import torch
+
+    with pytest.raises((utfx.UtfxError, TypeError)):
+        utfx._ptr_len(torch.zeros(4, dtype=torch.uint8), 1)
