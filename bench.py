@@ -40,11 +40,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size-mib", type=int, default=256, help="bytes per buffer (MiB)")
     ap.add_argument("--rotate", type=int, default=3, help="device copies per input")
-    ap.add_argument("--cpu-sample-mib", type=int, default=64, help="oracle sample per case (MiB)")
+    ap.add_argument("--cpu-sample-mib", type=int, default=256, help="oracle sample per case (MiB)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profiles", default="ascii,latin,cjk,emoji")
     ap.add_argument("--tile", type=int, default=0, help="override tile bytes (4096 or 8192)")
     ap.add_argument("--seg", type=int, default=0, help="override tiles per segment")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -74,7 +76,6 @@ def main():
             src = torch.from_numpy(host.view(np.uint8).copy()).cuda()
             copies = [src] + [src.clone() for _ in range(args.rotate - 1)]
             if d == synth.DIR_8TO16:
-                copies = copies
                 out = torch.empty(nbytes, dtype=torch.int16, device="cuda")  # n words
             else:
                 copies = [c.view(torch.int16) for c in copies]
@@ -145,6 +146,32 @@ def main():
         log("%-6s %-14s %8.3f ms  in %7.1f GB/s  hbm %.3f" % (pc["profile"], pc["dir"], pc["ms_avg"],
                                                                pc["in_GBps"], pc["hbm_frac"]))
 
+    # practical ceiling: a plain device-to-device copy of one input buffer
+    csrc = cases[0][3][0].view(torch.uint8)
+    cdst = torch.empty_like(csrc)
+    for _ in range(2):
+        cdst.copy_(csrc)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record(stream)
+    for _ in range(5):
+        cdst.copy_(csrc)
+    ce1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = ce0.elapsed_time(ce1) / 5
+    copy_gbps = 2 * csrc.numel() / (copy_ms * 1e6)
+    if args.copy_probe:
+        for _ in range(2):
+            cdst.copy_(csrc)
+        torch.cuda.synchronize()
+    del cdst
+    log("device copy %d MiB: %.3f ms = %.1f GB/s (read + write)" % (csrc.numel() // MIB, copy_ms, copy_gbps))
+
+    from paper_2212_05098_amd import profsum
+
+    case_name = "%s %s" % (dc["profile"], dc["dir"])
+    tpath = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%s_%dMiB.txt" % (kernel, dc["profile"], args.size_mib))
+    traffic = profsum.read_traffic(tpath, kernel, case_name)
+
     cpu = None
     if not args.no_cpu:
         import oracle as O
@@ -177,8 +204,8 @@ def main():
                 tot_in += 2 * part.size
             tot_t += best
         cpu = {"value": round(tot_in / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d MiB of each of the 8 (profile, direction) inputs, best of 2, "
-                         "single thread" % args.cpu_sample_mib}
+               "sample": "first %d MiB of each of the %d (profile, direction) inputs, cut at a character "
+                             "boundary; best of 2; single thread" % (args.cpu_sample_mib, len(cases))}
 
     out = {
         "metric": "validated transcode input GB/s (% HBM peak); batched p50/p99 latency at load",
@@ -197,9 +224,12 @@ def main():
                                "UTF-8->UTF-16LE and UTF-16LE->UTF-8 with validation" % args.size_mib,
                    "buffers": len(cases), "bytes_per_buffer": nbytes, "rotate": args.rotate,
                    "tuning": {"utf8->utf16le": list(ctx.get_tuning(0)), "utf16le->utf8": list(ctx.get_tuning(1))}},
-        "roofline": {"bound": "hbm", "kernel": kernel, "case": "%s %s" % (dc["profile"], dc["dir"]),
+        "roofline": {"bound": "hbm", "kernel": kernel, "case": case_name,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes": dc["in_bytes"] + dc["out_bytes"], "ms_avg": dc["ms_avg"],
+                     "traffic": traffic},
+        "device_copy_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
         "per_case": per_case,
     }
