@@ -43,8 +43,8 @@ def main():
     ap.add_argument("--cpu-sample-mib", type=int, default=256, help="oracle sample per case (MiB)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profiles", default="ascii,latin,cjk,emoji")
-    ap.add_argument("--tile", type=int, default=0, help="override tile bytes (4096 or 8192)")
-    ap.add_argument("--seg", type=int, default=0, help="override tiles per segment")
+    ap.add_argument("--u8", default="", help="UTF-8 -> UTF-16 launch: tile_bytes,tiles_per_segment")
+    ap.add_argument("--u16", default="", help="UTF-16 -> UTF-8 launch: tile_bytes,tiles_per_segment")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -62,10 +62,10 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = utfx.Context()
-    if args.tile or args.seg:
-        for op in range(6):
-            t, sg, _ = ctx.get_tuning(op)
-            ctx.set_tuning(op, args.tile or t, args.seg or sg)
+    for op, spec in ((utfx.OP_UTF8_TO_UTF16, args.u8), (utfx.OP_UTF16_TO_UTF8, args.u16)):
+        if spec:
+            t, sg = (int(v) for v in spec.split(","))
+            ctx.set_tuning(op, t, sg)
     nbytes = args.size_mib * MIB
     profiles = args.profiles.split(",")
     cases = []  # (profile, direction, host_input, [device copies], device_output, in_bytes, out_bytes)

@@ -13,6 +13,7 @@
 
 #include "utfx.h"
 #include "utfx_kernels.hpp"
+#include "utfx_transcode.hpp"
 #include "utfx_batch.hpp"
 
 using namespace utfx_dev;
@@ -124,8 +125,9 @@ utfx_status prep(utfx_ctx* c, int op, const void* in, uint64_t n, uint32_t unit,
   L.n = n;
   wg = c->tile_bytes[op] / 16;
   L.seg = c->seg_tiles[op];
-  L.pad_ = 0;
+  L.wg = wg;
   const uint64_t per_seg = static_cast<uint64_t>(wg) * (16 / unit) * L.seg;
+  L.seg_units = per_seg;
   L.ntiles = (L.mis + n + extra + per_seg - 1) / per_seg;
   utfx_status s = ensure_tiles(c, L.ntiles);
   if (s != UTFX_OK) return s;
@@ -153,8 +155,40 @@ UTFX_DEFINE_LAUNCH(launch_len8, k_len8)
 UTFX_DEFINE_LAUNCH(launch_len16, k_len16)
 UTFX_DEFINE_LAUNCH(launch_val8, k_validate8)
 UTFX_DEFINE_LAUNCH(launch_val16, k_validate16)
-UTFX_DEFINE_LAUNCH(launch_u8u16, k_u8_to_u16)
-UTFX_DEFINE_LAUNCH(launch_u16u8, k_u16_to_u8)
+
+// Transcode kernels are instantiated per (workgroup size, tiles per segment); the
+// pairs allowed for each direction keep the LDS stage of a whole segment within 64 KiB.
+hipError_t launch_u8u16(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {
+  const dim3 g((uint32_t)grid);
+  if (wg == 256) {
+    if (L.seg == 2) hipLaunchKernelGGL((k_u8_to_u16<256, 2>), g, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((k_u8_to_u16<256, 4>), g, dim3(256), 0, s, L);
+  } else {
+    hipLaunchKernelGGL((k_u8_to_u16<512, 2>), g, dim3(512), 0, s, L);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_u16u8(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {
+  const dim3 g((uint32_t)grid);
+  if (wg == 256) {
+    if (L.seg == 2) hipLaunchKernelGGL((k_u16_to_u8<256, 2>), g, dim3(256), 0, s, L);
+    else if (L.seg == 4) hipLaunchKernelGGL((k_u16_to_u8<256, 4>), g, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((k_u16_to_u8<256, 8>), g, dim3(256), 0, s, L);
+  } else {
+    if (L.seg == 2) hipLaunchKernelGGL((k_u16_to_u8<512, 2>), g, dim3(512), 0, s, L);
+    else hipLaunchKernelGGL((k_u16_to_u8<512, 4>), g, dim3(512), 0, s, L);
+  }
+  return hipGetLastError();
+}
+
+// (tile bytes, tiles per segment) pairs with a transcode kernel instance
+bool transcode_config_ok(int op, uint32_t tile_bytes, uint32_t seg) {
+  if (op == UTFX_OP_UTF8_TO_UTF16) return (tile_bytes == 4096 && (seg == 2 || seg == 4)) || (tile_bytes == 8192 && seg == 2);
+  if (op == UTFX_OP_UTF16_TO_UTF8)
+    return (tile_bytes == 4096 && (seg == 2 || seg == 4 || seg == 8)) || (tile_bytes == 8192 && (seg == 2 || seg == 4));
+  return true;
+}
 UTFX_DEFINE_LAUNCH(launch_fin_u8u16, k_fin_u8u16)
 UTFX_DEFINE_LAUNCH(launch_fin_u16u8, k_fin_u16u8)
 
@@ -308,6 +342,10 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
     c->seg_tiles[i] = 8;
     c->wgs_per_cu[i] = 4;
   }
+  c->tile_bytes[UTFX_OP_UTF8_TO_UTF16] = 4096;
+  c->seg_tiles[UTFX_OP_UTF8_TO_UTF16] = 4;
+  c->tile_bytes[UTFX_OP_UTF16_TO_UTF8] = 4096;
+  c->seg_tiles[UTFX_OP_UTF16_TO_UTF8] = 8;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
     int cus = 0;
@@ -349,7 +387,8 @@ utfx_status utfx_set_stream(utfx_ctx* c, void* hip_stream) {
 utfx_status utfx_set_tuning(utfx_ctx* c, int op, uint32_t tile_bytes, uint32_t tiles_per_segment,
                             uint32_t wgs_per_cu) {
   if (!c || op < 0 || op >= UTFX_OP_COUNT_ || !valid_tile(tile_bytes) || tiles_per_segment < 1 ||
-      tiles_per_segment > 256 || wgs_per_cu < 1 || wgs_per_cu > 16)
+      tiles_per_segment > 256 || wgs_per_cu < 1 || wgs_per_cu > 16 ||
+      !transcode_config_ok(op, tile_bytes, tiles_per_segment))
     return UTFX_E_INVALID_ARG;
   c->tile_bytes[op] = tile_bytes;
   c->seg_tiles[op] = tiles_per_segment;

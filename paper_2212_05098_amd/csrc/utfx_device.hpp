@@ -51,8 +51,9 @@ struct Launch {
   unsigned long long* status;
   void* result;         // utfx_result* (device)
   uint64_t ntiles;      // workgroups = segments
+  uint64_t seg_units;   // input units per segment
   uint32_t seg;         // tiles (one 16-byte chunk per thread) per segment
-  uint32_t pad_;
+  uint32_t wg;          // threads per workgroup of the main kernel
 };
 
 // Result record layout (matches utfx_result in utfx.h).

@@ -1,4 +1,6 @@
-// utfx_kernels.hpp -- gfx950 kernels for validating UTF-8 <-> UTF-16LE transcoding.
+// utfx_kernels.hpp -- gfx950 building blocks and the length / validate kernels for
+// validating UTF-8 <-> UTF-16LE transcoding (the transcode kernels that use these
+// blocks are in utfx_transcode.hpp).
 //
 // One kernel family per operation: output-length query (reduction), validate
 // (first-error minimum) and transcode (one look-back per segment + LDS-staged
@@ -279,16 +281,6 @@ __device__ __forceinline__ uint32_t len8_count(const uint32_t x[4], bool full, c
   return cnt;
 }
 
-// Emit offsets of one byte (bit o set: the byte's character emits a word at the
-// byte's position + o): ASCII 0; 2-byte lead 1; 3-byte lead 2; 4-byte lead 2 and 3.
-__device__ __forceinline__ uint32_t emit_offsets(uint32_t b) {
-  if (b < 0x80) return 1u;
-  if (b < 0xC0) return 0u;
-  if (b < 0xE0) return 2u;
-  if (b < 0xF0) return 4u;
-  return 12u;
-}
-
 // ================================================================ UTF-8 error location
 
 // Kind of the first rule broken by the character starting at in[i] (i < n): the
@@ -507,42 +499,6 @@ __device__ __forceinline__ uint32_t cur_epoch(WsHeader* ws) {
   return __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Coalesced store of a tile's staged output.  Stage element PAD + l (0 <= l < total)
-// goes to out[base + l].  Output is written in 16-byte chunks aligned to the
-// destination; a chunk's bytes are gathered from the stage with dword reads and a
-// byte funnel shift.  Elements at or beyond cap are never stored.
-template <int WG, typename U, uint32_t PAD>
-__device__ __forceinline__ void store_stage(const U* stage, uint32_t total, U* out, uint64_t base, uint64_t cap) {
-  constexpr uint32_t PER = 16 / sizeof(U);
-  static_assert(PAD >= PER && PAD % PER == 0, "stage padding");
-  const uint32_t d = (uint32_t)((((uintptr_t)out / sizeof(U)) + base) & (PER - 1));
-  const uint32_t nch = (d + total + PER - 1) / PER;
-  const int64_t g_first = (int64_t)base - (int64_t)d;
-  const uint32_t* s32 = reinterpret_cast<const uint32_t*>(stage);
-  for (uint32_t k = threadIdx.x; k < nch; k += WG) {
-    const int64_t g0 = g_first + (int64_t)(k * PER);
-    const uint32_t l0 = k * PER;  // chunk covers stage elements PAD + l0 - d .. + PER
-    if (l0 >= d && l0 + PER <= d + total && g0 + (int64_t)PER <= (int64_t)cap) {
-      const uint32_t b0 = (PAD + l0 - d) * sizeof(U);
-      const uint32_t w0 = b0 >> 2, sh = b0 & 3;
-      uint32_t v0 = s32[w0], v1 = s32[w0 + 1], v2 = s32[w0 + 2], v3 = s32[w0 + 3], v4 = s32[w0 + 4];
-      uint4 o;
-      o.x = abyte(v1, v0, sh);
-      o.y = abyte(v2, v1, sh);
-      o.z = abyte(v3, v2, sh);
-      o.w = abyte(v4, v3, sh);
-      *reinterpret_cast<uint4*>(out + g0) = o;
-    } else {
-#pragma unroll
-      for (uint32_t i = 0; i < PER; ++i) {
-        const uint32_t l = l0 + i;  // element index relative to d
-        const int64_t g = g0 + (int64_t)i;
-        if (l >= d && l < d + total && g >= 0 && g < (int64_t)cap) out[g] = stage[PAD + l - d];
-      }
-    }
-  }
-}
-
 // Loads chunk q0 of a UTF-8 input with its halo and range masks.
 template <int WG>
 __device__ __forceinline__ bool chunk8(const Launch& L, uint64_t q0, const uint32_t x[4], Chunk8& c,
@@ -694,369 +650,6 @@ __global__ void k_fin_validate16(Launch L) {
     if (ld_fault(L.ws)) write_result(L.result, ST_DEVICE, 0, 0);
     else if (err != NO_ERR) write_result(L.result, ST_SURROGATE, err, err);
     else write_result(L.result, ST_OK, L.n, L.n);
-    reset_ws(L.ws);
-  }
-}
-
-// ================================================================ UTF-8 -> UTF-16LE
-
-// Words a UTF-8 segment emits (positions [a, m) with m = min(segment end, n)), from
-// the per-byte counts of the segment plus the boundary bytes: characters whose words
-// fall across the segment's start or end (thread 0 only).
-__device__ __forceinline__ int64_t seg_boundary8(const Launch& L, int64_t a, int64_t m) {
-  const uint8_t* in = L.base + L.mis;
-  int64_t corr = 0;
-  const int64_t a0 = a > 0 ? a : 0;
-  // bytes just before the segment whose words land inside it
-  for (int64_t j = a0 - 3; j < a0; ++j) {
-    if (j < 0) continue;
-    const uint32_t off = emit_offsets(in[j]);
-    for (int o = 0; o < 4; ++o)
-      if ((off >> o) & 1) corr += (j + o >= a0 && j + o < m) ? 1 : 0;
-  }
-  // bytes at the end of the segment whose words land beyond it
-  for (int64_t j = m - 3; j < m; ++j) {
-    if (j < a0) continue;
-    const uint32_t off = emit_offsets(in[j]);
-    for (int o = 0; o < 4; ++o)
-      if ((off >> o) & 1) corr -= (j + o >= m) ? 1 : 0;
-  }
-  return corr;
-}
-
-template <int WG>
-__global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
-  constexpr uint32_t T = 16u * WG;
-  constexpr uint32_t PAD = 8;
-  constexpr uint32_t SSZ = PAD + T + 16;  // stage words per buffer
-  __shared__ unsigned long long lds[WG / 64 + 2];
-  __shared__ uint32_t scan_scratch[WG / 64];
-  __shared__ __attribute__((aligned(16))) uint16_t stage[2 * SSZ];
-  const uint64_t seg = blockIdx.x;
-  const uint32_t epoch = cur_epoch(L.ws);
-  const uint64_t SEGB = (uint64_t)L.seg * T;
-  const uint64_t q00 = seg * SEGB + 16ull * threadIdx.x;
-  const uint64_t lo = L.mis, hi = L.mis + L.n;
-  uint32_t x[4], xn[4];
-  uint64_t seg_total = 0;  // meaningful in thread 0
-
-  // pass 1: words this segment emits
-  {
-    uint32_t m[4];
-    load8(L, q00, x);
-    uint32_t acc = 0;
-    for (uint32_t s = 0; s < L.seg; ++s) {
-      const uint64_t q0 = q00 + s * T;
-      if (s + 1 < L.seg) load8(L, q0 + T, xn);
-      const bool full = q0 >= lo && q0 + 16 <= hi;
-      if (!full) range_masks(q0, lo, hi, m);
-      acc += len8_count(x, full, m);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = xn[k];
-    }
-    const uint64_t sum = block_sum_u64<WG>(acc, lds);
-    if (threadIdx.x == 0) {
-      const int64_t a = (int64_t)(seg * SEGB) - (int64_t)L.mis;
-      int64_t mend = a + (int64_t)SEGB;
-      if (mend > (int64_t)L.n) mend = (int64_t)L.n;
-      seg_total = (uint64_t)((int64_t)sum + seg_boundary8(L, a, mend));
-      publish_aggregate(L.status, seg, seg_total, epoch);
-    }
-  }
-
-  // pass 2: transcode tile by tile (the segment is re-read from cache)
-  uint64_t running = 0;
-  uint32_t buf = 0;
-  load8(L, q00, x);
-  for (uint32_t s = 0; s < L.seg; ++s) {
-    const uint64_t q0 = q00 + s * T;
-    if (s + 1 < L.seg) load8(L, q0 + T, xn);
-    Chunk8 c;
-    uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
-    const bool full = chunk8<WG>(L, q0, x, c, inE, inD);
-    const int cls = classify8(c);
-    process8_any<true>(cls, full, c, inE, inD, E, cnt, det, W);
-    uint32_t total;
-    const uint32_t local = block_excl_scan<WG>(cnt, total, scan_scratch);
-
-    // Scatter: position e writes at the running index of emitted words.  In a chunk
-    // wholly inside the input, a non-emitting position writes a placeholder at the
-    // slot of the next emit, which that emit then overwrites: inside a valid prefix
-    // at most two positions in a row do not emit, so only the last two positions of
-    // a chunk can lack a later emit in the chunk, and those write only real words.
-    // Past the first error every slot is at or beyond `written`.  Chunks that
-    // straddle the start or end of the input write real words only.
-    uint16_t* st = stage + buf * SSZ;
-    uint32_t idx = PAD + local;
-    if (full) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int e = 4 * k + i;
-          const uint32_t pair = W[2 * k + (i >> 1)];
-          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
-          const uint32_t bit = (E[k] >> (8 * i + 7)) & 1u;
-          if (e < 14 || bit) st[idx] = word;
-          idx += bit;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t pair = W[2 * k + (i >> 1)];
-          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
-          const uint32_t bit = (E[k] >> (8 * i + 7)) & 1u;
-          if (bit) st[idx] = word;
-          idx += bit;
-        }
-      }
-    }
-    if (s == 0) {
-      // the look-back runs after the first tile's work, when predecessors are likely done
-      if (threadIdx.x < 64) {
-        const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
-        if (threadIdx.x == 0) lds[WG / 64] = b;
-      }
-    }
-    __syncthreads();
-    if (s == 0) running = lds[WG / 64];
-    store_stage<WG, uint16_t, PAD>(st, total, reinterpret_cast<uint16_t*>(L.out), running, L.cap);
-    running += total;
-    if (det) {
-      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
-      const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
-      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
-    }
-    buf ^= 1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = xn[k];
-  }
-}
-
-// Words emitted before logical position `off` (the output length of the valid prefix
-// when off is the first error): the segment's exclusive prefix plus the words emitted
-// inside the segment before off.
-template <int WG>
-__device__ uint64_t prefix_words8(const Launch& L, uint64_t off, unsigned long long* lds) {
-  constexpr uint64_t T = 16ull * WG;
-  const uint64_t SEGB = (uint64_t)L.seg * T;
-  const uint64_t qoff = off + L.mis;
-  const uint64_t seg = qoff / SEGB;
-  uint32_t acc = 0;
-  uint32_t x[4];
-  for (uint64_t q0b = seg * SEGB; q0b < qoff + 1; q0b += T) {
-    const uint64_t q0 = q0b + 16ull * threadIdx.x;
-    load8(L, q0, x);
-    Chunk8 c;
-    uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
-    chunk8<WG>(L, q0, x, c, inE, inD);
-    range_masks(q0, L.mis, qoff, inE);  // positions before off (and inside the input)
-    range_masks(q0, L.mis, L.mis + L.n + 1, inD);
-    const int cls = classify8(c);
-    process8_any<false>(cls, false, c, inE, inD, E, cnt, det, W);
-    acc += cnt;
-  }
-  const uint64_t s = block_sum_u64<WG>(acc, lds);
-  const uint64_t before = seg ? tile_inclusive(L.status, seg - 1) : 0;
-  return before + s;
-}
-
-// Result of a UTF-8 -> UTF-16LE launch: error kind and the words of the valid prefix,
-// or the total (checked against cap).
-template <int WG>
-__global__ void __launch_bounds__(WG) k_fin_u8u16(Launch L) {
-  __shared__ unsigned long long lds[WG / 64 + 2];
-  const uint64_t err = ld_agent(&L.ws->err);
-  const bool fault = ld_fault(L.ws) != 0;
-  uint64_t written = 0;
-  if (!fault && err != NO_ERR) written = prefix_words8<WG>(L, err, lds);
-  if (threadIdx.x == 0) {
-    const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
-    if (fault) write_result(L.result, ST_DEVICE, 0, 0);
-    else if (err != NO_ERR) write_result(L.result, utf8_kind_at(L.base + L.mis, L.n, err), err, written);
-    else if (tot > L.cap) write_result(L.result, ST_OUTPUT_TOO_SMALL, tot, 0);
-    else write_result(L.result, ST_OK, tot, tot);
-    reset_ws(L.ws);
-  }
-}
-
-// ================================================================ UTF-16LE -> UTF-8
-
-template <int WG>
-__global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
-  constexpr uint32_t TW = 8u * WG;  // words per tile
-  constexpr uint32_t PAD = 16;
-  constexpr uint32_t SSZ = PAD + 3 * TW + 32;  // stage bytes per buffer
-  __shared__ unsigned long long lds[WG / 64 + 2];
-  __shared__ uint32_t scan_scratch[WG / 64];
-  __shared__ __attribute__((aligned(16))) uint8_t stage[2 * SSZ];
-  const uint64_t seg = blockIdx.x;
-  const uint32_t epoch = cur_epoch(L.ws);
-  const uint64_t SEGW = (uint64_t)L.seg * TW;
-  const uint64_t q00 = seg * SEGW + 8ull * threadIdx.x;
-  const uint64_t lo = L.mis, hi = L.mis + L.n;
-  uint32_t x[4], xn[4];
-  uint64_t seg_total = 0;  // meaningful in thread 0
-
-  // pass 1: bytes this segment emits (each word's bytes belong to its own position)
-  {
-    load16(L, q00, x);
-    uint32_t acc = 0;
-    for (uint32_t s = 0; s < L.seg; ++s) {
-      const uint64_t q0 = q00 + s * TW;
-      if (s + 1 < L.seg) load16(L, q0 + TW, xn);
-      if (q0 >= lo && q0 + 8 <= hi && !any_surrogate(x, 0u)) {
-        const uint32_t l = pk_len16(x[0]) + pk_len16(x[1]) + pk_len16(x[2]) + pk_len16(x[3]);
-        acc += (l & 0xFFFFu) + (l >> 16);
-      } else if (q0 >= lo && q0 + 8 <= hi) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc += len16((x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-          acc += (q0 + j >= lo && q0 + j < hi) ? len16(w) : 0u;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = xn[k];
-    }
-    const uint64_t sum = block_sum_u64<WG>(acc, lds);
-    if (threadIdx.x == 0) {
-      seg_total = sum;
-      publish_aggregate(L.status, seg, seg_total, epoch);
-    }
-  }
-
-  // pass 2: transcode tile by tile
-  uint64_t running = 0;
-  uint32_t buf = 0;
-  load16(L, q00, x);
-  for (uint32_t s = 0; s < L.seg; ++s) {
-    const uint64_t q0 = q00 + s * TW;
-    if (s + 1 < L.seg) load16(L, q0 + TW, xn);
-    uint32_t wp = __shfl_up(x[3] >> 16, 1, 64);
-    if ((threadIdx.x & 63) == 0) wp = load16_prev(L, q0);
-    uint32_t len[8], cnt;
-    bool det = false;
-    const bool full = q0 >= lo && q0 + 8 <= hi;
-    // wave-uniform choice: no surrogate anywhere in the wave's chunks (nor before them)
-    const bool simple = !__any(!full || any_surrogate(x, wp));
-    uint32_t L4[4];
-    if (simple) {
-      cnt = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        L4[k] = pk_len16(x[k]);
-        cnt += (L4[k] & 0xFFFFu) + (L4[k] >> 16);
-      }
-    } else if (full) {
-      analyze16<true>(x, wp, q0, lo, hi, len, cnt, det);
-    } else {
-      analyze16<false>(x, wp, q0, lo, hi, len, cnt, det);
-    }
-    uint32_t total;
-    const uint32_t local = block_excl_scan<WG>(cnt, total, scan_scratch);
-
-    // Scatter: in a chunk wholly inside the input every word writes three bytes at
-    // the running offset, and the unused ones are overwritten by the following words
-    // (each later word adds at least one byte); the last two words of the chunk write
-    // only their own bytes.  Chunks that straddle the start or end of the input
-    // write only real bytes.
-    uint8_t* st = stage + buf * SSZ;
-    uint32_t o = PAD + local;
-    if (simple) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t cl = L4[k] & 0xFFFFu, ch = L4[k] >> 16;
-        uint32_t vl, vh;
-        pk_enc16(x[k], cl, ch, vl, vh);
-        const bool last = (k == 3);  // words 6 and 7 write only their own bytes
-        st[o] = (uint8_t)vl;
-        if (!last || cl >= 2) st[o + 1] = (uint8_t)(vl >> 8);
-        if (!last || cl >= 3) st[o + 2] = (uint8_t)(vl >> 16);
-        o += cl;
-        st[o] = (uint8_t)vh;
-        if (!last || ch >= 2) st[o + 1] = (uint8_t)(vh >> 8);
-        if (!last || ch >= 3) st[o + 2] = (uint8_t)(vh >> 16);
-        o += ch;
-      }
-    } else {
-      uint32_t prev = wp;
-      const bool wave_sur = __any(any_surrogate(x, wp));
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-        const uint32_t cj = len[j];
-        const uint32_t v = wave_sur ? enc16<true>(w, prev, cj) : enc16<false>(w, prev, cj);
-        const bool spare = full && j < 6;
-        if (spare || cj >= 1) st[o] = (uint8_t)v;
-        if (spare || cj >= 2) st[o + 1] = (uint8_t)(v >> 8);
-        if (spare || cj >= 3) st[o + 2] = (uint8_t)(v >> 16);
-        o += cj;
-        prev = w;
-      }
-    }
-    if (s == 0) {
-      if (threadIdx.x < 64) {
-        const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
-        if (threadIdx.x == 0) lds[WG / 64] = b;
-      }
-    }
-    __syncthreads();
-    if (s == 0) running = lds[WG / 64];
-    store_stage<WG, uint8_t, PAD>(st, total, reinterpret_cast<uint8_t*>(L.out), running, L.cap);
-    running += total;
-    if (det) {
-      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
-      const uint16_t* in = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
-      const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
-      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
-    }
-    buf ^= 1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = xn[k];
-  }
-}
-
-template <int WG>
-__device__ uint64_t prefix_bytes16(const Launch& L, uint64_t off, unsigned long long* lds) {
-  constexpr uint64_t TW = 8ull * WG;
-  const uint64_t SEGW = (uint64_t)L.seg * TW;
-  const uint64_t qoff = off + L.mis;
-  const uint64_t seg = qoff / SEGW;
-  uint32_t acc = 0;
-  uint32_t x[4];
-  for (uint64_t q0b = seg * SEGW; q0b < qoff + 1; q0b += TW) {
-    const uint64_t q0 = q0b + 8ull * threadIdx.x;
-    load16(L, q0, x);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-      acc += (q0 + j >= L.mis && q0 + j < qoff) ? len16(w) : 0u;
-    }
-  }
-  const uint64_t s = block_sum_u64<WG>(acc, lds);
-  const uint64_t before = seg ? tile_inclusive(L.status, seg - 1) : 0;
-  return before + s;
-}
-
-template <int WG>
-__global__ void __launch_bounds__(WG) k_fin_u16u8(Launch L) {
-  __shared__ unsigned long long lds[WG / 64 + 2];
-  const uint64_t err = ld_agent(&L.ws->err);
-  const bool fault = ld_fault(L.ws) != 0;
-  uint64_t written = 0;
-  if (!fault && err != NO_ERR) written = prefix_bytes16<WG>(L, err, lds);
-  if (threadIdx.x == 0) {
-    const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
-    if (fault) write_result(L.result, ST_DEVICE, 0, 0);
-    else if (err != NO_ERR) write_result(L.result, ST_SURROGATE, err, written);
-    else if (tot > L.cap) write_result(L.result, ST_OUTPUT_TOO_SMALL, tot, 0);
-    else write_result(L.result, ST_OK, tot, tot);
     reset_ws(L.ws);
   }
 }

@@ -1,0 +1,537 @@
+// utfx_transcode.hpp -- single-read validating transcode kernels for gfx950.
+//
+// A workgroup owns one segment of S tiles (a tile is one 16-byte chunk per thread) and
+// reads it from HBM exactly once, into registers:
+//   phase A  every chunk's output length by the per-unit length formula (the length
+//            query of section 7.5; for valid input it is exact, and each character's
+//            units are counted at its first unit), a packed wave scan per pair of
+//            tiles, and the segment's total published for the decoupled look-back;
+//   phase B  per chunk: classify, validate, decode / encode, and scatter the units
+//            into an LDS stage holding the whole segment's output.  Wave 0 runs the
+//            look-back first; the other waves do not wait for it;
+//   store    one barrier, then coalesced 16-byte stores of the stage at the
+//            segment's global offset.
+// The chunk offsets come from the length formula, where a character is counted at
+// its lead; UTF-8 -> UTF-16 emits a character's words at its last bytes (the end mask
+// of section 6.1), so a chunk's first emitted word lies below the formula offset by
+// the words of characters that start in the 3 bytes before it (its "spill").
+#pragma once
+#include "utfx_kernels.hpp"
+
+namespace utfx_dev {
+
+// DPP wave_shr:1 -- lane i gets lane i-1's v; lane 0 gets `first`.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t first) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x138, 0xF, 0xF, false);
+}
+
+// Coalesced store of staged output: stage element s0 + l (0 <= l < total) goes to
+// out[base + l].  16-byte chunks aligned to the destination are gathered from the
+// stage with dword reads and a byte funnel shift; elements at or beyond cap are never
+// stored.  The stage must hold 16 readable bytes past s0 + total.
+template <int WG, typename U>
+__device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t total, U* out, uint64_t base,
+                                           uint64_t cap) {
+  constexpr uint32_t PER = 16 / sizeof(U);
+  const uint32_t d = (uint32_t)((((uintptr_t)out / sizeof(U)) + base) & (PER - 1));
+  const uint32_t nch = (d + total + PER - 1) / PER;
+  const int64_t g_first = (int64_t)base - (int64_t)d;
+  const uint32_t* s32 = reinterpret_cast<const uint32_t*>(stage);
+  for (uint32_t k = threadIdx.x; k < nch; k += WG) {
+    const int64_t g0 = g_first + (int64_t)(k * PER);
+    const uint32_t l0 = k * PER;  // chunk covers elements l0 - d .. l0 - d + PER - 1
+    if (l0 >= d && l0 + PER <= d + total && g0 + (int64_t)PER <= (int64_t)cap) {
+      const uint32_t b0 = (s0 + l0 - d) * sizeof(U);
+      const uint32_t w0 = b0 >> 2, sh = b0 & 3;
+      const uint32_t v0 = s32[w0], v1 = s32[w0 + 1], v2 = s32[w0 + 2], v3 = s32[w0 + 3], v4 = s32[w0 + 4];
+      uint4 o;
+      o.x = abyte(v1, v0, sh);
+      o.y = abyte(v2, v1, sh);
+      o.z = abyte(v3, v2, sh);
+      o.w = abyte(v4, v3, sh);
+      *reinterpret_cast<uint4*>(out + g0) = o;
+    } else {
+#pragma unroll
+      for (uint32_t i = 0; i < PER; ++i) {
+        const int64_t l = (int64_t)(l0 + i) - (int64_t)d;
+        const int64_t g = g0 + (int64_t)i;
+        if (l >= 0 && l < (int64_t)total && g >= 0 && g < (int64_t)cap) out[g] = stage[s0 + (uint32_t)l];
+      }
+    }
+  }
+}
+
+// Chunk offsets of a segment from per-chunk counts c[S] (formula units): packed wave
+// scans of tile pairs, wave totals through LDS (one barrier), then per chunk the sum of
+// the earlier tiles' totals, the earlier waves' totals of its own tile and the
+// exclusive scan inside its wave.  Counts must be < 2^16 per tile.  Returns the
+// segment total; `wtot` holds NW x S/2 words.
+template <int WG, int S>
+__device__ __forceinline__ uint32_t segment_offsets(const uint32_t c[S], uint32_t off[S], uint32_t* wtot) {
+  constexpr int NW = WG / 64;
+  constexpr int P = S / 2;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t own[P], inc[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    own[j] = c[2 * j] | (c[2 * j + 1] << 16);
+    inc[j] = wave_incl_scan(own[j]);
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) wtot[wid * P + j] = inc[j];
+  }
+  __syncthreads();
+  uint32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uint32_t tot = 0, before = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t t = wtot[w * P + j];
+      tot += t;
+      before += (w < wid) ? t : 0u;
+    }
+    const uint32_t ex = before + inc[j] - own[j];  // lane-wise, no carries: each half < 2^16
+    off[2 * j] = run + (ex & 0xFFFFu);
+    run += tot & 0xFFFFu;
+    off[2 * j + 1] = run + (ex >> 16);
+    run += tot >> 16;
+  }
+  return run;
+}
+
+// ================================================================ UTF-8 -> UTF-16LE
+
+// Output words of a 16-byte chunk by the length formula: one per byte that is not a
+// continuation (10xxxxxx) and one more per byte >= F0 (section 6.2: the 4-byte
+// characters become surrogate pairs).  Positions whose mask byte is clear count 0.
+__device__ __forceinline__ uint32_t count8(const uint32_t x[4], const uint32_t* m) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t v = x[k];
+    const uint32_t s1 = v << 1;
+    uint32_t nc = (~v | s1) & HI;         // bit 7: not 10xxxxxx
+    const uint32_t u = v & s1;            // bit 7: 11xxxxxx, bit 5: xx11xxxx
+    uint32_t f = u & (u << 2) & HI;       // bit 7: 1111xxxx
+    if (m) {
+      nc &= m[k];
+      f &= m[k];
+    }
+    acc += __builtin_popcount(nc) + __builtin_popcount(f);
+  }
+  return acc;
+}
+
+// Words that characters starting in the 3 bytes before a chunk emit inside it: a
+// 2-byte lead one back emits at position 0; a lead >= E0 two back emits at 0 and one
+// back at 1; a lead >= F0 also emits its low surrogate three back -> 0, two back -> 1,
+// one back -> 2.  Cp is the class dword of those bytes (with the >= F0 bits).
+__device__ __forceinline__ uint32_t spill8(uint32_t Cp) {
+  const uint32_t e = ((Cp >> 24) << 1) | ((Cp >> 16) << 2) | ((Cp >> 8) << 3);
+  return __builtin_popcount(e & HI);
+}
+
+template <int WG, int S>
+__global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
+  constexpr int NW = WG / 64;
+  constexpr uint32_t T = 16u * WG;
+  constexpr uint32_t SEGB = T * S;
+  constexpr uint32_t PAD = 16;            // stage slots below the segment's formula offset
+  constexpr uint32_t LIM = PAD + SEGB;    // a valid chunk ends at or below this slot
+  constexpr uint32_t SSZ = LIM + 32;
+  __shared__ __attribute__((aligned(16))) uint16_t stage[SSZ];
+  __shared__ uint32_t wtot[NW * (S / 2)];
+  __shared__ uint32_t halo[S * NW];
+  __shared__ unsigned long long seg_base;
+  __shared__ uint32_t bounds[2];
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t seg = blockIdx.x;
+  const uint32_t epoch = cur_epoch(L.ws);
+  const uint64_t s0 = seg * SEGB;
+  const uint64_t q00 = s0 + 16ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const bool segfull = s0 >= lo && s0 + SEGB <= hi;
+
+  // ---- phase A: load the segment, count, scan
+  uint32_t x[S][4];
+  if (segfull) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint4 v = *reinterpret_cast<const uint4*>(L.base + q00 + (uint64_t)k * T);
+      x[k][0] = v.x; x[k][1] = v.y; x[k][2] = v.z; x[k][3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < S; ++k) load8(L, q00 + (uint64_t)k * T, x[k]);
+  }
+  const uint32_t xp_seg = (threadIdx.x == 0) ? load8_prev(L, s0) : 0u;
+  uint32_t c[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const uint64_t q0 = q00 + (uint64_t)k * T;
+    if (segfull || (q0 >= lo && q0 + 16 <= hi)) {
+      c[k] = count8(x[k], nullptr);
+    } else {
+      uint32_t m[4];
+      range_masks(q0, lo, hi, m);
+      c[k] = count8(x[k], m);
+    }
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) halo[k * NW + wid] = x[k][3];
+  }
+  uint32_t off[S];
+  const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);  // contains a barrier
+
+  if (wid == 0) {
+    if (lane == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    if (lane == 0) seg_base = b;
+  }
+
+  // ---- phase B: per chunk, validate + decode + scatter into the stage
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const uint64_t q0 = q00 + (uint64_t)k * T;
+    const uint32_t hl = (wid > 0) ? halo[k * NW + wid - 1] : (k > 0 ? halo[(k - 1) * NW + NW - 1] : xp_seg);
+    Chunk8 ch;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ch.x[i] = x[k][i];
+    ch.xp = wave_shr1(x[k][3], hl);
+    uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
+    const bool full = segfull || (q0 >= lo && q0 + 16 <= hi);
+    if (!full) {
+      range_masks(q0, lo, hi, inE);
+      range_masks(q0, lo, hi + 1, inD);
+    }
+    const int cls = classify8(ch);
+    process8_any<true>(cls, full, ch, inE, inD, E, cnt, det, W);
+    uint32_t idx = PAD + off[k] - spill8(ch.Cp);
+    if (k == 0 && threadIdx.x == 0) bounds[0] = idx;
+    // Scatter.  In a chunk wholly inside the input, a non-emitting position writes a
+    // placeholder at the slot of the next emit, which that emit overwrites: inside a
+    // valid prefix at most two positions in a row do not emit, so only the last two
+    // positions can lack a later emit in the chunk, and those write only real words.
+    // Past the first error every slot is at or beyond the valid prefix's length, and a
+    // chunk whose slots would leave the stage is past it and writes nothing.
+    if (idx + 16 <= LIM) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = 4 * kk + i;
+          const uint32_t pair = W[2 * kk + (i >> 1)];
+          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+          const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
+          if ((full && e < 14) || bit) stage[idx] = word;
+          idx += bit;
+        }
+      }
+    } else {
+      idx = LIM;
+    }
+    if (k == S - 1 && threadIdx.x == WG - 1) bounds[1] = idx;
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
+      const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
+      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+    }
+  }
+  __syncthreads();
+
+  // ---- store the segment's output
+  const uint32_t st0 = bounds[0];
+  uint32_t st1 = bounds[1];
+  st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
+  const int64_t g = (int64_t)seg_base + (int64_t)st0 - (int64_t)PAD;
+  store_span<WG, uint16_t>(stage, st0, st1 - st0, reinterpret_cast<uint16_t*>(L.out), (uint64_t)g, L.cap);
+}
+
+// Words of the valid prefix in[0:off]: the exclusive prefix of off's segment plus the
+// length formula over the segment's positions before off (exact there, because every
+// character before the first error is complete).
+template <int WG>
+__device__ uint64_t prefix_words8(const Launch& L, uint64_t off, uint64_t seg_units, unsigned long long* lds) {
+  constexpr uint64_t T = 16ull * WG;
+  const uint64_t qoff = off + L.mis;
+  const uint64_t seg = qoff / seg_units;
+  uint32_t acc = 0;
+  uint32_t x[4], m[4];
+  for (uint64_t q0b = seg * seg_units; q0b < qoff; q0b += T) {
+    const uint64_t q0 = q0b + 16ull * threadIdx.x;
+    load8(L, q0, x);
+    range_masks(q0, L.mis, qoff, m);
+    acc += count8(x, m);
+  }
+  const uint64_t s = block_sum_u64<WG>(acc, lds);
+  const uint64_t before = seg ? tile_inclusive(L.status, seg - 1) : 0;
+  return before + s;
+}
+
+// Result of a UTF-8 -> UTF-16LE launch: error kind and the words of the valid prefix,
+// or the total (checked against cap).
+template <int WG>
+__global__ void __launch_bounds__(WG) k_fin_u8u16(Launch L) {
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  const uint64_t err = ld_agent(&L.ws->err);
+  const bool fault = ld_fault(L.ws) != 0;
+  uint64_t written = 0;
+  if (!fault && err != NO_ERR) written = prefix_words8<WG>(L, err, L.seg_units, lds);
+  if (threadIdx.x == 0) {
+    const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
+    if (fault) write_result(L.result, ST_DEVICE, 0, 0);
+    else if (err != NO_ERR) write_result(L.result, utf8_kind_at(L.base + L.mis, L.n, err), err, written);
+    else if (tot > L.cap) write_result(L.result, ST_OUTPUT_TOO_SMALL, tot, 0);
+    else write_result(L.result, ST_OK, tot, tot);
+    reset_ws(L.ws);
+  }
+}
+
+// ================================================================ UTF-16LE -> UTF-8
+
+typedef short ss2 __attribute__((ext_vector_type(2)));
+
+// Output bytes of the two words of X (16-bit lanes): 1 below U+0080, 2 below U+0800,
+// 2 for each half of a surrogate pair, else 3 (section 7.3).
+__device__ __forceinline__ uint32_t pk_len16s(uint32_t X) {
+  const us2 w = as_us2(X);
+  const us2 one = (us2)(1);
+  const us2 a = __builtin_elementwise_min(w >> (us2)(7), one);
+  const us2 b = __builtin_elementwise_min(w >> (us2)(11), one);
+  const us2 ns = __builtin_elementwise_min(as_us2((X & 0xF800F800u) ^ 0xD800D800u), one);  // not a surrogate
+  return as_u32(a + b + ns);
+}
+
+// Lane-wise unpaired-surrogate detection for the words of X, with P holding each
+// word's predecessor: a word is flagged when "is a low surrogate" differs from "the
+// word before is a high surrogate" (sections 2.1 and 7.4).
+__device__ __forceinline__ uint32_t pk_pair_err(uint32_t X, uint32_t P) {
+  const us2 one = (us2)(1);
+  const us2 a = __builtin_elementwise_min(as_us2((X & 0xFC00FC00u) ^ 0xDC00DC00u), one);  // 0: low surrogate
+  const us2 b = __builtin_elementwise_min(as_us2((P & 0xFC00FC00u) ^ 0xD800D800u), one);  // 0: after a high
+  return as_u32(a ^ b);
+}
+
+// UTF-8 bytes of the two words of X with surrogates (little-endian in a dword each),
+// P = each word's predecessor, c_lo / c_hi = their lengths.  Figure 1(a) forms: the
+// 3-byte form [E0|w>>12, 80|(w>>6 & 3F), 80|(w & 3F)]; the 2-byte form [C0|w>>6,
+// 80|(w & 3F)].  A high surrogate emits the first two bytes of its 4-byte character,
+// which depend on it alone: with u = w - 0xD7C0 (the code point >> 10, section 7.2)
+// they are [F0|u>>8, 80|(u>>2 & 3F)], i.e. the 2-byte form of u>>2 with the tag
+// raised from C0 to F0.  A low surrogate emits the last two, [80|(h & 3)<<4|(w>>6 &
+// F), 80|(w & 3F)] with h its high surrogate: the 2-byte form's bytes with the tag
+// bits 5..4 replaced by h's bits 1..0.
+__device__ __forceinline__ void pk_enc16s(uint32_t X, uint32_t P, uint32_t c_lo, uint32_t c_hi, uint32_t& v_lo,
+                                          uint32_t& v_hi) {
+  const us2 w = as_us2(X);
+  const us2 one = (us2)(1);
+  const uint32_t ns = as_u32(__builtin_elementwise_min(as_us2((X & 0xF800F800u) ^ 0xD800D800u), one));
+  const uint32_t mS = as_u32(as_us2(ns) - one);                     // 0xFFFF: surrogate
+  const uint32_t b10 = as_u32(__builtin_bit_cast(us2, __builtin_bit_cast(ss2, X << 5) >> (ss2)(15)));
+  const uint32_t mH = mS & ~b10, mL = mS & b10;                     // high / low surrogate lanes
+  const uint32_t D = as_u32((w - (us2)(0xD7C0)) >> (us2)(2));
+  const uint32_t Wp = (mH & D) | (~mH & X);
+  const uint32_t p0 = as_u32(w >> (us2)(12)) | 0x00E000E0u;
+  const uint32_t p1 = (as_u32(as_us2(Wp) >> (us2)(6)) & 0x003F003Fu) | 0x00800080u;
+  const uint32_t p2 = (Wp & 0x003F003Fu) | 0x00800080u;
+  const uint32_t tag = (mL & ~(P << 4) & 0x00300030u) | (~mL & 0x00400040u) | (mH & 0x00300030u);
+  const uint32_t l2 = p1 ^ tag;
+  const uint32_t q12 = p1 | (p2 << 8);
+  const uint32_t q2 = l2 | (p2 << 8);
+  const uint32_t t3l = perm(q12, p0, 0x0C050400u), t3h = perm(q12, p0, 0x0C070602u);
+  const uint32_t t2l = perm(q2, 0u, 0x0C0C0504u), t2h = perm(q2, 0u, 0x0C0C0706u);
+  v_lo = c_lo == 3 ? t3l : (c_lo == 2 ? t2l : (X & 0xFFFFu));
+  v_hi = c_hi == 3 ? t3h : (c_hi == 2 ? t2h : (X >> 16));
+}
+
+// Output bytes of a chunk of 8 words (positions outside [lo, hi) count 0).
+__device__ __forceinline__ uint32_t count16(const uint32_t x[4], uint64_t q0, uint64_t lo, uint64_t hi, bool full) {
+  if (full) {
+    const uint32_t l = pk_len16s(x[0]) + pk_len16s(x[1]) + pk_len16s(x[2]) + pk_len16s(x[3]);
+    return (l & 0xFFFFu) + (l >> 16);
+  }
+  uint32_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+    acc += (q0 + j >= lo && q0 + j < hi) ? len16(w) : 0u;
+  }
+  return acc;
+}
+
+template <int WG, int S>
+__global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
+  constexpr int NW = WG / 64;
+  constexpr uint32_t TW = 8u * WG;      // words per tile
+  constexpr uint32_t SEGW = TW * S;
+  constexpr uint32_t PAD = 16;
+  constexpr uint32_t SSZ = PAD + 3 * SEGW + 48;
+  __shared__ __attribute__((aligned(16))) uint8_t stage[SSZ];
+  __shared__ uint32_t wtot[NW * (S / 2)];
+  __shared__ uint32_t halo[S * NW];
+  __shared__ unsigned long long seg_base;
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t seg = blockIdx.x;
+  const uint32_t epoch = cur_epoch(L.ws);
+  const uint64_t s0 = seg * SEGW;
+  const uint64_t q00 = s0 + 8ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const bool segfull = s0 >= lo && s0 + SEGW <= hi;
+  const uint16_t* in16 = reinterpret_cast<const uint16_t*>(L.base);
+
+  // ---- phase A
+  uint32_t x[S][4];
+  if (segfull) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint4 v = *reinterpret_cast<const uint4*>(in16 + q00 + (uint64_t)k * TW);
+      x[k][0] = v.x; x[k][1] = v.y; x[k][2] = v.z; x[k][3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < S; ++k) load16(L, q00 + (uint64_t)k * TW, x[k]);
+  }
+  // the word before the segment, in the high half (the layout of a chunk's last dword)
+  const uint32_t xp_seg = (threadIdx.x == 0) ? (load16_prev(L, s0) << 16) : 0u;
+  uint32_t c[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const uint64_t q0 = q00 + (uint64_t)k * TW;
+    c[k] = count16(x[k], q0, lo, hi, segfull || (q0 >= lo && q0 + 8 <= hi));
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) halo[k * NW + wid] = x[k][3];
+  }
+  uint32_t off[S];
+  const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);
+
+  if (wid == 0) {
+    if (lane == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    if (lane == 0) seg_base = b;
+  }
+
+  // ---- phase B
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const uint64_t q0 = q00 + (uint64_t)k * TW;
+    const uint32_t hl = (wid > 0) ? halo[k * NW + wid - 1] : (k > 0 ? halo[(k - 1) * NW + NW - 1] : xp_seg);
+    const uint32_t xprev = wave_shr1(x[k][3], hl);  // high half: the word before the chunk
+    const uint32_t wp = xprev >> 16;
+    const bool full = segfull || (q0 >= lo && q0 + 8 <= hi);
+    uint8_t* st = stage + PAD + off[k];
+    bool det = false;
+    if (!__any(!full || any_surrogate(x[k], wp))) {
+      // no surrogate anywhere in the wave's chunks: lengths 1..3, nothing to validate.
+      // Each word writes three bytes at its offset; the spare ones are overwritten by
+      // the following words (each adds at least one byte), except for the last two
+      // words of the chunk, which write only their own bytes.
+      uint32_t o = 0;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t l = pk_len16(x[k][kk]);
+        const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
+        uint32_t vl, vh;
+        pk_enc16(x[k][kk], cl, chh, vl, vh);
+        const bool last = (kk == 3);
+        st[o] = (uint8_t)vl;
+        if (!last || cl >= 2) st[o + 1] = (uint8_t)(vl >> 8);
+        if (!last || cl >= 3) st[o + 2] = (uint8_t)(vl >> 16);
+        o += cl;
+        st[o] = (uint8_t)vh;
+        if (!last || chh >= 2) st[o + 1] = (uint8_t)(vh >> 8);
+        if (!last || chh >= 3) st[o + 2] = (uint8_t)(vh >> 16);
+        o += chh;
+      }
+    } else if (full) {
+      uint32_t o = 0, d = 0, prevd = xprev;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t X = x[k][kk];
+        const uint32_t P = abyte(X, prevd, 2);  // each word's predecessor
+        d |= pk_pair_err(X, P);
+        const uint32_t l = pk_len16s(X);
+        const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
+        uint32_t vl, vh;
+        pk_enc16s(X, P, cl, chh, vl, vh);
+        const bool last = (kk == 3);
+        st[o] = (uint8_t)vl;
+        if (!last || cl >= 2) st[o + 1] = (uint8_t)(vl >> 8);
+        if (!last || cl >= 3) st[o + 2] = (uint8_t)(vl >> 16);
+        o += cl;
+        st[o] = (uint8_t)vh;
+        if (!last || chh >= 2) st[o + 1] = (uint8_t)(vh >> 8);
+        if (!last || chh >= 3) st[o + 2] = (uint8_t)(vh >> 16);
+        o += chh;
+        prevd = X;
+      }
+      det = d != 0;
+    } else {
+      // chunk straddling the start or end of the input: word by word, real bytes only
+      uint32_t len[8], cnt;
+      analyze16<false>(x[k], wp, q0, lo, hi, len, cnt, det);
+      uint32_t o = 0, prev = wp;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t w = (x[k][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+        const uint32_t cj = len[j];
+        const uint32_t v = enc16<true>(w, prev, cj);
+        if (cj >= 1) st[o] = (uint8_t)v;
+        if (cj >= 2) st[o + 1] = (uint8_t)(v >> 8);
+        if (cj >= 3) st[o + 2] = (uint8_t)(v >> 16);
+        o += cj;
+        prev = w;
+      }
+    }
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
+      const uint16_t* in = in16 + L.mis;
+      const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
+      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+    }
+  }
+  __syncthreads();
+  store_span<WG, uint8_t>(stage, PAD, seg_total, reinterpret_cast<uint8_t*>(L.out), seg_base, L.cap);
+}
+
+template <int WG>
+__device__ uint64_t prefix_bytes16(const Launch& L, uint64_t off, uint64_t seg_units, unsigned long long* lds) {
+  constexpr uint64_t TW = 8ull * WG;
+  const uint64_t qoff = off + L.mis;
+  const uint64_t seg = qoff / seg_units;
+  uint32_t acc = 0;
+  uint32_t x[4];
+  for (uint64_t q0b = seg * seg_units; q0b < qoff; q0b += TW) {
+    const uint64_t q0 = q0b + 8ull * threadIdx.x;
+    load16(L, q0, x);
+    acc += count16(x, q0, L.mis, qoff, false);
+  }
+  const uint64_t s = block_sum_u64<WG>(acc, lds);
+  const uint64_t before = seg ? tile_inclusive(L.status, seg - 1) : 0;
+  return before + s;
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_fin_u16u8(Launch L) {
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  const uint64_t err = ld_agent(&L.ws->err);
+  const bool fault = ld_fault(L.ws) != 0;
+  uint64_t written = 0;
+  if (!fault && err != NO_ERR) written = prefix_bytes16<WG>(L, err, L.seg_units, lds);
+  if (threadIdx.x == 0) {
+    const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
+    if (fault) write_result(L.result, ST_DEVICE, 0, 0);
+    else if (err != NO_ERR) write_result(L.result, ST_SURROGATE, err, written);
+    else if (tot > L.cap) write_result(L.result, ST_OUTPUT_TOO_SMALL, tot, 0);
+    else write_result(L.result, ST_OK, tot, tot);
+    reset_ws(L.ws);
+  }
+}
+
+}  // namespace utfx_dev
