@@ -98,8 +98,8 @@ utfx_status utfx_set_stream(utfx_ctx *ctx, void *hip_stream);
  *             tile_bytes * tiles_per_segment input bytes and performs one cross-
  *             segment look-back for it.  The transcodes hold a whole segment in
  *             registers and its output in LDS, so they take only these pairs:
- *             UTF-8 -> UTF-16 (4096, 2 or 4), (8192, 2); UTF-16 -> UTF-8 (4096, 2, 4
- *             or 8), (8192, 2 or 4);
+ *             UTF-8 -> UTF-16 (4096, 2, 4 or 8), (8192, 2 or 4); UTF-16 -> UTF-8
+ *             (4096 or 8192, 2, 4 or 8);
  * wgs_per_cu: resident workgroups per compute unit of the batched kernel's persistent
  *             grid (1..16; ignored by the single-buffer kernels).
  * Returns UTFX_E_INVALID_ARG for an unsupported value. */

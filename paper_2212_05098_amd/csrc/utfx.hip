@@ -156,15 +156,18 @@ UTFX_DEFINE_LAUNCH(launch_len16, k_len16)
 UTFX_DEFINE_LAUNCH(launch_val8, k_validate8)
 UTFX_DEFINE_LAUNCH(launch_val16, k_validate16)
 
-// Transcode kernels are instantiated per (workgroup size, tiles per segment); the
-// pairs allowed for each direction keep the LDS stage of a whole segment within 64 KiB.
+// Transcode kernels are instantiated per (workgroup size, tiles per segment); a whole
+// segment's output is staged in LDS (up to 96 KiB of the 160 KiB a gfx950 workgroup
+// may use).
 hipError_t launch_u8u16(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {
   const dim3 g((uint32_t)grid);
   if (wg == 256) {
     if (L.seg == 2) hipLaunchKernelGGL((k_u8_to_u16<256, 2>), g, dim3(256), 0, s, L);
-    else hipLaunchKernelGGL((k_u8_to_u16<256, 4>), g, dim3(256), 0, s, L);
+    else if (L.seg == 4) hipLaunchKernelGGL((k_u8_to_u16<256, 4>), g, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((k_u8_to_u16<256, 8>), g, dim3(256), 0, s, L);
   } else {
-    hipLaunchKernelGGL((k_u8_to_u16<512, 2>), g, dim3(512), 0, s, L);
+    if (L.seg == 2) hipLaunchKernelGGL((k_u8_to_u16<512, 2>), g, dim3(512), 0, s, L);
+    else hipLaunchKernelGGL((k_u8_to_u16<512, 4>), g, dim3(512), 0, s, L);
   }
   return hipGetLastError();
 }
@@ -177,18 +180,21 @@ hipError_t launch_u16u8(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t
     else hipLaunchKernelGGL((k_u16_to_u8<256, 8>), g, dim3(256), 0, s, L);
   } else {
     if (L.seg == 2) hipLaunchKernelGGL((k_u16_to_u8<512, 2>), g, dim3(512), 0, s, L);
-    else hipLaunchKernelGGL((k_u16_to_u8<512, 4>), g, dim3(512), 0, s, L);
+    else if (L.seg == 4) hipLaunchKernelGGL((k_u16_to_u8<512, 4>), g, dim3(512), 0, s, L);
+    else hipLaunchKernelGGL((k_u16_to_u8<512, 8>), g, dim3(512), 0, s, L);
   }
   return hipGetLastError();
 }
 
 // (tile bytes, tiles per segment) pairs with a transcode kernel instance
 bool transcode_config_ok(int op, uint32_t tile_bytes, uint32_t seg) {
-  if (op == UTFX_OP_UTF8_TO_UTF16) return (tile_bytes == 4096 && (seg == 2 || seg == 4)) || (tile_bytes == 8192 && seg == 2);
-  if (op == UTFX_OP_UTF16_TO_UTF8)
+  if (op == UTFX_OP_UTF8_TO_UTF16)
     return (tile_bytes == 4096 && (seg == 2 || seg == 4 || seg == 8)) || (tile_bytes == 8192 && (seg == 2 || seg == 4));
+  if (op == UTFX_OP_UTF16_TO_UTF8)
+    return (seg == 2 || seg == 4 || seg == 8) && (tile_bytes == 4096 || tile_bytes == 8192);
   return true;
 }
+
 UTFX_DEFINE_LAUNCH(launch_fin_u8u16, k_fin_u8u16)
 UTFX_DEFINE_LAUNCH(launch_fin_u16u8, k_fin_u16u8)
 
@@ -342,10 +348,10 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
     c->seg_tiles[i] = 8;
     c->wgs_per_cu[i] = 4;
   }
-  c->tile_bytes[UTFX_OP_UTF8_TO_UTF16] = 4096;
+  c->tile_bytes[UTFX_OP_UTF8_TO_UTF16] = 8192;
   c->seg_tiles[UTFX_OP_UTF8_TO_UTF16] = 4;
-  c->tile_bytes[UTFX_OP_UTF16_TO_UTF8] = 4096;
-  c->seg_tiles[UTFX_OP_UTF16_TO_UTF8] = 8;
+  c->tile_bytes[UTFX_OP_UTF16_TO_UTF8] = 8192;
+  c->seg_tiles[UTFX_OP_UTF16_TO_UTF8] = 4;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
     int cus = 0;

@@ -7,8 +7,8 @@
 //            units are counted at its first unit), a packed wave scan per pair of
 //            tiles, and the segment's total published for the decoupled look-back;
 //   phase B  per chunk: classify, validate, decode / encode, and scatter the units
-//            into an LDS stage holding the whole segment's output.  Wave 0 runs the
-//            look-back first; the other waves do not wait for it;
+//            into an LDS stage holding the whole segment's output; then wave 0 runs
+//            the look-back, by when its predecessors have usually published;
 //   store    one barrier, then coalesced 16-byte stores of the stage at the
 //            segment's global offset.
 // The chunk offsets come from the length formula, where a character is counted at
@@ -187,11 +187,7 @@ __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);  // contains a barrier
 
-  if (wid == 0) {
-    if (lane == 0) publish_aggregate(L.status, seg, seg_total, epoch);
-    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
-    if (lane == 0) seg_base = b;
-  }
+  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
 
   // ---- phase B: per chunk, validate + decode + scatter into the stage
 #pragma unroll
@@ -240,6 +236,11 @@ __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
       const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
       if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
     }
+  }
+  if (wid == 0) {
+    // the look-back runs after the wave's own work, when predecessors are likely done
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    if (lane == 0) seg_base = b;
   }
   __syncthreads();
 
@@ -411,11 +412,7 @@ __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);
 
-  if (wid == 0) {
-    if (lane == 0) publish_aggregate(L.status, seg, seg_total, epoch);
-    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
-    if (lane == 0) seg_base = b;
-  }
+  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
 
   // ---- phase B
 #pragma unroll
@@ -495,6 +492,11 @@ __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
       const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
       if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
     }
+  }
+  if (wid == 0) {
+    // the look-back runs after the wave's own work, when predecessors are likely done
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    if (lane == 0) seg_base = b;
   }
   __syncthreads();
   store_span<WG, uint8_t>(stage, PAD, seg_total, reinterpret_cast<uint8_t*>(L.out), seg_base, L.cap);
