@@ -105,19 +105,18 @@ __device__ __forceinline__ int classify8(Chunk8& c) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) c.C[k] = cls_lut(c.x[k]);
   const uint32_t orc = c.Cp | c.C[0] | c.C[1] | c.C[2] | c.C[3];
+  if (!__any((orc & 0x0C0C0C0Cu) != 0)) return 0;
+  if (!__any((orc & 0x20202020u) != 0)) return 1;
+  // some lead >= E0: look for leads >= F0 (only then are their bits needed)
   const uint32_t fp = f0_bits(c.Cp, c.xp), f0 = f0_bits(c.C[0], c.x[0]), f1 = f0_bits(c.C[1], c.x[1]),
                  f2 = f0_bits(c.C[2], c.x[2]), f3 = f0_bits(c.C[3], c.x[3]);
-  const uint32_t orf = fp | f0 | f1 | f2 | f3;
-  int m = __any(orf != 0) ? 3 : (__any((orc & 0x20202020u) != 0) ? 2 : (__any((orc & 0x0C0C0C0Cu) != 0) ? 1 : 0));
-  m = __builtin_amdgcn_readfirstlane(m);
-  if (m == 3) {
-    c.Cp |= fp;
-    c.C[0] |= f0;
-    c.C[1] |= f1;
-    c.C[2] |= f2;
-    c.C[3] |= f3;
-  }
-  return m;
+  if (!__any((fp | f0 | f1 | f2 | f3) != 0)) return 2;
+  c.Cp |= fp;
+  c.C[0] |= f0;
+  c.C[1] |= f1;
+  c.C[2] |= f2;
+  c.C[3] |= f3;
+  return 3;
 }
 
 // Per-chunk analysis, and (DECODE) the UTF-16 words of the chunk.

@@ -140,7 +140,8 @@ __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
   constexpr uint32_t SEGB = T * S;
   constexpr uint32_t PAD = 16;            // stage slots below the segment's formula offset
   constexpr uint32_t LIM = PAD + SEGB;    // a valid chunk ends at or below this slot
-  constexpr uint32_t SSZ = LIM + 32;
+  constexpr uint32_t DUMP = LIM + 16;     // 16 slots for writes that must not land
+  constexpr uint32_t SSZ = DUMP + 16;
   __shared__ __attribute__((aligned(16))) uint16_t stage[SSZ];
   __shared__ uint32_t wtot[NW * (S / 2)];
   __shared__ uint32_t halo[S * NW];
@@ -213,8 +214,12 @@ __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
     // valid prefix at most two positions in a row do not emit, so only the last two
     // positions can lack a later emit in the chunk, and those write only real words.
     // Past the first error every slot is at or beyond the valid prefix's length, and a
-    // chunk whose slots would leave the stage is past it and writes nothing.
-    if (idx + 16 <= LIM) {
+    // chunk whose slots would leave the stage is past it and writes to a dump area.
+    // Writes that must not land go to the dump slot, so the loop has no branches.
+    const bool fits = idx + 16 <= LIM;
+    uint16_t* pw = stage + (fits ? idx : DUMP);
+    uint16_t* const dump = stage + DUMP;
+    if (full) {
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
 #pragma unroll
@@ -223,13 +228,24 @@ __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
           const uint32_t pair = W[2 * kk + (i >> 1)];
           const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
           const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
-          if ((full && e < 14) || bit) stage[idx] = word;
-          idx += bit;
+          *((e < 14 || bit) ? pw : dump) = word;
+          pw += bit;
         }
       }
     } else {
-      idx = LIM;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t pair = W[2 * kk + (i >> 1)];
+          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+          const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
+          *(bit ? pw : dump) = word;
+          pw += bit;
+        }
+      }
     }
+    idx = fits ? (uint32_t)(pw - stage) : LIM;
     if (k == S - 1 && threadIdx.x == WG - 1) bounds[1] = idx;
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
@@ -364,13 +380,23 @@ __device__ __forceinline__ uint32_t count16(const uint32_t x[4], uint64_t q0, ui
   return acc;
 }
 
+// Writes the c (0..3) bytes of v at p.  With own_only false all three bytes are
+// written (c >= 1; the spare ones are overwritten by later words of the chunk);
+// otherwise the spare ones go to the dump slot, so there are no branches.
+__device__ __forceinline__ void put3(uint8_t* p, uint32_t v, uint32_t c, bool own_only, uint8_t* dump) {
+  *((!own_only || c >= 1) ? p : dump) = (uint8_t)v;
+  *((!own_only || c >= 2) ? p + 1 : dump) = (uint8_t)(v >> 8);
+  *((!own_only || c >= 3) ? p + 2 : dump) = (uint8_t)(v >> 16);
+}
+
 template <int WG, int S>
 __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
   constexpr int NW = WG / 64;
   constexpr uint32_t TW = 8u * WG;      // words per tile
   constexpr uint32_t SEGW = TW * S;
   constexpr uint32_t PAD = 16;
-  constexpr uint32_t SSZ = PAD + 3 * SEGW + 48;
+  constexpr uint32_t DUMP = PAD + 3 * SEGW + 32;  // slot for writes that must not land
+  constexpr uint32_t SSZ = DUMP + 16;
   __shared__ __attribute__((aligned(16))) uint8_t stage[SSZ];
   __shared__ uint32_t wtot[NW * (S / 2)];
   __shared__ uint32_t halo[S * NW];
@@ -423,6 +449,7 @@ __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
     const uint32_t wp = xprev >> 16;
     const bool full = segfull || (q0 >= lo && q0 + 8 <= hi);
     uint8_t* st = stage + PAD + off[k];
+    uint8_t* const dump = stage + DUMP;
     bool det = false;
     if (!__any(!full || any_surrogate(x[k], wp))) {
       // no surrogate anywhere in the wave's chunks: lengths 1..3, nothing to validate.
@@ -436,14 +463,9 @@ __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
         const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
         uint32_t vl, vh;
         pk_enc16(x[k][kk], cl, chh, vl, vh);
-        const bool last = (kk == 3);
-        st[o] = (uint8_t)vl;
-        if (!last || cl >= 2) st[o + 1] = (uint8_t)(vl >> 8);
-        if (!last || cl >= 3) st[o + 2] = (uint8_t)(vl >> 16);
+        put3(st + o, vl, cl, kk == 3, dump);
         o += cl;
-        st[o] = (uint8_t)vh;
-        if (!last || chh >= 2) st[o + 1] = (uint8_t)(vh >> 8);
-        if (!last || chh >= 3) st[o + 2] = (uint8_t)(vh >> 16);
+        put3(st + o, vh, chh, kk == 3, dump);
         o += chh;
       }
     } else if (full) {
@@ -457,14 +479,9 @@ __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
         const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
         uint32_t vl, vh;
         pk_enc16s(X, P, cl, chh, vl, vh);
-        const bool last = (kk == 3);
-        st[o] = (uint8_t)vl;
-        if (!last || cl >= 2) st[o + 1] = (uint8_t)(vl >> 8);
-        if (!last || cl >= 3) st[o + 2] = (uint8_t)(vl >> 16);
+        put3(st + o, vl, cl, kk == 3, dump);
         o += cl;
-        st[o] = (uint8_t)vh;
-        if (!last || chh >= 2) st[o + 1] = (uint8_t)(vh >> 8);
-        if (!last || chh >= 3) st[o + 2] = (uint8_t)(vh >> 16);
+        put3(st + o, vh, chh, kk == 3, dump);
         o += chh;
         prevd = X;
       }
@@ -479,9 +496,7 @@ __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
         const uint32_t w = (x[k][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
         const uint32_t cj = len[j];
         const uint32_t v = enc16<true>(w, prev, cj);
-        if (cj >= 1) st[o] = (uint8_t)v;
-        if (cj >= 2) st[o + 1] = (uint8_t)(v >> 8);
-        if (cj >= 3) st[o + 2] = (uint8_t)(v >> 16);
+        put3(st + o, v, cj, true, dump);
         o += cj;
         prev = w;
       }
