@@ -100,8 +100,8 @@ utfx_status utfx_set_stream(utfx_ctx *ctx, void *hip_stream);
  *             registers and its output in LDS, so they take only these pairs:
  *             UTF-8 -> UTF-16 (4096, 2, 4 or 8), (8192, 2 or 4); UTF-16 -> UTF-8
  *             (4096 or 8192, 2, 4 or 8);
- * wgs_per_cu: resident workgroups per compute unit of the batched kernel's persistent
- *             grid (1..16; ignored by the single-buffer kernels).
+ * wgs_per_cu: workgroups per compute unit of the batched call's persistent grid for
+ *             long strings (1..16, default 2; ignored by the single-buffer kernels).
  * Returns UTFX_E_INVALID_ARG for an unsupported value. */
 typedef enum {
   UTFX_OP_UTF8_TO_UTF16 = 0,
@@ -157,11 +157,14 @@ utfx_status utfx_utf8_to_utf16le_async(utfx_ctx *ctx, const uint8_t *in, size_t 
 utfx_status utfx_utf16le_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
                                        uint8_t *out, size_t cap_bytes, utfx_result *d_result);
 
-/* ---- batched: many independent strings in one persistent launch ---------------- */
+/* ---- batched: many independent strings in one call ---------------------------- */
 /* One string.  in_off/out_off are byte offsets into the arenas; in_len is in input
  * units and out_cap in output units; dir 0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8.
- * Offsets of UTF-16 data (the input of dir 1, the output of dir 0) must be even.
- * Each item gets the same result as the single-buffer call on its bytes. */
+ * UTF-16 data (the input of dir 1, the output of dir 0) must start at an even
+ * address.  Each item gets the same result as the single-buffer call on its bytes;
+ * an item with a bad descriptor (dir > 1, odd UTF-16 address, in_len above
+ * UTFX_MAX_UNITS, input or output slot not inside its arena) gets
+ * UTFX_E_INVALID_ARG.  Items may share input; their outputs must not overlap. */
 typedef struct {
   uint64_t in_off;
   uint64_t in_len;
@@ -171,16 +174,22 @@ typedef struct {
   uint32_t pad;
 } utfx_item;
 
-/* Plans and runs the batch: d_items (device, n_items entries) describe the strings,
- * d_results (device, n_items entries) receive one result each.  The per-string tile
- * table is built on the device, so the call issues a fixed sequence of kernels that
- * can be captured into a HIP graph and replayed with new contents of the same
- * buffers.  max_in_units bounds every in_len (used to size the plan); the call fails
- * with UTFX_E_INVALID_ARG if an item exceeds it or if the plan does not fit the
- * context's workspace.  Returns UTFX_OK if queued. */
-utfx_status utfx_batch_run(utfx_ctx *ctx, const uint8_t *in_arena, uint8_t *out_arena,
-                           const utfx_item *d_items, uint32_t n_items, uint64_t max_in_units,
-                           utfx_result *d_results);
+/* Runs the batch: the arenas hold in_bytes and out_bytes bytes; d_items (device,
+ * n_items entries) describe the strings, d_results (device, n_items entries) receive
+ * one result each.  Strings of up to 16,384 units
+ * are transcoded by one wavefront each; longer ones are cut into segments that
+ * persistent workgroups take in order, with a look-back that ends at the string's
+ * first segment (sections 6 and 7 per string).  The plan is built on the device, so
+ * the call issues a fixed sequence of kernels with no allocation and no host
+ * synchronisation once the workspace is large enough: it can be captured into a HIP
+ * graph and replayed with new contents of the same buffers.  total_in_units bounds
+ * the sum of in_len over the items (it sizes the plan); if the items add up to more,
+ * every string above 16,384 units gets UTFX_E_INVALID_ARG.  Growing the workspace
+ * (first call, or a larger n_items / total_in_units) synchronises the stream once.
+ * Returns UTFX_OK if queued, UTFX_E_INVALID_ARG for null pointers. */
+utfx_status utfx_batch_run(utfx_ctx *ctx, const uint8_t *in_arena, size_t in_bytes, uint8_t *out_arena,
+                           size_t out_bytes, const utfx_item *d_items, uint32_t n_items,
+                           uint64_t total_in_units, utfx_result *d_results);
 
 #ifdef __cplusplus
 }

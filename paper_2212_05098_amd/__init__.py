@@ -106,7 +106,7 @@ def lib() -> ctypes.CDLL:
         "utfx_validate_utf16le_async": (I, [P, P, Z, P]),
         "utfx_utf8_to_utf16le_async": (I, [P, P, Z, P, Z, P]),
         "utfx_utf16le_to_utf8_async": (I, [P, P, Z, P, Z, P]),
-        "utfx_batch_run": (I, [P, P, P, P, U32, U64, P]),
+        "utfx_batch_run": (I, [P, P, Z, P, Z, P, U32, U64, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -249,18 +249,37 @@ class Context:
         p, n = _ptr_len(src, 2)
         return int(self._lib.utfx_utf8_length_from_utf16le_async(self._h, p, n, d_result.data_ptr()))
 
-    def batch_run(self, in_arena, out_arena, d_items, n_items: int, max_in_units: int, d_results) -> int:
+    def batch_run(self, in_arena, out_arena, d_items, n_items: int, total_in_units: int, d_results) -> int:
+        """Queue a batch (see utfx_batch_run); the arenas are uint8 device tensors."""
         return int(
             self._lib.utfx_batch_run(
                 self._h,
                 in_arena.data_ptr(),
+                in_arena.numel() * in_arena.element_size(),
                 out_arena.data_ptr(),
+                out_arena.numel() * out_arena.element_size(),
                 d_items.data_ptr(),
                 n_items,
-                max_in_units,
+                total_in_units,
                 d_results.data_ptr(),
             )
         )
+
+
+# numpy layout of utfx_item (include/utfx.h)
+ITEM_FIELDS = [("in_off", "<u8"), ("in_len", "<u8"), ("out_off", "<u8"), ("out_cap", "<u8"), ("dir", "<u4"),
+               ("pad", "<u4")]
+
+
+def pack_items(in_off, in_len, out_off, out_cap, dirs, device="cuda"):
+    """Item table for batch_run: a uint8 tensor of len(in_off) utfx_item records."""
+    import numpy as np
+    import torch
+
+    a = np.zeros(len(in_off), dtype=np.dtype(ITEM_FIELDS))
+    a["in_off"], a["in_len"], a["out_off"], a["out_cap"], a["dir"] = in_off, in_len, out_off, out_cap, dirs
+    t = torch.from_numpy(a.view(np.uint8).copy())
+    return t.to(device) if device else t
 
 
 def results_from_tensor(t) -> list:

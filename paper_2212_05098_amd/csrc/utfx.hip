@@ -7,6 +7,7 @@
 // back.  Kernels reset the workspace counters themselves (the last workgroup of every
 // launch does it), so no call issues a memset and launches can be graph-captured.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -21,6 +22,7 @@ using namespace utfx_dev;
 static_assert(sizeof(utfx_result) == 24, "utfx_result layout");
 static_assert(sizeof(Result) == sizeof(utfx_result), "device result layout");
 static_assert(sizeof(WsHeader) == 64, "workspace header layout");
+static_assert(sizeof(utfx_item) == sizeof(BItem) && offsetof(utfx_item, dir) == offsetof(BItem, dir), "item layout");
 
 struct utfx_ctx {
   hipStream_t stream = nullptr;
@@ -132,6 +134,7 @@ utfx_status prep(utfx_ctx* c, int op, const void* in, uint64_t n, uint32_t unit,
   utfx_status s = ensure_tiles(c, L.ntiles);
   if (s != UTFX_OK) return s;
   L.ws = c->ws;
+  L.err = &c->ws->err;
   L.status = c->status;
   L.result = result;
   L.out = nullptr;
@@ -352,6 +355,7 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
   c->seg_tiles[UTFX_OP_UTF8_TO_UTF16] = 4;
   c->tile_bytes[UTFX_OP_UTF16_TO_UTF8] = 8192;
   c->seg_tiles[UTFX_OP_UTF16_TO_UTF8] = 4;
+  c->wgs_per_cu[UTFX_OP_BATCH] = 2;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
     int cus = 0;
@@ -451,12 +455,13 @@ utfx_status utfx_utf16le_to_utf8_async(utfx_ctx* c, const uint16_t* in, size_t n
   return run(c, U16U8, in, n, out, cap, r);
 }
 
-utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, uint8_t* out_arena, const utfx_item* d_items,
-                           uint32_t n_items, uint64_t max_in_units, utfx_result* d_results) {
+utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes, uint8_t* out_arena,
+                           size_t out_bytes, const utfx_item* d_items, uint32_t n_items, uint64_t total_in_units,
+                           utfx_result* d_results) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
-  return batch_run(c->batch, c->stream, c->num_cus, c->tile_bytes[UTFX_OP_BATCH], c->wgs_per_cu[UTFX_OP_BATCH],
-                   in_arena, out_arena, d_items, n_items, max_in_units, d_results, c->err, sizeof(c->err));
+  return batch_run(c->batch, c->stream, c->num_cus, c->wgs_per_cu[UTFX_OP_BATCH], in_arena, in_bytes, out_arena,
+                   out_bytes, d_items, n_items, total_in_units, d_results, c->err, sizeof(c->err));
 }
 
 }  // extern "C"

@@ -1,16 +1,544 @@
-// utfx_batch.hpp -- batched path (placeholder until the persistent kernel lands).
+// utfx_batch.hpp -- many independent strings in one call (the batched path).
+//
+// Every string (item) gets the result the single-buffer call would give on its bytes.
+// Kernels, in stream order:
+//   k_batch_begin  advance the batch epoch; clear the segment ticket, the large-item
+//                  count and the fault flag (one thread, so the call needs no memset
+//                  and can be captured into a graph);
+//   k_batch_plan   per item: check its descriptor and, for a large item (more than
+//                  SMALL_MAX input units), count its segments; exclusive scans of the
+//                  counts over items, one per direction (workgroup scan + decoupled
+//                  look-back across workgroups); each large item writes the segment ->
+//                  item map of its segments and enters the large-item list;
+//   k_batch_small  one wave per item of at most SMALL_MAX units: the wave walks the
+//                  string 1 KiB (512 words) at a time carrying the output offset, so it
+//                  needs no look-back and no barrier, and writes the item's result;
+//   k_batch_large  persistent workgroups take segments of large items in ticket order
+//                  and run the single-buffer segment code on them; a segment's look-back
+//                  ends at its item's first segment, which publishes its prefix directly
+//                  (one launch per direction, so each holds only its own registers);
+//   k_batch_fin    one workgroup per large item: the result from its segments.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdio.h>
+
 #include "utfx.h"
+#include "utfx_transcode.hpp"
+
+namespace utfx_dev {
+
+struct BItem {  // utfx_item
+  uint64_t in_off, in_len, out_off, out_cap;
+  uint32_t dir, pad;
+};
+
+// Items up to this many input units are transcoded by one wave.
+constexpr uint64_t SMALL_MAX = 16384;
+// Geometry of the large-item segments (workgroup size, tiles per segment per direction).
+constexpr int BWG = 512, BS8 = 4, BS16 = 4;
+constexpr uint64_t BSEG8 = 16ull * BWG * BS8;   // UTF-8 bytes per segment
+constexpr uint64_t BSEG16 = 8ull * BWG * BS16;  // UTF-16 words per segment
+constexpr int PLAN_WG = 256;
+constexpr int SMALL_WG = 256;
+
+struct BatchArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  uint64_t in_bytes, out_bytes;      // arena sizes
+  const BItem* items;
+  Result* results;
+  uint64_t n_items;
+  // ws: epoch, fault; acc = large items; err = sum of in_len over the valid items;
+  // spare0 / pad[0] = segment tickets and spare1 / pad[1] = segment totals of the
+  // UTF-8 / UTF-16 large items
+  WsHeader* ws;
+  unsigned long long* unit_start;    // n_items: an item's first segment in its direction's numbering
+  unsigned long long* item_err;      // n_items: first error of a large item
+  unsigned long long* status[2];     // cap_units each: look-back status word per segment
+  uint32_t* unit_item[2];            // cap_units each: item of each segment
+  uint32_t* large;                   // n_items: list of large items
+  unsigned long long* plan_status[2];  // one status word per plan workgroup and direction
+  uint64_t cap_units;
+  uint64_t total_in;                 // the caller's bound on the sum of in_len
+};
+
+// Whether the plan holds: the items add up to at most the caller's bound, and so
+// their segments fit the workspace.
+__device__ __forceinline__ bool plan_ok(const BatchArgs& A) {
+  return ld_agent(&A.ws->err) <= A.total_in && ld_agent(&A.ws->spare1) <= A.cap_units &&
+         ld_agent(&A.ws->pad[1]) <= A.cap_units;
+}
+
+__device__ __forceinline__ unsigned long long* ticket_of(WsHeader* ws, int dir) {
+  return dir ? &ws->pad[0] : &ws->spare0;
+}
+__device__ __forceinline__ unsigned long long* total_of(WsHeader* ws, int dir) {
+  return dir ? &ws->pad[1] : &ws->spare1;
+}
+
+__device__ __forceinline__ bool item_ok(const BatchArgs& A, const BItem& it) {
+  if (it.dir > 1 || it.in_len > (1ull << 35) || it.out_cap > (3ull << 35)) return false;
+  const uint64_t iu = it.dir ? 2 : 1, ou = it.dir ? 1 : 2;
+  if (it.in_off > A.in_bytes || it.in_len * iu > A.in_bytes - it.in_off) return false;
+  if (it.out_off > A.out_bytes || it.out_cap * ou > A.out_bytes - it.out_off) return false;
+  if (it.dir == 1 && (((uintptr_t)(A.in + it.in_off)) & 1)) return false;   // UTF-16 input
+  if (it.dir == 0 && (((uintptr_t)(A.out + it.out_off)) & 1)) return false;  // UTF-16 output
+  return true;
+}
+
+__device__ __forceinline__ uint64_t item_units(const BatchArgs& A, const BItem& it) {
+  const uint32_t unit = it.dir ? 2u : 1u;
+  const uint64_t mis = (((uintptr_t)(A.in + it.in_off)) & 15) / unit;
+  const uint64_t seg = it.dir ? BSEG16 : BSEG8;
+  return (mis + it.in_len + 1 + seg - 1) / seg;
+}
+
+// The single-buffer launch description of a large item.
+__device__ __forceinline__ Launch item_launch(const BatchArgs& A, const BItem& it, uint64_t i) {
+  Launch L;
+  const uint32_t unit = it.dir ? 2u : 1u;
+  const uintptr_t a = (uintptr_t)(A.in + it.in_off);
+  L.base = reinterpret_cast<const uint8_t*>(a & ~(uintptr_t)15);
+  L.mis = (a & 15) / unit;
+  L.n = it.in_len;
+  L.out = A.out + it.out_off;
+  L.cap = it.out_cap;
+  L.ws = A.ws;
+  L.err = A.item_err + i;
+  L.status = A.status[it.dir] + A.unit_start[i];
+  L.result = A.results + i;
+  L.ntiles = item_units(A, it);
+  L.seg_units = it.dir ? BSEG16 : BSEG8;
+  L.seg = it.dir ? BS16 : BS8;
+  L.wg = BWG;
+  return L;
+}
+
+__global__ void k_batch_begin(WsHeader* ws) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const uint32_t ep = __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ws->epoch, (ep + 1) & EPOCH_MASK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    st_agent(&ws->spare0, 0);
+    st_agent(&ws->spare1, 0);
+    st_agent(&ws->pad[0], 0);
+    st_agent(&ws->pad[1], 0);
+    st_agent(&ws->acc, 0);
+    st_agent(&ws->err, 0);
+    __hip_atomic_store(&ws->fault, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
+  __shared__ uint32_t scr[2][PLAN_WG / 64];
+  __shared__ unsigned long long pfx[2];
+  __shared__ unsigned long long sum_scr[PLAN_WG / 64 + 2];
+  const uint64_t i = (uint64_t)blockIdx.x * PLAN_WG + threadIdx.x;
+  uint32_t units = 0;
+  int dir = 0;
+  uint64_t len = 0;
+  if (i < A.n_items) {
+    const BItem it = A.items[i];
+    if (item_ok(A, it)) {
+      len = it.in_len;
+      if (it.in_len > SMALL_MAX) {
+        units = (uint32_t)item_units(A, it);
+        dir = (int)it.dir;
+      }
+    }
+  }
+  const uint64_t len_sum = block_sum_u64<PLAN_WG>(len, sum_scr);
+  if (threadIdx.x == 0 && len_sum) atomicAdd(&A.ws->err, (unsigned long long)len_sum);
+  uint32_t total[2], local[2];
+  local[0] = block_excl_scan<PLAN_WG>(dir == 0 ? units : 0u, total[0], scr[0]);
+  local[1] = block_excl_scan<PLAN_WG>(dir == 1 ? units : 0u, total[1], scr[1]);
+  const uint32_t epoch = cur_epoch(A.ws);
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      if (threadIdx.x == 0) publish_aggregate(A.plan_status[d], blockIdx.x, total[d], epoch);
+      const uint64_t b = lookback_wave(A.plan_status[d], blockIdx.x, total[d], epoch, A.ws);
+      if (threadIdx.x == 0) pfx[d] = b;
+    }
+  }
+  __syncthreads();
+  if (i < A.n_items) {
+    const uint64_t start = pfx[dir] + local[dir];
+    A.unit_start[i] = start;
+    if (units) {
+      A.item_err[i] = NO_ERR;
+      const unsigned long long slot = atomicAdd(&A.ws->acc, 1ull);
+      A.large[slot] = (uint32_t)i;
+      if (start + units <= A.cap_units)
+        for (uint32_t u = 0; u < units; ++u) A.unit_item[dir][start + u] = (uint32_t)i;
+    }
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    st_agent(total_of(A.ws, 0), pfx[0] + total[0]);
+    st_agent(total_of(A.ws, 1), pfx[1] + total[1]);
+  }
+}
+
+// A value the whole wave holds, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// One wave transcodes a UTF-8 string of n bytes (n <= SMALL_MAX) 1 KiB at a time.
+// stage: the wave's LDS (WSTAGE bytes).
+constexpr uint32_t WSTAGE = 2176;
+__device__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, uint16_t* out, uint64_t cap, uint16_t* stage,
+                               Result* res) {
+  constexpr uint32_t PAD = 16, LIM = PAD + 1024, DUMP = LIM + 16;
+  static_assert((DUMP + 16) * 2 <= WSTAGE, "wave stage");
+  const uint32_t lane = threadIdx.x & 63;
+  Launch L = {};
+  L.base = reinterpret_cast<const uint8_t*>((uintptr_t)in & ~(uintptr_t)15);
+  L.mis = (uintptr_t)in & 15;
+  L.n = n;
+  const uint64_t lo = L.mis, hi = L.mis + n;
+  uint64_t running = 0;  // formula units before the chunk
+  uint32_t carry = 0;    // the 4 bytes before the chunk
+  uint64_t err = NO_ERR;
+  for (uint64_t c0 = 0; c0 <= hi; c0 += 1024) {
+    const uint64_t q0 = c0 + 16ull * lane;
+    uint32_t x[4], m[4];
+    load8(L, q0, x);
+    const bool full = q0 >= lo && q0 + 16 <= hi;
+    if (!full) range_masks(q0, lo, hi, m);
+    const uint32_t cnt = count8(x, full ? nullptr : m);
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t tot = __shfl(incl, 63, 64);
+    const uint32_t xp = wave_shr1(x[3], carry);
+    carry = __shfl(x[3], 63, 64);
+    uint32_t first, det;
+    const uint32_t end = chunk_u8_to_u16<PAD, LIM, DUMP>(x, xp, full, q0, lo, hi, incl - cnt, stage, &first, &det);
+    const uint32_t st0 = __shfl(first, 0, 64);
+    uint32_t st1 = __shfl(end, 63, 64);
+    st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
+    __builtin_amdgcn_wave_barrier();
+    store_span<uint16_t>(stage, st0, st1 - st0, out, running + st0 - PAD, cap, lane, 64);
+    __builtin_amdgcn_wave_barrier();
+    if (__any(det)) {
+      uint64_t e = NO_ERR;
+      if (det) {
+        const int64_t p0 = (int64_t)q0 - (int64_t)lo;
+        e = locate8(in, n, p0 - 3, p0 + 16);
+      }
+      e = wave_min_u64(e);
+      if (e != NO_ERR) {
+        err = e;
+        break;
+      }
+    }
+    running += tot;
+  }
+  if (err != NO_ERR) {
+    // words of the valid prefix: the length formula over [0, err)
+    uint64_t acc = 0;
+    for (uint64_t c0 = 0; c0 < lo + err; c0 += 1024) {
+      const uint64_t q0 = c0 + 16ull * lane;
+      uint32_t x[4], m[4];
+      load8(L, q0, x);
+      range_masks(q0, lo, lo + err, m);
+      acc += count8(x, m);
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0) write_result(res, utf8_kind_at(in, n, err), err, acc);
+  } else if (lane == 0) {
+    if (running > cap) write_result(res, ST_OUTPUT_TOO_SMALL, running, 0);
+    else write_result(res, ST_OK, running, running);
+  }
+}
+
+// One wave transcodes a UTF-16LE string of n words (n <= SMALL_MAX) 512 words at a time.
+__device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uint64_t cap, uint8_t* stage,
+                               Result* res) {
+  constexpr uint32_t PAD = 16, DUMP = PAD + 3 * 512 + 32;
+  static_assert(DUMP + 16 <= WSTAGE, "wave stage");
+  const uint32_t lane = threadIdx.x & 63;
+  Launch L = {};
+  L.base = reinterpret_cast<const uint8_t*>((uintptr_t)in & ~(uintptr_t)15);
+  L.mis = ((uintptr_t)in & 15) / 2;
+  L.n = n;
+  const uint64_t lo = L.mis, hi = L.mis + n;
+  uint64_t running = 0;
+  uint32_t carry = 0;  // high half: the word before the chunk
+  uint64_t err = NO_ERR;
+  for (uint64_t c0 = 0; c0 <= hi; c0 += 512) {
+    const uint64_t q0 = c0 + 8ull * lane;
+    uint32_t x[4];
+    load16(L, q0, x);
+    const bool full = q0 >= lo && q0 + 8 <= hi;
+    const uint32_t cnt = count16(x, q0, lo, hi, full);
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t tot = __shfl(incl, 63, 64);
+    const uint32_t xprev = wave_shr1(x[3], carry);
+    carry = __shfl(x[3], 63, 64);
+    const bool det = chunk_u16_to_u8(x, xprev, full, q0, lo, hi, stage + PAD + (incl - cnt), stage + DUMP);
+    __builtin_amdgcn_wave_barrier();
+    store_span<uint8_t>(stage, PAD, tot, out, running, cap, lane, 64);
+    __builtin_amdgcn_wave_barrier();
+    if (__any(det)) {
+      uint64_t e = NO_ERR;
+      if (det) {
+        const int64_t p0 = (int64_t)q0 - (int64_t)lo;
+        e = locate16(in, n, p0 - 1, p0 + 8);
+      }
+      e = wave_min_u64(e);
+      if (e != NO_ERR) {
+        err = e;
+        break;
+      }
+    }
+    running += tot;
+  }
+  if (err != NO_ERR) {
+    uint64_t acc = 0;
+    for (uint64_t c0 = 0; c0 < lo + err; c0 += 512) {
+      const uint64_t q0 = c0 + 8ull * lane;
+      uint32_t x[4];
+      load16(L, q0, x);
+      acc += count16(x, q0, lo, lo + err, false);
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0) write_result(res, ST_SURROGATE, err, acc);
+  } else if (lane == 0) {
+    if (running > cap) write_result(res, ST_OUTPUT_TOO_SMALL, running, 0);
+    else write_result(res, ST_OK, running, running);
+  }
+}
+
+__global__ void __launch_bounds__(SMALL_WG) k_batch_small(BatchArgs A) {
+  constexpr int NW = SMALL_WG / 64;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[NW * WSTAGE];
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint64_t i = (uint64_t)blockIdx.x * NW + wid;
+  if (i >= A.n_items) return;
+  const BItem it = A.items[i];
+  Result* res = A.results + i;
+  if (!item_ok(A, it)) {
+    if ((threadIdx.x & 63) == 0) write_result(res, ST_INVALID_ARG, 0, 0);
+    return;
+  }
+  if (it.in_len > SMALL_MAX) return;  // a large item: k_batch_large and k_batch_fin
+  uint8_t* st = smem + wid * WSTAGE;
+  if (it.dir == 0)
+    wave_u8_to_u16(A.in + it.in_off, it.in_len, reinterpret_cast<uint16_t*>(A.out + it.out_off), it.out_cap,
+                   reinterpret_cast<uint16_t*>(st), res);
+  else
+    wave_u16_to_u8(reinterpret_cast<const uint16_t*>(A.in + it.in_off), it.in_len, A.out + it.out_off,
+                   it.out_cap, st, res);
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(BWG) k_batch_large(BatchArgs A) {
+  __shared__ __attribute__((aligned(16))) uint8_t raw[DIR ? sizeof(Seg16Smem<BWG, BS16>) : sizeof(Seg8Smem<BWG, BS8>)];
+  __shared__ unsigned long long tk;
+  const uint64_t total = ld_agent(total_of(A.ws, DIR));
+  if (!plan_ok(A)) return;
+  while (true) {
+    if (threadIdx.x == 0) tk = atomicAdd(ticket_of(A.ws, DIR), 1ull);
+    __syncthreads();
+    const uint64_t t = uniform_u64(tk);
+    if (t >= total) break;
+    const uint32_t i = __builtin_amdgcn_readfirstlane(A.unit_item[DIR][t]);
+    const BItem it = A.items[i];
+    const Launch L = item_launch(A, it, i);
+    const uint64_t seg = t - A.unit_start[i];
+    if (DIR == 0) seg_u8_to_u16<BWG, BS8>(L, seg, *reinterpret_cast<Seg8Smem<BWG, BS8>*>(raw));
+    else seg_u16_to_u8<BWG, BS16>(L, seg, *reinterpret_cast<Seg16Smem<BWG, BS16>*>(raw));
+    __syncthreads();
+  }
+}
+
+constexpr int FIN_WG = 256;
+__global__ void __launch_bounds__(FIN_WG) k_batch_fin(BatchArgs A) {
+  __shared__ unsigned long long lds[FIN_WG / 64 + 2];
+  const uint64_t nl = ld_agent(&A.ws->acc);
+  const bool over = !plan_ok(A);
+  const bool fault = ld_fault(A.ws) != 0;
+  for (uint64_t k = blockIdx.x; k < nl; k += gridDim.x) {
+    const uint32_t i = A.large[k];
+    const BItem it = A.items[i];
+    Result* r = A.results + i;
+    if (over) {
+      if (threadIdx.x == 0) write_result(r, ST_INVALID_ARG, 0, 0);
+      continue;
+    }
+    const Launch L = item_launch(A, it, i);
+    const uint64_t err = ld_agent(L.err);
+    uint64_t written = 0;
+    if (!fault && err != NO_ERR)
+      written = it.dir == 0 ? prefix_words8<FIN_WG>(L, err, L.seg_units, lds)
+                            : prefix_bytes16<FIN_WG>(L, err, L.seg_units, lds);
+    if (threadIdx.x == 0) {
+      const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
+      if (fault) write_result(r, ST_DEVICE, 0, 0);
+      else if (err != NO_ERR)
+        write_result(r, it.dir == 0 ? utf8_kind_at(L.base + L.mis, L.n, err) : ST_SURROGATE, err, written);
+      else if (tot > L.cap) write_result(r, ST_OUTPUT_TOO_SMALL, tot, 0);
+      else write_result(r, ST_OK, tot, tot);
+    }
+  }
+}
+
+}  // namespace utfx_dev
+
+// ---------------------------------------------------------------- host side
 
 struct BatchWs {
   void* mem = nullptr;
+  utfx_dev::WsHeader* ws = nullptr;
+  unsigned long long* unit_start = nullptr;
+  unsigned long long* item_err = nullptr;
+  unsigned long long* status[2] = {nullptr, nullptr};
+  uint32_t* unit_item[2] = {nullptr, nullptr};
+  uint32_t* large = nullptr;
+  unsigned long long* plan_status[2] = {nullptr, nullptr};
+  uint64_t cap_items = 0, cap_units = 0;
+  uint64_t launches = 0;
 };
+
 inline hipError_t batch_ws_init(BatchWs&) { return hipSuccess; }
-inline void batch_ws_free(BatchWs&) {}
-inline utfx_status batch_run(BatchWs&, hipStream_t, int, uint32_t, uint32_t, const uint8_t*, uint8_t*,
-                             const utfx_item*, uint32_t, uint64_t, utfx_result*, char* err, size_t errlen) {
-  snprintf(err, errlen, "batched path not available in this build");
-  return UTFX_E_INVALID_ARG;
+
+inline void batch_ws_free(BatchWs& b) {
+  if (b.mem) (void)hipFree(b.mem);
+  b = BatchWs();
+}
+
+// Clears every status word and initialises the header.  Synchronous.
+inline hipError_t batch_ws_clear(BatchWs& b, hipStream_t s) {
+  const size_t plan_words = (b.cap_items + utfx_dev::PLAN_WG - 1) / utfx_dev::PLAN_WG;
+  hipError_t e = hipSuccess;
+  for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+    e = hipMemsetAsync(b.status[d], 0, b.cap_units * sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b.plan_status[d], 0, plan_words * sizeof(unsigned long long), s);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(utfx_dev::k_ws_init, dim3(1), dim3(64), 0, s, b.ws);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  b.launches = 0;
+  return e;
+}
+
+// Sizes the workspace for n_items items and cap_units segments per direction (grows
+// by doubling; synchronises the stream when it grows).
+inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, uint64_t cap_units) {
+  if (n_items <= b.cap_items && cap_units <= b.cap_units) {
+    if (b.launches >= (1ull << 24)) return batch_ws_clear(b, s);
+    return hipSuccess;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  uint64_t ni = b.cap_items ? b.cap_items : 1024, nu = b.cap_units ? b.cap_units : 4096;
+  while (ni < n_items) ni *= 2;
+  while (nu < cap_units) nu *= 2;
+  if (b.mem) (void)hipFree(b.mem);
+  b.mem = nullptr;
+  const uint64_t plan_words = (ni + utfx_dev::PLAN_WG - 1) / utfx_dev::PLAN_WG;
+  auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+  uint64_t o = al(sizeof(utfx_dev::WsHeader));
+  const uint64_t o_start = o; o += al(ni * 8);
+  const uint64_t o_err = o; o += al(ni * 8);
+  const uint64_t o_large = o; o += al(ni * 4);
+  uint64_t o_plan[2], o_status[2], o_uitem[2];
+  for (int d = 0; d < 2; ++d) {
+    o_plan[d] = o; o += al(plan_words * 8);
+    o_status[d] = o; o += al(nu * 8);
+    o_uitem[d] = o; o += al(nu * 4);
+  }
+  e = hipMalloc(&b.mem, o);
+  if (e != hipSuccess) {
+    b = BatchWs();
+    return e;
+  }
+  char* m = static_cast<char*>(b.mem);
+  b.ws = reinterpret_cast<utfx_dev::WsHeader*>(m);
+  b.unit_start = reinterpret_cast<unsigned long long*>(m + o_start);
+  b.item_err = reinterpret_cast<unsigned long long*>(m + o_err);
+  b.large = reinterpret_cast<uint32_t*>(m + o_large);
+  for (int d = 0; d < 2; ++d) {
+    b.plan_status[d] = reinterpret_cast<unsigned long long*>(m + o_plan[d]);
+    b.status[d] = reinterpret_cast<unsigned long long*>(m + o_status[d]);
+    b.unit_item[d] = reinterpret_cast<uint32_t*>(m + o_uitem[d]);
+  }
+  b.cap_items = ni;
+  b.cap_units = nu;
+  return batch_ws_clear(b, s);
+}
+
+inline utfx_status batch_run(BatchWs& b, hipStream_t s, int num_cus, uint32_t wgs_per_cu, const uint8_t* in,
+                             uint64_t in_bytes, uint8_t* out, uint64_t out_bytes, const utfx_item* d_items,
+                             uint32_t n_items, uint64_t total_in_units, utfx_result* d_results, char* err,
+                             size_t errlen) {
+  using namespace utfx_dev;
+  if (n_items == 0) return UTFX_OK;
+  if ((!in && in_bytes) || (!out && out_bytes) || !d_items || !d_results) {
+    snprintf(err, errlen, "null pointer");
+    return UTFX_E_INVALID_ARG;
+  }
+  // segments of large items per direction: an item of n > SMALL_MAX units has at most
+  // n / BSEG + 2, and there are at most total / SMALL_MAX such items
+  const uint64_t seg_min = BSEG16 < BSEG8 ? BSEG16 : BSEG8;
+  const uint64_t cap_units = total_in_units / seg_min + 2 * (total_in_units / SMALL_MAX) + 2;
+  hipError_t e = batch_ws_ensure(b, s, n_items, cap_units);
+  if (e != hipSuccess) {
+    snprintf(err, errlen, "batch workspace: %s", hipGetErrorString(e));
+    return UTFX_E_DEVICE;
+  }
+  BatchArgs A;
+  A.in = in;
+  A.out = out;
+  A.in_bytes = in_bytes;
+  A.out_bytes = out_bytes;
+  A.items = reinterpret_cast<const BItem*>(d_items);
+  A.results = reinterpret_cast<Result*>(d_results);
+  A.n_items = n_items;
+  A.ws = b.ws;
+  A.unit_start = b.unit_start;
+  A.item_err = b.item_err;
+  A.large = b.large;
+  for (int d = 0; d < 2; ++d) {
+    A.status[d] = b.status[d];
+    A.unit_item[d] = b.unit_item[d];
+    A.plan_status[d] = b.plan_status[d];
+  }
+  A.cap_units = cap_units;
+  A.total_in = total_in_units;
+  const uint32_t plan_blocks = (n_items + PLAN_WG - 1) / PLAN_WG;
+  const uint32_t small_blocks = (n_items + SMALL_WG / 64 - 1) / (SMALL_WG / 64);
+  const uint32_t large_blocks = (uint32_t)num_cus * (wgs_per_cu ? wgs_per_cu : 2);
+  const uint32_t fin_blocks = n_items < 1024 ? n_items : 1024;
+  hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ws);
+  hipLaunchKernelGGL(k_batch_plan, dim3(plan_blocks), dim3(PLAN_WG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_small, dim3(small_blocks), dim3(SMALL_WG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_large<0>, dim3(large_blocks), dim3(BWG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_large<1>, dim3(large_blocks), dim3(BWG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_fin, dim3(fin_blocks), dim3(FIN_WG), 0, s, A);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    snprintf(err, errlen, "batch launch: %s", hipGetErrorString(e));
+    return UTFX_E_DEVICE;
+  }
+  b.launches++;
+  return UTFX_OK;
 }

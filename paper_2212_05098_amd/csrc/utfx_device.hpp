@@ -47,7 +47,8 @@ struct Launch {
   uint64_t n;           // input units
   void* out;            // output (UTF-16 or UTF-8)
   uint64_t cap;         // output units
-  WsHeader* ws;
+  WsHeader* ws;                 // epoch and fault flag of the launch
+  unsigned long long* err;      // smallest error offset found (NO_ERR = none)
   unsigned long long* status;
   void* result;         // utfx_result* (device)
   uint64_t ntiles;      // workgroups = segments
@@ -73,6 +74,7 @@ enum : int32_t {
   ST_SURROGATE = 5,
   ST_BAD_BYTE = 6,
   ST_OUTPUT_TOO_SMALL = 16,
+  ST_INVALID_ARG = 17,
   ST_DEVICE = 18
 };
 

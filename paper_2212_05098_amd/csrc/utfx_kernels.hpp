@@ -37,6 +37,7 @@ __device__ __forceinline__ void load8(const Launch& L, uint64_t q0, uint32_t x[4
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
   } else {
     x[0] = x[1] = x[2] = x[3] = 0;
+    if (q0 + 16 <= lo || q0 >= hi) return;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       uint64_t q = q0 + i;
@@ -337,6 +338,7 @@ __device__ __forceinline__ void load16(const Launch& L, uint64_t q0, uint32_t x[
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
   } else {
     x[0] = x[1] = x[2] = x[3] = 0;
+    if (q0 + 8 <= lo || q0 >= hi) return;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       uint64_t q = q0 + i;
@@ -599,7 +601,7 @@ __global__ void __launch_bounds__(WG) k_validate8(Launch L) {
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
       const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
-      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = xn[k];
@@ -608,7 +610,7 @@ __global__ void __launch_bounds__(WG) k_validate8(Launch L) {
 
 __global__ void k_fin_validate8(Launch L) {
   if (threadIdx.x == 0) {
-    const uint64_t err = ld_agent(&L.ws->err);
+    const uint64_t err = ld_agent(L.err);
     if (ld_fault(L.ws)) write_result(L.result, ST_DEVICE, 0, 0);
     else if (err != NO_ERR) write_result(L.result, utf8_kind_at(L.base + L.mis, L.n, err), err, err);
     else write_result(L.result, ST_OK, L.n, L.n);
@@ -636,7 +638,7 @@ __global__ void __launch_bounds__(WG) k_validate16(Launch L) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
       const uint16_t* in = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
       const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
-      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = xn[k];
@@ -645,7 +647,7 @@ __global__ void __launch_bounds__(WG) k_validate16(Launch L) {
 
 __global__ void k_fin_validate16(Launch L) {
   if (threadIdx.x == 0) {
-    const uint64_t err = ld_agent(&L.ws->err);
+    const uint64_t err = ld_agent(L.err);
     if (ld_fault(L.ws)) write_result(L.result, ST_DEVICE, 0, 0);
     else if (err != NO_ERR) write_result(L.result, ST_SURROGATE, err, err);
     else write_result(L.result, ST_OK, L.n, L.n);

@@ -25,19 +25,19 @@ __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t first) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x138, 0xF, 0xF, false);
 }
 
-// Coalesced store of staged output: stage element s0 + l (0 <= l < total) goes to
-// out[base + l].  16-byte chunks aligned to the destination are gathered from the
-// stage with dword reads and a byte funnel shift; elements at or beyond cap are never
-// stored.  The stage must hold 16 readable bytes past s0 + total.
-template <int WG, typename U>
+// Coalesced store of staged output by threads tid = 0..nthr-1: stage element s0 + l
+// (0 <= l < total) goes to out[base + l].  16-byte chunks aligned to the destination
+// are gathered from the stage with dword reads and a byte funnel shift; elements at or
+// beyond cap are never stored.  The stage must hold 16 readable bytes past s0 + total.
+template <typename U>
 __device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t total, U* out, uint64_t base,
-                                           uint64_t cap) {
+                                           uint64_t cap, uint32_t tid, uint32_t nthr) {
   constexpr uint32_t PER = 16 / sizeof(U);
   const uint32_t d = (uint32_t)((((uintptr_t)out / sizeof(U)) + base) & (PER - 1));
   const uint32_t nch = (d + total + PER - 1) / PER;
   const int64_t g_first = (int64_t)base - (int64_t)d;
   const uint32_t* s32 = reinterpret_cast<const uint32_t*>(stage);
-  for (uint32_t k = threadIdx.x; k < nch; k += WG) {
+  for (uint32_t k = tid; k < nch; k += nthr) {
     const int64_t g0 = g_first + (int64_t)(k * PER);
     const uint32_t l0 = k * PER;  // chunk covers elements l0 - d .. l0 - d + PER - 1
     if (l0 >= d && l0 + PER <= d + total && g0 + (int64_t)PER <= (int64_t)cap) {
@@ -133,23 +133,99 @@ __device__ __forceinline__ uint32_t spill8(uint32_t Cp) {
   return __builtin_popcount(e & HI);
 }
 
+// One 16-byte chunk of UTF-8 -> UTF-16: classify, validate and decode it, and scatter
+// its words into the stage from slot `idx` on (formula offset minus spill, computed
+// inside).  x: the chunk; xp: the 4 bytes before it; off: the chunk's formula offset
+// relative to the stage's PAD slot.  Returns the slot after the chunk's last word (LIM
+// for a chunk that lies past the stage); *det reports a detected error nearby.
+template <uint32_t PAD, uint32_t LIM, uint32_t DUMP>
+__device__ __forceinline__ uint32_t chunk_u8_to_u16(const uint32_t x[4], uint32_t xp, bool full, uint64_t q0,
+                                                    uint64_t lo, uint64_t hi, uint32_t off, uint16_t* stage,
+                                                    uint32_t* first, uint32_t* det_out) {
+  Chunk8 ch;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ch.x[i] = x[i];
+  ch.xp = xp;
+  uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
+  if (!full) {
+    range_masks(q0, lo, hi, inE);
+    range_masks(q0, lo, hi + 1, inD);
+  }
+  const int cls = classify8(ch);
+  process8_any<true>(cls, full, ch, inE, inD, E, cnt, det, W);
+  uint32_t idx = PAD + off - spill8(ch.Cp);
+  *first = idx;
+  // Scatter.  In a chunk wholly inside the input, a non-emitting position writes a
+  // placeholder at the slot of the next emit, which that emit overwrites: inside a
+  // valid prefix at most two positions in a row do not emit, so only the last two
+  // positions can lack a later emit in the chunk, and those write only real words.
+  // Past the first error every slot is at or beyond the valid prefix's length, and a
+  // chunk whose slots would leave the stage is past it and writes to a dump area.
+  // Writes that must not land go to the dump slot, so the loop has no branches.
+  const bool fits = idx + 16 <= LIM;
+  uint16_t* pw = stage + (fits ? idx : DUMP);
+  uint16_t* const dump = stage + DUMP;
+  if (full) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = 4 * kk + i;
+        const uint32_t pair = W[2 * kk + (i >> 1)];
+        const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+        const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
+        *((e < 14 || bit) ? pw : dump) = word;
+        pw += bit;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t pair = W[2 * kk + (i >> 1)];
+        const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+        const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
+        *(bit ? pw : dump) = word;
+        pw += bit;
+      }
+    }
+  }
+  idx = fits ? (uint32_t)(pw - stage) : LIM;
+  *det_out = det;
+  return idx;
+}
+
+// LDS of one UTF-8 -> UTF-16 segment: the stage holds the segment's output words.
 template <int WG, int S>
-__global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
-  constexpr int NW = WG / 64;
+struct Seg8Smem {
+  static constexpr int NW = WG / 64;
+  static constexpr uint32_t SEGB = 16u * WG * S;
+  static constexpr uint32_t PAD = 16;             // stage slots below the segment's formula offset
+  static constexpr uint32_t LIM = PAD + SEGB;     // a valid chunk ends at or below this slot
+  static constexpr uint32_t DUMP = LIM + 16;      // 16 slots for writes that must not land
+  static constexpr uint32_t SSZ = DUMP + 16;
+  uint16_t stage[SSZ];
+  uint32_t wtot[NW * (S / 2)];
+  uint32_t halo[S * NW];
+  unsigned long long seg_base;
+  uint32_t bounds[2];
+};
+
+// One segment of a UTF-8 -> UTF-16LE transcode (segment `seg` of the buffer L).
+template <int WG, int S>
+__device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg8Smem<WG, S>& sm) {
+  typedef Seg8Smem<WG, S> M;
+  constexpr int NW = M::NW;
   constexpr uint32_t T = 16u * WG;
-  constexpr uint32_t SEGB = T * S;
-  constexpr uint32_t PAD = 16;            // stage slots below the segment's formula offset
-  constexpr uint32_t LIM = PAD + SEGB;    // a valid chunk ends at or below this slot
-  constexpr uint32_t DUMP = LIM + 16;     // 16 slots for writes that must not land
-  constexpr uint32_t SSZ = DUMP + 16;
-  __shared__ __attribute__((aligned(16))) uint16_t stage[SSZ];
-  __shared__ uint32_t wtot[NW * (S / 2)];
-  __shared__ uint32_t halo[S * NW];
-  __shared__ unsigned long long seg_base;
-  __shared__ uint32_t bounds[2];
+  constexpr uint32_t SEGB = M::SEGB;
+  constexpr uint32_t PAD = M::PAD, LIM = M::LIM, DUMP = M::DUMP;
+  uint16_t* const stage = sm.stage;
+  uint32_t* const wtot = sm.wtot;
+  uint32_t* const halo = sm.halo;
+  uint32_t* const bounds = sm.bounds;
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint64_t seg = blockIdx.x;
   const uint32_t epoch = cur_epoch(L.ws);
   const uint64_t s0 = seg * SEGB;
   const uint64_t q00 = s0 + 16ull * threadIdx.x;
@@ -195,68 +271,22 @@ __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
   for (int k = 0; k < S; ++k) {
     const uint64_t q0 = q00 + (uint64_t)k * T;
     const uint32_t hl = (wid > 0) ? halo[k * NW + wid - 1] : (k > 0 ? halo[(k - 1) * NW + NW - 1] : xp_seg);
-    Chunk8 ch;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ch.x[i] = x[k][i];
-    ch.xp = wave_shr1(x[k][3], hl);
-    uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
+    uint32_t first, det;
     const bool full = segfull || (q0 >= lo && q0 + 16 <= hi);
-    if (!full) {
-      range_masks(q0, lo, hi, inE);
-      range_masks(q0, lo, hi + 1, inD);
-    }
-    const int cls = classify8(ch);
-    process8_any<true>(cls, full, ch, inE, inD, E, cnt, det, W);
-    uint32_t idx = PAD + off[k] - spill8(ch.Cp);
-    if (k == 0 && threadIdx.x == 0) bounds[0] = idx;
-    // Scatter.  In a chunk wholly inside the input, a non-emitting position writes a
-    // placeholder at the slot of the next emit, which that emit overwrites: inside a
-    // valid prefix at most two positions in a row do not emit, so only the last two
-    // positions can lack a later emit in the chunk, and those write only real words.
-    // Past the first error every slot is at or beyond the valid prefix's length, and a
-    // chunk whose slots would leave the stage is past it and writes to a dump area.
-    // Writes that must not land go to the dump slot, so the loop has no branches.
-    const bool fits = idx + 16 <= LIM;
-    uint16_t* pw = stage + (fits ? idx : DUMP);
-    uint16_t* const dump = stage + DUMP;
-    if (full) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int e = 4 * kk + i;
-          const uint32_t pair = W[2 * kk + (i >> 1)];
-          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
-          const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
-          *((e < 14 || bit) ? pw : dump) = word;
-          pw += bit;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t pair = W[2 * kk + (i >> 1)];
-          const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
-          const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
-          *(bit ? pw : dump) = word;
-          pw += bit;
-        }
-      }
-    }
-    idx = fits ? (uint32_t)(pw - stage) : LIM;
+    const uint32_t idx = chunk_u8_to_u16<PAD, LIM, DUMP>(x[k], wave_shr1(x[k][3], hl), full, q0, lo, hi, off[k],
+                                                         stage, &first, &det);
+    if (k == 0 && threadIdx.x == 0) bounds[0] = first;
     if (k == S - 1 && threadIdx.x == WG - 1) bounds[1] = idx;
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
       const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
-      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
     }
   }
   if (wid == 0) {
     // the look-back runs after the wave's own work, when predecessors are likely done
     const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
-    if (lane == 0) seg_base = b;
+    if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
 
@@ -264,8 +294,15 @@ __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
   const uint32_t st0 = bounds[0];
   uint32_t st1 = bounds[1];
   st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
-  const int64_t g = (int64_t)seg_base + (int64_t)st0 - (int64_t)PAD;
-  store_span<WG, uint16_t>(stage, st0, st1 - st0, reinterpret_cast<uint16_t*>(L.out), (uint64_t)g, L.cap);
+  const int64_t g = (int64_t)sm.seg_base + (int64_t)st0 - (int64_t)PAD;
+  store_span<uint16_t>(stage, st0, st1 - st0, reinterpret_cast<uint16_t*>(L.out), (uint64_t)g, L.cap,
+                       threadIdx.x, WG);
+}
+
+template <int WG, int S>
+__global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
+  __shared__ __attribute__((aligned(16))) Seg8Smem<WG, S> sm;
+  seg_u8_to_u16<WG, S>(L, blockIdx.x, sm);
 }
 
 // Words of the valid prefix in[0:off]: the exclusive prefix of off's segment plus the
@@ -294,7 +331,7 @@ __device__ uint64_t prefix_words8(const Launch& L, uint64_t off, uint64_t seg_un
 template <int WG>
 __global__ void __launch_bounds__(WG) k_fin_u8u16(Launch L) {
   __shared__ unsigned long long lds[WG / 64 + 2];
-  const uint64_t err = ld_agent(&L.ws->err);
+  const uint64_t err = ld_agent(L.err);
   const bool fault = ld_fault(L.ws) != 0;
   uint64_t written = 0;
   if (!fault && err != NO_ERR) written = prefix_words8<WG>(L, err, L.seg_units, lds);
@@ -389,21 +426,93 @@ __device__ __forceinline__ void put3(uint8_t* p, uint32_t v, uint32_t c, bool ow
   *((!own_only || c >= 3) ? p + 2 : dump) = (uint8_t)(v >> 16);
 }
 
+// One chunk of 8 words of UTF-16 -> UTF-8: validate, encode and scatter its bytes
+// to st (the chunk's first output byte).  xprev: the dword before the chunk (its
+// high half is the word before).  Returns whether an error was detected nearby.
+__device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xprev, bool full, uint64_t q0,
+                                                uint64_t lo, uint64_t hi, uint8_t* st, uint8_t* dump) {
+  const uint32_t wp = xprev >> 16;
+  bool det = false;
+  if (!__any(!full || any_surrogate(x, wp))) {
+    // no surrogate anywhere in the wave's chunks: lengths 1..3, nothing to validate.
+    // Each word writes three bytes at its offset; the spare ones are overwritten by
+    // the following words (each adds at least one byte), except for the last two
+    // words of the chunk, which write only their own bytes.
+    uint32_t o = 0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const uint32_t l = pk_len16(x[kk]);
+      const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
+      uint32_t vl, vh;
+      pk_enc16(x[kk], cl, chh, vl, vh);
+      put3(st + o, vl, cl, kk == 3, dump);
+      o += cl;
+      put3(st + o, vh, chh, kk == 3, dump);
+      o += chh;
+    }
+  } else if (full) {
+    uint32_t o = 0, d = 0, prevd = xprev;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const uint32_t X = x[kk];
+      const uint32_t P = abyte(X, prevd, 2);  // each word's predecessor
+      d |= pk_pair_err(X, P);
+      const uint32_t l = pk_len16s(X);
+      const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
+      uint32_t vl, vh;
+      pk_enc16s(X, P, cl, chh, vl, vh);
+      put3(st + o, vl, cl, kk == 3, dump);
+      o += cl;
+      put3(st + o, vh, chh, kk == 3, dump);
+      o += chh;
+      prevd = X;
+    }
+    det = d != 0;
+  } else {
+    // chunk straddling the start or end of the input: word by word, real bytes only
+    uint32_t len[8], cnt;
+    analyze16<false>(x, wp, q0, lo, hi, len, cnt, det);
+    uint32_t o = 0, prev = wp;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+      const uint32_t cj = len[j];
+      const uint32_t v = enc16<true>(w, prev, cj);
+      put3(st + o, v, cj, true, dump);
+      o += cj;
+      prev = w;
+    }
+  }
+  return det;
+}
+
+// LDS of one UTF-16 -> UTF-8 segment: the stage holds the segment's output bytes.
 template <int WG, int S>
-__global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
-  constexpr int NW = WG / 64;
+struct Seg16Smem {
+  static constexpr int NW = WG / 64;
+  static constexpr uint32_t SEGW = 8u * WG * S;
+  static constexpr uint32_t PAD = 16;
+  static constexpr uint32_t DUMP = PAD + 3 * SEGW + 32;  // slot for writes that must not land
+  static constexpr uint32_t SSZ = DUMP + 16;
+  uint8_t stage[SSZ];
+  uint32_t wtot[NW * (S / 2)];
+  uint32_t halo[S * NW];
+  unsigned long long seg_base;
+};
+
+// One segment of a UTF-16LE -> UTF-8 transcode.
+template <int WG, int S>
+__device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg16Smem<WG, S>& sm) {
+  typedef Seg16Smem<WG, S> M;
+  constexpr int NW = M::NW;
   constexpr uint32_t TW = 8u * WG;      // words per tile
-  constexpr uint32_t SEGW = TW * S;
-  constexpr uint32_t PAD = 16;
-  constexpr uint32_t DUMP = PAD + 3 * SEGW + 32;  // slot for writes that must not land
-  constexpr uint32_t SSZ = DUMP + 16;
-  __shared__ __attribute__((aligned(16))) uint8_t stage[SSZ];
-  __shared__ uint32_t wtot[NW * (S / 2)];
-  __shared__ uint32_t halo[S * NW];
-  __shared__ unsigned long long seg_base;
+  constexpr uint32_t SEGW = M::SEGW;
+  constexpr uint32_t PAD = M::PAD, DUMP = M::DUMP;
+  uint8_t* const stage = sm.stage;
+  uint32_t* const wtot = sm.wtot;
+  uint32_t* const halo = sm.halo;
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint64_t seg = blockIdx.x;
   const uint32_t epoch = cur_epoch(L.ws);
   const uint64_t s0 = seg * SEGW;
   const uint64_t q00 = s0 + 8ull * threadIdx.x;
@@ -446,75 +555,29 @@ __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
     const uint64_t q0 = q00 + (uint64_t)k * TW;
     const uint32_t hl = (wid > 0) ? halo[k * NW + wid - 1] : (k > 0 ? halo[(k - 1) * NW + NW - 1] : xp_seg);
     const uint32_t xprev = wave_shr1(x[k][3], hl);  // high half: the word before the chunk
-    const uint32_t wp = xprev >> 16;
     const bool full = segfull || (q0 >= lo && q0 + 8 <= hi);
-    uint8_t* st = stage + PAD + off[k];
-    uint8_t* const dump = stage + DUMP;
-    bool det = false;
-    if (!__any(!full || any_surrogate(x[k], wp))) {
-      // no surrogate anywhere in the wave's chunks: lengths 1..3, nothing to validate.
-      // Each word writes three bytes at its offset; the spare ones are overwritten by
-      // the following words (each adds at least one byte), except for the last two
-      // words of the chunk, which write only their own bytes.
-      uint32_t o = 0;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const uint32_t l = pk_len16(x[k][kk]);
-        const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
-        uint32_t vl, vh;
-        pk_enc16(x[k][kk], cl, chh, vl, vh);
-        put3(st + o, vl, cl, kk == 3, dump);
-        o += cl;
-        put3(st + o, vh, chh, kk == 3, dump);
-        o += chh;
-      }
-    } else if (full) {
-      uint32_t o = 0, d = 0, prevd = xprev;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const uint32_t X = x[k][kk];
-        const uint32_t P = abyte(X, prevd, 2);  // each word's predecessor
-        d |= pk_pair_err(X, P);
-        const uint32_t l = pk_len16s(X);
-        const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
-        uint32_t vl, vh;
-        pk_enc16s(X, P, cl, chh, vl, vh);
-        put3(st + o, vl, cl, kk == 3, dump);
-        o += cl;
-        put3(st + o, vh, chh, kk == 3, dump);
-        o += chh;
-        prevd = X;
-      }
-      det = d != 0;
-    } else {
-      // chunk straddling the start or end of the input: word by word, real bytes only
-      uint32_t len[8], cnt;
-      analyze16<false>(x[k], wp, q0, lo, hi, len, cnt, det);
-      uint32_t o = 0, prev = wp;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t w = (x[k][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-        const uint32_t cj = len[j];
-        const uint32_t v = enc16<true>(w, prev, cj);
-        put3(st + o, v, cj, true, dump);
-        o += cj;
-        prev = w;
-      }
-    }
+    const bool det = chunk_u16_to_u8(x[k], xprev, full, q0, lo, hi, stage + PAD + off[k], stage + DUMP);
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
       const uint16_t* in = in16 + L.mis;
       const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
-      if (e != NO_ERR) atomicMin(&L.ws->err, (unsigned long long)e);
+      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
     }
   }
   if (wid == 0) {
     // the look-back runs after the wave's own work, when predecessors are likely done
     const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
-    if (lane == 0) seg_base = b;
+    if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
-  store_span<WG, uint8_t>(stage, PAD, seg_total, reinterpret_cast<uint8_t*>(L.out), seg_base, L.cap);
+  store_span<uint8_t>(stage, PAD, seg_total, reinterpret_cast<uint8_t*>(L.out), sm.seg_base, L.cap, threadIdx.x,
+                      WG);
+}
+
+template <int WG, int S>
+__global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
+  __shared__ __attribute__((aligned(16))) Seg16Smem<WG, S> sm;
+  seg_u16_to_u8<WG, S>(L, blockIdx.x, sm);
 }
 
 template <int WG>
@@ -537,7 +600,7 @@ __device__ uint64_t prefix_bytes16(const Launch& L, uint64_t off, uint64_t seg_u
 template <int WG>
 __global__ void __launch_bounds__(WG) k_fin_u16u8(Launch L) {
   __shared__ unsigned long long lds[WG / 64 + 2];
-  const uint64_t err = ld_agent(&L.ws->err);
+  const uint64_t err = ld_agent(L.err);
   const bool fault = ld_fault(L.ws) != 0;
   uint64_t written = 0;
   if (!fault && err != NO_ERR) written = prefix_bytes16<WG>(L, err, L.seg_units, lds);
