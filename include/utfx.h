@@ -191,6 +191,23 @@ utfx_status utfx_batch_run(utfx_ctx *ctx, const uint8_t *in_arena, size_t in_byt
                            size_t out_bytes, const utfx_item *d_items, uint32_t n_items,
                            uint64_t total_in_units, utfx_result *d_results);
 
+/* ---- HIP graphs: record a sequence of calls once, replay it many times ---------- */
+/* Between utfx_capture_begin and utfx_capture_end, the context's _async calls and
+ * utfx_batch_run are recorded into a HIP graph instead of being run (on a private
+ * capture stream).  Every kernel takes its description from its arguments and from
+ * device memory, and no call records a memset, so a replay runs the same calls on the
+ * buffers' contents at replay time: refill inputs or item tables between replays,
+ * keep sizes and pointers.  Calls that would allocate or synchronise are refused
+ * while capturing (UTFX_E_INVALID_ARG): synchronous calls, and calls whose workspace
+ * would have to grow -- make each call once eagerly first.  Launch a graph on any
+ * stream; replays of graphs made on one context must not overlap in time.  One graph
+ * per capture; utfx_graph_destroy frees it (the context must outlive its graphs). */
+typedef struct utfx_graph utfx_graph;
+utfx_status utfx_capture_begin(utfx_ctx *ctx);
+utfx_status utfx_capture_end(utfx_ctx *ctx, utfx_graph **graph);
+utfx_status utfx_graph_launch(utfx_graph *graph, void *hip_stream);
+void utfx_graph_destroy(utfx_graph *graph);
+
 #ifdef __cplusplus
 }
 #endif

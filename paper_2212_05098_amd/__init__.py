@@ -107,6 +107,10 @@ def lib() -> ctypes.CDLL:
         "utfx_utf8_to_utf16le_async": (I, [P, P, Z, P, Z, P]),
         "utfx_utf16le_to_utf8_async": (I, [P, P, Z, P, Z, P]),
         "utfx_batch_run": (I, [P, P, Z, P, Z, P, U32, U64, P]),
+        "utfx_capture_begin": (I, [P]),
+        "utfx_capture_end": (I, [P, ctypes.POINTER(P)]),
+        "utfx_graph_launch": (I, [P, P]),
+        "utfx_graph_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -264,6 +268,47 @@ class Context:
                 d_results.data_ptr(),
             )
         )
+
+
+    # ---- HIP graphs
+    def capture_begin(self):
+        st = self._lib.utfx_capture_begin(self._h)
+        if st != OK:
+            raise UtfxError("capture_begin: %d %s" % (st, self.last_error()))
+
+    def capture_end(self) -> "Graph":
+        g = ctypes.c_void_p()
+        st = self._lib.utfx_capture_end(self._h, ctypes.byref(g))
+        if st != OK:
+            raise UtfxError("capture_end: %d %s" % (st, self.last_error()))
+        return Graph(self, g)
+
+
+class Graph:
+    """A recorded sequence of calls on a Context (utfx_capture_begin / _end)."""
+
+    def __init__(self, ctx: "Context", handle):
+        self._ctx = ctx
+        self._h = handle
+
+    def launch(self, stream=None):
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream()
+        st = self._ctx._lib.utfx_graph_launch(self._h, ctypes.c_void_p(s.cuda_stream))
+        if st != OK:
+            raise UtfxError("graph launch: %d %s" % (st, self._ctx.last_error()))
+
+    def close(self):
+        if self._h:
+            self._ctx._lib.utfx_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # numpy layout of utfx_item (include/utfx.h)

@@ -38,7 +38,21 @@ struct utfx_ctx {
   uint32_t seg_tiles[UTFX_OP_COUNT_];
   uint32_t wgs_per_cu[UTFX_OP_COUNT_];
   BatchWs batch;                          // batched-path workspace
+  // graph capture: while capturing, calls are recorded on cap_stream
+  bool capturing = false;
+  hipStream_t user_stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  uint64_t cap_launches = 0;              // single-buffer launches recorded so far
+  uint64_t cap_batches = 0;               // batched calls recorded so far
   char err[256];
+};
+
+struct utfx_graph {
+  utfx_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t launches = 0;                  // single-buffer launches per replay
+  uint64_t batches = 0;                   // batched calls per replay
 };
 
 namespace {
@@ -97,6 +111,10 @@ utfx_status alloc_ws(utfx_ctx* c, uint64_t tiles) {
 // Makes room for `tiles` status words.  Growing synchronises the stream once; a
 // workload of a fixed size never grows again.
 utfx_status ensure_tiles(utfx_ctx* c, uint64_t tiles) {
+  if (c->capturing && (c->launches >= kEpochClearEvery || tiles > c->cap_tiles)) {
+    set_msg(c, "workspace must grow during graph capture; make the same call once before capturing");
+    return UTFX_E_INVALID_ARG;
+  }
   if (c->launches >= kEpochClearEvery) {
     utfx_status s = init_ws(c);
     if (s != UTFX_OK) return s;
@@ -313,11 +331,16 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
     return UTFX_E_DEVICE;
   }
   c->launches++;
+  if (c->capturing) c->cap_launches++;
   return UTFX_OK;
 }
 
 utfx_result run_sync(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, uint64_t cap) {
   if (!c) return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  if (c->capturing) {
+    set_msg(c, "synchronous call during graph capture");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
   utfx_status s = run(c, kind, in, n, out, cap, c->d_result);
   if (s != UTFX_OK) return mkres(s, 0, 0);
   hipError_t e = hipMemcpyAsync(c->h_result, c->d_result, sizeof(Result), hipMemcpyDeviceToHost, c->stream);
@@ -460,8 +483,96 @@ utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes
                            utfx_result* d_results) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
-  return batch_run(c->batch, c->stream, c->num_cus, c->wgs_per_cu[UTFX_OP_BATCH], in_arena, in_bytes, out_arena,
-                   out_bytes, d_items, n_items, total_in_units, d_results, c->err, sizeof(c->err));
+  utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, c->wgs_per_cu[UTFX_OP_BATCH], in_arena,
+                             in_bytes, out_arena, out_bytes, d_items, n_items, total_in_units, d_results, c->err,
+                             sizeof(c->err));
+  if (st == UTFX_OK && c->capturing) c->cap_batches++;
+  return st;
+}
+
+utfx_status utfx_capture_begin(utfx_ctx* c) {
+  if (!c || c->capturing) return UTFX_E_INVALID_ARG;
+  c->err[0] = 0;
+  hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    set_err(c, "begin capture", e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
+    return UTFX_E_DEVICE;
+  }
+  c->user_stream = c->stream;
+  c->stream = c->cap_stream;
+  c->capturing = true;
+  c->cap_launches = 0;
+  c->cap_batches = 0;
+  return UTFX_OK;
+}
+
+utfx_status utfx_capture_end(utfx_ctx* c, utfx_graph** out) {
+  if (!c || !c->capturing || !out) return UTFX_E_INVALID_ARG;
+  *out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  c->stream = c->user_stream;
+  c->capturing = false;
+  (void)hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
+  if (e != hipSuccess || !graph) {
+    set_err(c, "end capture", e);
+    return UTFX_E_DEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    set_err(c, "instantiate graph", e);
+    (void)hipGraphDestroy(graph);
+    return UTFX_E_DEVICE;
+  }
+  utfx_graph* g = new (std::nothrow) utfx_graph();
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return UTFX_E_DEVICE;
+  }
+  g->ctx = c;
+  g->graph = graph;
+  g->exec = exec;
+  g->launches = c->cap_launches;
+  g->batches = c->cap_batches;
+  *out = g;
+  return UTFX_OK;
+}
+
+utfx_status utfx_graph_launch(utfx_graph* g, void* hip_stream) {
+  if (!g || g->ctx->capturing) return UTFX_E_INVALID_ARG;
+  utfx_ctx* c = g->ctx;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  // replays advance the workspace epochs like eager calls; clear the status words
+  // before the epoch space could wrap
+  if (c->launches + g->launches >= kEpochClearEvery) {
+    (void)hipStreamSynchronize(s);
+    if (init_ws(c) != UTFX_OK) return UTFX_E_DEVICE;
+  }
+  if (c->batch.launches + g->batches >= (1ull << 24)) {
+    (void)hipStreamSynchronize(s);
+    if (batch_ws_clear(c->batch, c->stream) != hipSuccess) return UTFX_E_DEVICE;
+  }
+  hipError_t e = hipGraphLaunch(g->exec, s);
+  if (e != hipSuccess) {
+    set_err(c, "graph launch", e);
+    return UTFX_E_DEVICE;
+  }
+  c->launches += g->launches;
+  c->batch.launches += g->batches;
+  return UTFX_OK;
+}
+
+void utfx_graph_destroy(utfx_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 }  // extern "C"

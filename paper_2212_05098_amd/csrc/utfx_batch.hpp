@@ -486,7 +486,8 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   return batch_ws_clear(b, s);
 }
 
-inline utfx_status batch_run(BatchWs& b, hipStream_t s, int num_cus, uint32_t wgs_per_cu, const uint8_t* in,
+inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_cus, uint32_t wgs_per_cu,
+                             const uint8_t* in,
                              uint64_t in_bytes, uint8_t* out, uint64_t out_bytes, const utfx_item* d_items,
                              uint32_t n_items, uint64_t total_in_units, utfx_result* d_results, char* err,
                              size_t errlen) {
@@ -500,6 +501,10 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, int num_cus, uint32_t wg
   // n / BSEG + 2, and there are at most total / SMALL_MAX such items
   const uint64_t seg_min = BSEG16 < BSEG8 ? BSEG16 : BSEG8;
   const uint64_t cap_units = total_in_units / seg_min + 2 * (total_in_units / SMALL_MAX) + 2;
+  if (capturing && (n_items > b.cap_items || cap_units > b.cap_units || b.launches >= (1ull << 24))) {
+    snprintf(err, errlen, "batch workspace must grow during graph capture; make the same call once before capturing");
+    return UTFX_E_INVALID_ARG;
+  }
   hipError_t e = batch_ws_ensure(b, s, n_items, cap_units);
   if (e != hipSuccess) {
     snprintf(err, errlen, "batch workspace: %s", hipGetErrorString(e));

@@ -1,0 +1,151 @@
+"""HIP graph capture and replay: a recorded single-buffer transcode and a recorded
+batched call are replayed several times with new input contents, with eager work and
+synchronisations between replays; every replay must match the oracle exactly."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2212_05098_amd as utfx
+from paper_2212_05098_amd import synth
+from gpu_helpers import note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    c = utfx.Context()
+    yield c
+    c.close()
+
+
+def test_graph_single_buffer_replays(ctx):
+    import torch
+
+    n = 200_000
+    src = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(n, dtype=torch.int16, device="cuda")
+    src16 = torch.zeros(n // 2, dtype=torch.int16, device="cuda")
+    dst8 = torch.zeros(3 * (n // 2), dtype=torch.uint8, device="cuda")
+    res = utfx.result_tensor(2)
+    # eager calls size the workspaces
+    assert ctx.utf8_to_utf16le_async(src, dst, res[:24]) == utfx.OK
+    assert ctx.utf16le_to_utf8_async(src16, dst8, res[24:]) == utfx.OK
+    torch.cuda.synchronize()
+    ctx.capture_begin()
+    try:
+        assert ctx.utf8_to_utf16le_async(src, dst, res[:24]) == utfx.OK
+        assert ctx.utf16le_to_utf8_async(src16, dst8, res[24:]) == utfx.OK
+        # synchronous calls are refused while capturing
+        assert ctx.utf8_to_utf16le(src, dst).status == utfx.E_INVALID_ARG
+    finally:
+        g = ctx.capture_end()
+    for rep, (prof, err) in enumerate((("cjk", False), ("emoji", True), ("latin", False), ("mixed4", True))):
+        rng = synth.rng_for(21, rep)
+        d8 = synth.utf8_buffer(prof, n, rng)
+        w16 = synth.utf16_buffer(prof, n // 2, rng)
+        if err:
+            d8[n // 3] = 0xFF
+            w16[n // 5] = 0xDC00
+        src.copy_(torch.from_numpy(d8))
+        src16.copy_(torch.from_numpy(w16.view(np.int16)))
+        torch.cuda.synchronize()
+        note("graph replay %d" % rep)
+        g.launch()
+        torch.cuda.synchronize()
+        r8, r16 = utfx.results_from_tensor(res)
+        want8, ref8 = O.utf8_to_utf16le(d8, cap=n)
+        want16, ref16 = O.utf16le_to_utf8(w16, cap=3 * (n // 2))
+        assert tuple(r8) == tuple(want8), (rep, r8, want8)
+        assert tuple(r16) == tuple(want16), (rep, r16, want16)
+        assert np.array_equal(dst.cpu().numpy().view(np.uint16)[:want8.written], ref8[:want8.written])
+        assert np.array_equal(dst8.cpu().numpy()[:want16.written], ref16[:want16.written])
+        # eager work on the same context between replays
+        r = ctx.validate_utf8(src)
+        assert tuple(r) == tuple(O.validate_utf8(d8))
+    g.close()
+
+
+def test_graph_batch_replays(ctx):
+    import torch
+
+    n_items = 600
+    batches = [synth.make_batch(n_items, seed_key=(22, k), median=1024, sigma=1.8, hi=96 << 10, err_frac=0.05)
+               for k in range(3)]
+    arena_bytes = max(b.arena.size for b in batches)
+    total = max(int(np.sum(b.in_len)) for b in batches)
+    out_bytes = 0
+    layouts = []
+    for b in batches:
+        caps = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
+        sizes = np.where(b.direction == 0, 2 * caps, caps)
+        out_off = np.concatenate([[0], np.cumsum(sizes + 16)[:-1]]).astype(np.uint64)
+        out_off += out_off % 2
+        layouts.append((caps, out_off))
+        out_bytes = max(out_bytes, int(out_off[-1] + sizes[-1] + 64))
+    d_in = torch.zeros(arena_bytes, dtype=torch.uint8, device="cuda")
+    d_out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    items = torch.zeros(n_items * 40, dtype=torch.uint8, device="cuda")
+    res = utfx.result_tensor(n_items)
+    # eager call sizes the workspace, then capture the same call
+    assert ctx.batch_run(d_in, d_out, items, n_items, total, res) == utfx.OK
+    torch.cuda.synchronize()
+    ctx.capture_begin()
+    try:
+        assert ctx.batch_run(d_in, d_out, items, n_items, total, res) == utfx.OK
+    finally:
+        g = ctx.capture_end()
+    for rep in range(6):
+        b = batches[rep % 3]
+        caps, out_off = layouts[rep % 3]
+        d_in.zero_()
+        d_in[: b.arena.size].copy_(torch.from_numpy(b.arena))
+        items.copy_(utfx.pack_items(b.in_off, b.in_len, out_off, caps, b.direction))
+        torch.cuda.synchronize()
+        note("batch graph replay %d" % rep)
+        g.launch()
+        torch.cuda.synchronize()
+        got = utfx.results_from_tensor(res)
+        out = d_out.cpu().numpy()
+        for i in range(n_items):
+            a, L, cap, o = int(b.in_off[i]), int(b.in_len[i]), int(caps[i]), int(out_off[i])
+            if b.direction[i] == 0:
+                want, ref = O.utf8_to_utf16le(b.arena[a:a + L], cap=cap)
+                gw = out[o:o + 2 * want.written].view(np.uint16)
+            else:
+                want, ref = O.utf16le_to_utf8(b.arena[a:a + 2 * L].view(np.uint16), cap=cap)
+                gw = out[o:o + want.written]
+            assert tuple(got[i]) == tuple(want), (rep, i, got[i], want)
+            assert np.array_equal(gw, ref[:want.written]), (rep, i)
+        # eager batched call between replays
+        assert ctx.batch_run(d_in, d_out, items, n_items, total, res) == utfx.OK
+        torch.cuda.synchronize()
+        assert utfx.results_from_tensor(res) == got
+    g.close()
+
+
+def test_capture_refuses_growth(ctx):
+    """A call whose workspace would have to grow is refused while capturing (a fresh
+    context has no batch workspace yet)."""
+    import torch
+
+    d_in = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    d_out = torch.zeros(8192, dtype=torch.uint8, device="cuda")
+    items = utfx.pack_items([0] * 4, [1000] * 4, [0, 2048, 4096, 6144], [1000] * 4, [0] * 4)
+    res = utfx.result_tensor(4)
+    fresh = utfx.Context()
+    try:
+        fresh.capture_begin()
+        st = fresh.batch_run(d_in, d_out, items, 4, 4000, res)
+        g = fresh.capture_end()
+        g.close()
+        assert st == utfx.E_INVALID_ARG
+        # outside capture the same call runs
+        assert fresh.batch_run(d_in, d_out, items, 4, 4000, res) == utfx.OK
+        torch.cuda.synchronize()
+        assert all(r.status == utfx.OK and r.count == 1000 for r in utfx.results_from_tensor(res))
+    finally:
+        fresh.close()
