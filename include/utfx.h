@@ -208,6 +208,51 @@ utfx_status utfx_capture_end(utfx_ctx *ctx, utfx_graph **graph);
 utfx_status utfx_graph_launch(utfx_graph *graph, void *hip_stream);
 void utfx_graph_destroy(utfx_graph *graph);
 
+/* ---- serving: continuous batching of host requests ------------------------------ */
+/* A server owns `inflight` slots, each with its own HIP stream, context, device
+ * arenas and pinned host staging.  Submitted requests (host payloads) wait in a
+ * queue.  Whenever a slot is free, utfx_server_progress packs every queued request
+ * that fits the slot's arenas and item count (admission by free arena bytes, in
+ * arrival order) into one step: host-to-device copy, one utfx_batch_run, device-to-
+ * host copy of results and outputs.  Requests arriving meanwhile join the next step
+ * (continuous batching); with inflight >= 2, steps overlap.  When a step completes,
+ * each request's output (its valid prefix, `written` units) is copied to its `out`
+ * buffer and a completion {tag, result} is reported.  A request larger than an arena
+ * completes with UTFX_E_INVALID_ARG.  Payloads and outputs must stay valid until the
+ * request completes.  Single-threaded: one thread drives a server. */
+typedef struct utfx_server utfx_server;
+typedef struct {
+  uint64_t arena_in_bytes;   /* input arena bytes per slot */
+  uint64_t arena_out_bytes;  /* output arena bytes per slot */
+  uint64_t device_cap_bytes; /* limit on inflight * (in + out) device bytes; 0 = none */
+  uint32_t max_items;        /* requests per step (1 = one launch per request) */
+  uint32_t inflight;         /* slots, 1..16 */
+} utfx_server_config;
+typedef struct {
+  uint64_t tag;
+  utfx_result result;
+} utfx_completion;
+utfx_status utfx_server_create(utfx_server **srv, const utfx_server_config *cfg);
+void utfx_server_destroy(utfx_server *srv);
+const char *utfx_server_last_error(const utfx_server *srv);
+/* Queues one request: len_units input units at host address data, direction dir
+ * (0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8), output to host address out with room
+ * for out_cap_units output units. */
+utfx_status utfx_server_submit(utfx_server *srv, uint64_t tag, const void *data, uint64_t len_units,
+                               uint32_t dir, void *out, uint64_t out_cap_units);
+/* Reports up to max_done completions (drains a slot only when all its requests fit)
+ * and launches steps on free slots.  Never blocks. */
+utfx_status utfx_server_progress(utfx_server *srv, utfx_completion *done, uint32_t max_done,
+                                 uint32_t *n_done);
+/* Replays an arrival trace in real time: request i (tag i) is submitted once
+ * arrival_ns[i] (ascending, from the call's start) has passed, and progress runs
+ * continuously until all n complete.  latency_ns[i] = completion - arrival (result and
+ * output on the host); results[i] its result; *wall_ns the replay's duration. */
+utfx_status utfx_server_replay(utfx_server *srv, uint32_t n, const uint64_t *arrival_ns,
+                               const void *const *data, const uint64_t *len_units, const uint32_t *dirs,
+                               void *const *outs, const uint64_t *out_caps, uint64_t *latency_ns,
+                               utfx_result *results, uint64_t *wall_ns);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,10 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIBRARY):
         raise UtfxError("libutfx.so is not built (run __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname as the system one; load it
+    # first so that the library and torch share one runtime in the process
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIBRARY)
     P = ctypes.c_void_p
     Z = ctypes.c_size_t
@@ -111,6 +115,12 @@ def lib() -> ctypes.CDLL:
         "utfx_capture_end": (I, [P, ctypes.POINTER(P)]),
         "utfx_graph_launch": (I, [P, P]),
         "utfx_graph_destroy": (None, [P]),
+        "utfx_server_create": (I, [ctypes.POINTER(P), P]),
+        "utfx_server_destroy": (None, [P]),
+        "utfx_server_last_error": (ctypes.c_char_p, [P]),
+        "utfx_server_submit": (I, [P, U64, P, U64, U32, P, U64]),
+        "utfx_server_progress": (I, [P, P, U32, ctypes.POINTER(U32)]),
+        "utfx_server_replay": (I, [P, U32, P, P, P, P, P, P, P, P, ctypes.POINTER(U64)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -184,6 +194,18 @@ class Context:
         st = self._lib.utfx_set_tuning(self._h, op, tile_bytes, tiles_per_segment, wgs_per_cu)
         if st != OK:
             raise UtfxError("bad tuning %r" % ((op, tile_bytes, tiles_per_segment, wgs_per_cu),))
+
+    def load_tuning(self, path=None) -> bool:
+        """Apply a tuning cache written by paper_2212_05098_amd.tune (default: the
+        package's tune_cache.json).  Returns False if there is none."""
+        from paper_2212_05098_amd import tune
+
+        cache = tune.load(path or tune.DEFAULT_CACHE)
+        if not cache:
+            return False
+        for op, (tile, seg, wgs) in cache["ops"].items():
+            self.set_tuning(int(op), int(tile), int(seg), int(wgs))
+        return True
 
     def get_tuning(self, op: int):
         """(tile_bytes, tiles_per_segment, wgs_per_cu) of an operation."""
@@ -309,6 +331,89 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class ServerConfig(ctypes.Structure):
+    """utfx_server_config"""
+    _fields_ = [
+        ("arena_in_bytes", ctypes.c_uint64),
+        ("arena_out_bytes", ctypes.c_uint64),
+        ("device_cap_bytes", ctypes.c_uint64),
+        ("max_items", ctypes.c_uint32),
+        ("inflight", ctypes.c_uint32),
+    ]
+
+
+class Completion(ctypes.Structure):
+    """utfx_completion"""
+    _fields_ = [("tag", ctypes.c_uint64), ("result", CResult)]
+
+
+class Server:
+    """Continuous-batching server (utfx_server_*): host requests in, results and
+    outputs back on the host."""
+
+    def __init__(self, arena_in_bytes: int, arena_out_bytes: int, max_items: int = 65536, inflight: int = 2,
+                 device_cap_bytes: int = 32 << 30):
+        self._lib = lib()
+        cfg = ServerConfig(arena_in_bytes, arena_out_bytes, device_cap_bytes, max_items, inflight)
+        h = ctypes.c_void_p()
+        st = self._lib.utfx_server_create(ctypes.byref(h), ctypes.byref(cfg))
+        if st != OK:
+            raise UtfxError("utfx_server_create failed with status %d" % st)
+        self._h = h
+        self.max_items = max_items
+        self.inflight = inflight
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.utfx_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return (self._lib.utfx_server_last_error(self._h) or b"").decode()
+
+    def submit(self, tag: int, data_ptr: int, len_units: int, direction: int, out_ptr: int, out_cap: int) -> int:
+        return int(self._lib.utfx_server_submit(self._h, tag, data_ptr, len_units, direction, out_ptr, out_cap))
+
+    def progress(self, max_done: int = 4096):
+        """Completions [(tag, Result)] reported by one progress call."""
+        buf = (Completion * max_done)()
+        n = ctypes.c_uint32()
+        st = self._lib.utfx_server_progress(self._h, buf, max_done, ctypes.byref(n))
+        if st != OK:
+            raise UtfxError("progress: %d %s" % (st, self.last_error()))
+        return [(int(buf[i].tag), _res(buf[i].result)) for i in range(n.value)]
+
+    def replay(self, arrival_ns, data_ptrs, len_units, dirs, out_ptrs, out_caps):
+        """Real-time replay of an arrival trace (numpy arrays).  Returns (latency_ns
+        array, list of Result, wall_ns)."""
+        import numpy as np
+
+        n = len(arrival_ns)
+        arr = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        dp = np.ascontiguousarray(data_ptrs, dtype=np.uint64)
+        ln = np.ascontiguousarray(len_units, dtype=np.uint64)
+        dr = np.ascontiguousarray(dirs, dtype=np.uint32)
+        op = np.ascontiguousarray(out_ptrs, dtype=np.uint64)
+        oc = np.ascontiguousarray(out_caps, dtype=np.uint64)
+        lat = np.zeros(n, dtype=np.uint64)
+        res = np.zeros(n * 24, dtype=np.uint8)
+        wall = ctypes.c_uint64()
+        st = self._lib.utfx_server_replay(self._h, n, arr.ctypes.data, dp.ctypes.data, ln.ctypes.data,
+                                          dr.ctypes.data, op.ctypes.data, oc.ctypes.data, lat.ctypes.data,
+                                          res.ctypes.data, ctypes.byref(wall))
+        if st != OK:
+            raise UtfxError("replay: %d %s" % (st, self.last_error()))
+        rec = np.dtype([("status", "<i4"), ("reserved", "<u4"), ("count", "<u8"), ("written", "<u8")])
+        r = res.view(rec)
+        return lat, r, int(wall.value)
 
 
 # numpy layout of utfx_item (include/utfx.h)

@@ -576,3 +576,5 @@ void utfx_graph_destroy(utfx_graph* g) {
 }
 
 }  // extern "C"
+
+#include "utfx_serve.hpp"

@@ -1,0 +1,293 @@
+// utfx_serve.hpp -- continuous-batching server over the batched call (host code).
+//
+// Requests (host payloads) queue up; whenever one of the server's in-flight slots is
+// free, one step takes every queued request that fits the slot's arenas (admission by
+// free arena bytes and item slots), packs the payloads into the slot's pinned staging
+// buffer, and on the slot's own stream copies them to the device, runs one batched
+// call, and copies results and outputs back.  Requests that arrive while steps run
+// join the next step (continuous batching); with two or more slots a step is packed
+// and launched while earlier ones are still on the GPU.  Completion copies each
+// request's output to its destination and reports its result.  Single-threaded: the
+// caller drives it with utfx_server_progress, or replays a whole arrival trace in real
+// time with utfx_server_replay.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <time.h>
+
+#include <deque>
+#include <new>
+#include <vector>
+
+#include "utfx.h"
+
+namespace utfx_srv {
+
+struct Req {
+  uint64_t tag;
+  const uint8_t* data;
+  uint64_t len;       // input units
+  uint32_t dir;
+  uint8_t* out;
+  uint64_t out_cap;   // output units
+};
+
+struct Slot {
+  utfx_ctx* ctx = nullptr;  // own context: batch workspaces are per context
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  uint8_t* h_in = nullptr;
+  uint8_t* d_in = nullptr;
+  uint8_t* h_out = nullptr;
+  uint8_t* d_out = nullptr;
+  utfx_item* h_items = nullptr;
+  utfx_item* d_items = nullptr;
+  utfx_result* h_res = nullptr;
+  utfx_result* d_res = nullptr;
+  std::vector<Req> reqs;
+  bool busy = false;
+};
+
+inline uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+inline uint64_t al16(uint64_t x) { return (x + 15) & ~15ull; }
+
+}  // namespace utfx_srv
+
+struct utfx_server {
+  utfx_server_config cfg;
+  std::deque<utfx_srv::Req> pending;
+  std::deque<uint64_t> rejected;  // tags of requests no slot can ever hold
+  std::vector<utfx_srv::Slot> slots;
+  uint64_t steps = 0;
+  uint64_t items_total = 0;
+  char err[256];
+};
+
+namespace utfx_srv {
+
+inline void free_slot(Slot& s) {
+  if (s.stream) (void)hipStreamSynchronize(s.stream);
+  if (s.ctx) utfx_destroy(s.ctx);
+  if (s.done) (void)hipEventDestroy(s.done);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  if (s.h_in) (void)hipHostFree(s.h_in);
+  if (s.h_out) (void)hipHostFree(s.h_out);
+  if (s.h_items) (void)hipHostFree(s.h_items);
+  if (s.h_res) (void)hipHostFree(s.h_res);
+  if (s.d_in) (void)hipFree(s.d_in);
+  if (s.d_out) (void)hipFree(s.d_out);
+  if (s.d_items) (void)hipFree(s.d_items);
+  if (s.d_res) (void)hipFree(s.d_res);
+  s = Slot();
+}
+
+inline hipError_t alloc_slot(Slot& s, const utfx_server_config& c) {
+  hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_in, c.arena_in_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_out, c.arena_out_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_items, c.max_items * sizeof(utfx_item), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_res, c.max_items * sizeof(utfx_result), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&s.d_in, c.arena_in_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&s.d_out, c.arena_out_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&s.d_items, c.max_items * sizeof(utfx_item));
+  if (e == hipSuccess) e = hipMalloc((void**)&s.d_res, c.max_items * sizeof(utfx_result));
+  if (e == hipSuccess && utfx_create(&s.ctx, s.stream) != UTFX_OK) e = hipErrorOutOfMemory;
+  return e;
+}
+
+// Bytes a request needs in the input and output arenas.
+inline uint64_t in_bytes(const Req& r) { return r.len * (r.dir ? 2 : 1); }
+inline uint64_t out_bytes(const Req& r) { return r.out_cap * (r.dir ? 1 : 2); }
+
+// Packs every queued request that fits into slot s and launches the step.  Returns the
+// number of requests taken.  A request no slot can hold is rejected (it completes with
+// UTFX_E_INVALID_ARG on the next progress call).
+inline uint32_t launch_step(utfx_server* S, Slot& s, utfx_status* st) {
+  const utfx_server_config& c = S->cfg;
+  uint64_t in_used = 0, out_used = 0, units = 0;
+  s.reqs.clear();
+  while (!S->pending.empty() && s.reqs.size() < c.max_items) {
+    const Req& r = S->pending.front();
+    const uint64_t io = al16(in_used), oo = al16(out_used);
+    if (r.dir > 1 || in_bytes(r) > c.arena_in_bytes || out_bytes(r) > c.arena_out_bytes) {
+      S->rejected.push_back(r.tag);
+      S->pending.pop_front();
+      continue;
+    }
+    if (io + in_bytes(r) > c.arena_in_bytes || oo + out_bytes(r) > c.arena_out_bytes) break;
+    if (in_bytes(r)) memcpy(s.h_in + io, r.data, in_bytes(r));
+    utfx_item& it = s.h_items[s.reqs.size()];
+    it.in_off = io;
+    it.in_len = r.len;
+    it.out_off = oo;
+    it.out_cap = r.out_cap;
+    it.dir = r.dir;
+    it.pad = 0;
+    in_used = io + in_bytes(r);
+    out_used = oo + out_bytes(r);
+    units += r.len;
+    s.reqs.push_back(r);
+    S->pending.pop_front();
+  }
+  const uint32_t n = (uint32_t)s.reqs.size();
+  if (!n) return 0;
+  hipError_t e = hipMemcpyAsync(s.d_items, s.h_items, n * sizeof(utfx_item), hipMemcpyHostToDevice, s.stream);
+  if (e == hipSuccess && in_used) e = hipMemcpyAsync(s.d_in, s.h_in, in_used, hipMemcpyHostToDevice, s.stream);
+  utfx_status bs = UTFX_OK;
+  if (e == hipSuccess)
+    bs = utfx_batch_run(s.ctx, s.d_in, c.arena_in_bytes, s.d_out, c.arena_out_bytes, s.d_items, n, units, s.d_res);
+  if (e == hipSuccess && bs == UTFX_OK)
+    e = hipMemcpyAsync(s.h_res, s.d_res, n * sizeof(utfx_result), hipMemcpyDeviceToHost, s.stream);
+  if (e == hipSuccess && bs == UTFX_OK && out_used)
+    e = hipMemcpyAsync(s.h_out, s.d_out, out_used, hipMemcpyDeviceToHost, s.stream);
+  if (e == hipSuccess && bs == UTFX_OK) e = hipEventRecord(s.done, s.stream);
+  if (e != hipSuccess || bs != UTFX_OK) {
+    snprintf(S->err, sizeof(S->err), "step launch: %s / status %d", hipGetErrorString(e), (int)bs);
+    *st = UTFX_E_DEVICE;
+  }
+  s.busy = true;
+  S->steps++;
+  S->items_total += n;
+  return n;
+}
+
+}  // namespace utfx_srv
+
+extern "C" {
+
+utfx_status utfx_server_create(utfx_server** out, const utfx_server_config* cfg) {
+  using namespace utfx_srv;
+  if (!out || !cfg || cfg->inflight < 1 || cfg->inflight > 16 || cfg->max_items < 1 || cfg->arena_in_bytes < 16 ||
+      cfg->arena_out_bytes < 16)
+    return UTFX_E_INVALID_ARG;
+  *out = nullptr;
+  const uint64_t dev = (uint64_t)cfg->inflight * (cfg->arena_in_bytes + cfg->arena_out_bytes);
+  if (cfg->device_cap_bytes && dev > cfg->device_cap_bytes) return UTFX_E_INVALID_ARG;
+  utfx_server* S = new (std::nothrow) utfx_server();
+  if (!S) return UTFX_E_DEVICE;
+  S->cfg = *cfg;
+  S->err[0] = 0;
+  S->slots.resize(cfg->inflight);
+  for (auto& s : S->slots) {
+    bool ok = alloc_slot(s, *cfg) == hipSuccess;
+    // size the slot's batch workspace for any step now, so serving never allocates:
+    // a step of max_items empty items with the largest possible input total
+    if (ok) ok = hipMemsetAsync(s.d_items, 0, cfg->max_items * sizeof(utfx_item), s.stream) == hipSuccess;
+    if (ok)
+      ok = utfx_batch_run(s.ctx, s.d_in, cfg->arena_in_bytes, s.d_out, cfg->arena_out_bytes, s.d_items,
+                          cfg->max_items, cfg->arena_in_bytes, s.d_res) == UTFX_OK;
+    if (ok) ok = hipStreamSynchronize(s.stream) == hipSuccess;
+    if (!ok) {
+      for (auto& t : S->slots) free_slot(t);
+      delete S;
+      return UTFX_E_DEVICE;
+    }
+  }
+  *out = S;
+  return UTFX_OK;
+}
+
+void utfx_server_destroy(utfx_server* S) {
+  if (!S) return;
+  for (auto& s : S->slots) utfx_srv::free_slot(s);
+  delete S;
+}
+
+const char* utfx_server_last_error(const utfx_server* S) { return S ? S->err : "null server"; }
+
+utfx_status utfx_server_submit(utfx_server* S, uint64_t tag, const void* data, uint64_t len_units, uint32_t dir,
+                               void* out, uint64_t out_cap_units) {
+  if (!S || (len_units && !data) || (out_cap_units && !out)) return UTFX_E_INVALID_ARG;
+  S->pending.push_back(utfx_srv::Req{tag, static_cast<const uint8_t*>(data), len_units, dir,
+                                     static_cast<uint8_t*>(out), out_cap_units});
+  return UTFX_OK;
+}
+
+utfx_status utfx_server_progress(utfx_server* S, utfx_completion* done, uint32_t max_done, uint32_t* n_done) {
+  using namespace utfx_srv;
+  if (!S || !n_done || (max_done && !done)) return UTFX_E_INVALID_ARG;
+  *n_done = 0;
+  utfx_status st = UTFX_OK;
+  // completions first (a slot is only drained when all its requests fit in `done`)
+  for (auto& s : S->slots) {
+    if (!s.busy || *n_done + s.reqs.size() > max_done) continue;
+    const hipError_t q = hipEventQuery(s.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) {
+      snprintf(S->err, sizeof(S->err), "step: %s", hipGetErrorString(q));
+      return UTFX_E_DEVICE;
+    }
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+      const Req& r = s.reqs[i];
+      const utfx_result& res = s.h_res[i];
+      const uint64_t w = res.written < r.out_cap ? res.written : r.out_cap;
+      const uint64_t ob = w * (r.dir ? 1 : 2);
+      if (ob && res.status != UTFX_E_OUTPUT_TOO_SMALL) memcpy(r.out, s.h_out + s.h_items[i].out_off, ob);
+      utfx_completion& c = done[(*n_done)++];
+      c.tag = r.tag;
+      c.result = res;
+    }
+    s.busy = false;
+    s.reqs.clear();
+  }
+  // requests no slot can hold
+  while (!S->rejected.empty() && *n_done < max_done) {
+    utfx_completion& c = done[(*n_done)++];
+    c.tag = S->rejected.front();
+    c.result.status = UTFX_E_INVALID_ARG;
+    c.result.reserved = 0;
+    c.result.count = 0;
+    c.result.written = 0;
+    S->rejected.pop_front();
+  }
+  // then launch steps on free slots while requests wait
+  for (auto& s : S->slots) {
+    if (S->pending.empty()) break;
+    if (s.busy) continue;
+    launch_step(S, s, &st);
+    if (st != UTFX_OK) return st;
+  }
+  return st;
+}
+
+utfx_status utfx_server_replay(utfx_server* S, uint32_t n, const uint64_t* arrival_ns, const void* const* data,
+                               const uint64_t* len_units, const uint32_t* dirs, void* const* outs,
+                               const uint64_t* out_caps, uint64_t* latency_ns, utfx_result* results,
+                               uint64_t* wall_ns) {
+  using namespace utfx_srv;
+  if (!S || (n && (!arrival_ns || !data || !len_units || !dirs || !outs || !out_caps || !latency_ns || !results)))
+    return UTFX_E_INVALID_ARG;
+  std::vector<utfx_completion> done(S->cfg.max_items * S->slots.size() + 64);
+  const uint64_t t0 = now_ns();
+  uint32_t next = 0, finished = 0;
+  while (finished < n) {
+    uint64_t t = now_ns() - t0;
+    while (next < n && arrival_ns[next] <= t) {
+      utfx_server_submit(S, next, data[next], len_units[next], dirs[next], outs[next], out_caps[next]);
+      ++next;
+    }
+    uint32_t k = 0;
+    utfx_status st = utfx_server_progress(S, done.data(), (uint32_t)done.size(), &k);
+    if (st != UTFX_OK) return st;
+    if (k) {
+      t = now_ns() - t0;
+      for (uint32_t j = 0; j < k; ++j) {
+        const uint64_t i = done[j].tag;
+        results[i] = done[j].result;
+        latency_ns[i] = t - arrival_ns[i];
+      }
+      finished += k;
+    }
+  }
+  if (wall_ns) *wall_ns = now_ns() - t0;
+  return UTFX_OK;
+}
+
+}  // extern "C"

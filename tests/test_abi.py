@@ -72,3 +72,14 @@ def test_no_cpu_fallback_without_gpu():
 
     with pytest.raises((utfx.UtfxError, TypeError)):
         utfx._ptr_len(torch.zeros(4, dtype=torch.uint8), 1)
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """The tuning cache is plain JSON that load() returns unchanged."""
+    from paper_2212_05098_amd import tune
+
+    cache = {"device": "x", "size_mib": 1, "ops": {"0": [8192, 4, 4], "6": [8192, 4, 2]}}
+    p = str(tmp_path / "c.json")
+    tune.save(cache, p)
+    assert tune.load(p) == cache
+    assert tune.load(str(tmp_path / "missing.json")) is None

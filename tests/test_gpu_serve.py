@@ -1,0 +1,98 @@
+"""The continuous-batching server: every request served through it (host payload in,
+host output out) matches the oracle exactly, whether it was batched with others or
+alone; small arenas force admission to wait; oversized requests are rejected."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2212_05098_amd as utfx
+from paper_2212_05098_amd import serve, synth
+from gpu_helpers import note
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(data, d, out_bytes, res):
+    if d == 0:
+        want, ref = O.utf8_to_utf16le(data)
+        got = out_bytes[:2 * want.written].view(np.uint16)
+    else:
+        want, ref = O.utf16le_to_utf8(data)
+        got = out_bytes[:want.written]
+    assert tuple(res) == tuple(want), (d, res, want)
+    assert np.array_equal(got, ref[:want.written])
+
+
+def test_server_progress_small_arenas():
+    """500 requests through arenas of 64 KiB: most steps are full, requests wait for
+    admission; one request larger than an arena completes with INVALID_ARG."""
+    rng = synth.rng_for(31, 1)
+    srv = utfx.Server(arena_in_bytes=64 << 10, arena_out_bytes=192 << 10, max_items=64, inflight=2)
+    reqs = []
+    for i in range(500):
+        d = int(rng.integers(0, 2))
+        prof = synth.SCRIPT_PROFILES[int(rng.integers(0, 4))]
+        L = int(synth.lognormal_lengths(rng, 1, 300, 1.5, 1, 30000)[0])
+        if d == 0:
+            data = synth.utf8_buffer(prof, L, rng)
+            if rng.random() < 0.1 and L > 4:
+                data[int(rng.integers(0, L))] = 0xC0
+            cap = data.size
+            out = np.zeros(2 * cap + 2, dtype=np.uint8)
+        else:
+            data = synth.utf16_buffer(prof, max(L // 2, 1), rng)
+            if rng.random() < 0.1:
+                data[int(rng.integers(0, data.size))] = 0xD800
+            cap = 3 * data.size
+            out = np.zeros(cap + 1, dtype=np.uint8)
+        reqs.append((data, d, cap, out))
+    big = np.full(100 << 10, 0x41, dtype=np.uint8)
+    big_out = np.zeros(2 * big.size, dtype=np.uint8)
+    reqs.append((big, 0, big.size, big_out))
+    for i, (data, d, cap, out) in enumerate(reqs):
+        n_units = data.size
+        assert srv.submit(i, data.ctypes.data, n_units, d, out.ctypes.data, cap) == utfx.OK
+    got = {}
+    note("server progress: %d requests" % len(reqs))
+    for _ in range(2_000_000):
+        for tag, r in srv.progress():
+            got[tag] = r
+        if len(got) == len(reqs):
+            break
+    assert len(got) == len(reqs)
+    assert got[len(reqs) - 1].status == utfx.E_INVALID_ARG
+    for i, (data, d, cap, out) in enumerate(reqs[:-1]):
+        _check(data, d, out, got[i])
+    srv.close()
+
+
+def test_server_replay_trace_fully_checked():
+    """A seeded Poisson trace (20k requests/s for 0.25 s) replayed in real time with
+    every request checked against the oracle."""
+    import torch
+
+    pool = serve.PayloadPool(mib_per_pool=4, seed=1)
+    check = torch.zeros(256 << 20, dtype=torch.uint8, pin_memory=True)
+    scratch = torch.zeros(64 << 20, dtype=torch.uint8, pin_memory=True)
+    w = serve.make_workload(pool, 20000, 0.25, seed=3, scratch_ptr=scratch.data_ptr(), check_every=1,
+                            check_ptr=check.data_ptr(), check_bytes=check.numel())
+    assert w.checked.size > 0.9 * w.arrival_ns.size
+    srv = utfx.Server(arena_in_bytes=64 << 20, arena_out_bytes=192 << 20, max_items=65536, inflight=2)
+    note("server replay: %d requests" % w.arrival_ns.size)
+    lat, res, wall = srv.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
+    srv.close()
+    assert np.all(lat > 0)
+    outs = check.numpy()
+    import ctypes
+
+    for j, i in enumerate(w.checked):
+        d, n = int(w.dirs[i]), int(w.len_units[i])
+        raw = np.ctypeslib.as_array((ctypes.c_uint8 * (n * (2 if d else 1))).from_address(int(w.data_ptrs[i])))
+        data = raw.view(np.uint16) if d else raw
+        r = utfx.Result(int(res[i]["status"]), int(res[i]["count"]), int(res[i]["written"]))
+        _check(data, d, outs[int(w.check_off[j]):], r)
+
+
+def test_server_device_cap():
+    with pytest.raises(utfx.UtfxError):
+        utfx.Server(arena_in_bytes=1 << 30, arena_out_bytes=2 << 30, inflight=2, device_cap_bytes=4 << 30)
