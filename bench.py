@@ -45,6 +45,14 @@ def main():
     ap.add_argument("--profiles", default="ascii,latin,cjk,emoji")
     ap.add_argument("--u8", default="", help="UTF-8 -> UTF-16 launch: tile_bytes,tiles_per_segment")
     ap.add_argument("--u16", default="", help="UTF-16 -> UTF-8 launch: tile_bytes,tiles_per_segment")
+    ap.add_argument("--batch-strings", type=int, default=200000, help="strings in the batched workload (0 = skip)")
+    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--single-sample", type=int, default=20000,
+                    help="strings of the batch run with one launch each, for the comparison")
+    ap.add_argument("--serve-rates", default="20000,50000,100000,200000,500000",
+                    help="offered request rates of the serving runs (empty = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=0.5)
+    ap.add_argument("--no-tune-cache", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -62,6 +70,7 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = utfx.Context()
+    tuned = False if args.no_tune_cache else ctx.load_tuning()
     for op, spec in ((utfx.OP_UTF8_TO_UTF16, args.u8), (utfx.OP_UTF16_TO_UTF8, args.u16)):
         if spec:
             t, sg = (int(v) for v in spec.split(","))
@@ -207,6 +216,9 @@ def main():
                "sample": "first %d MiB of each of the %d (profile, direction) inputs, cut at a character "
                              "boundary; best of 2; single thread" % (args.cpu_sample_mib, len(cases))}
 
+    batch = run_batch(args, ctx, log) if args.batch_strings else None
+    serving = run_serving(args, log) if args.serve_rates else None
+
     out = {
         "metric": "validated transcode input GB/s (% HBM peak); batched p50/p99 latency at load",
         "value": round(in_bytes / step_s / 1e9, 2),
@@ -223,7 +235,8 @@ def main():
         "config": {"workload": "four %d MiB buffers (ascii, latin, cjk, emoji profiles), each transcoded "
                                "UTF-8->UTF-16LE and UTF-16LE->UTF-8 with validation" % args.size_mib,
                    "buffers": len(cases), "bytes_per_buffer": nbytes, "rotate": args.rotate,
-                   "tuning": {"utf8->utf16le": list(ctx.get_tuning(0)), "utf16le->utf8": list(ctx.get_tuning(1))}},
+                   "tuning": {"utf8->utf16le": list(ctx.get_tuning(0)), "utf16le->utf8": list(ctx.get_tuning(1)),
+                              "source": "tune_cache.json" if tuned else "defaults"}},
         "roofline": {"bound": "hbm", "kernel": kernel, "case": case_name,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -232,9 +245,123 @@ def main():
         "device_copy_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
         "per_case": per_case,
+        "batched": batch,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def run_batch(args, ctx, log):
+    """Batched call on many strings (log-normal lengths, median 256 B, sigma 2, 8 B .. 4
+    MiB, mixed profiles and directions, 0.5 % with an error): device time per call, and
+    the same strings with one launch each (a sample, extrapolated)."""
+    import numpy as np
+    import torch
+
+    import paper_2212_05098_amd as utfx
+    from paper_2212_05098_amd import synth
+
+    t0 = time.time()
+    b = synth.make_batch(args.batch_strings, seed_key=(0, 4), median=256, sigma=2.0, hi=4 << 20, err_frac=0.005)
+    n = args.batch_strings
+    caps = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
+    sizes = np.where(b.direction == 0, 2 * caps, caps)
+    out_off = np.concatenate([[0], np.cumsum(sizes + 16)[:-1]]).astype(np.uint64)
+    out_off += out_off % 2
+    d_in = torch.from_numpy(b.arena).cuda()
+    d_out = torch.empty(int(out_off[-1] + sizes[-1] + 64), dtype=torch.uint8, device="cuda")
+    items = utfx.pack_items(b.in_off, b.in_len, out_off, caps, b.direction)
+    res = utfx.result_tensor(n)
+    total = int(np.sum(b.in_len))
+    in_bytes = int(np.sum(np.where(b.direction == 0, b.in_len, 2 * b.in_len)))
+    log("batch: %d strings, %.1f MB generated in %.1fs" % (n, in_bytes / 1e6, time.time() - t0))
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        assert ctx.batch_run(d_in, d_out, items, n, total, res) == utfx.OK
+    torch.cuda.synchronize()
+    rs = utfx.results_from_tensor(res)
+    n_err = sum(1 for r in rs if r.status != utfx.OK)
+    ms = []
+    for _ in range(args.batch_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        assert ctx.batch_run(d_in, d_out, items, n, total, res) == utfx.OK
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ms = np.array(ms)
+    # one launch per string on a sample (the first k strings), same kernels' results
+    k = min(args.single_sample, n)
+    one = utfx.result_tensor(1)
+    srcs = []
+    for i in range(k):
+        a, L, o = int(b.in_off[i]), int(b.in_len[i]), int(out_off[i])
+        if b.direction[i] == 0:
+            srcs.append((0, d_in[a:a + L], d_out[o:o + 2 * int(caps[i])].view(torch.int16)))
+        else:
+            srcs.append((1, d_in[a:a + 2 * L].view(torch.int16), d_out[o:o + int(caps[i])]))
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for d, src, dst in srcs:
+        if d == 0:
+            ctx.utf8_to_utf16le_async(src, dst, one)
+        else:
+            ctx.utf16le_to_utf8_async(src, dst, one)
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - ts
+    per_string_us = single_s / k * 1e6
+    batch_ms = float(np.median(ms))
+    log("batch: %.3f ms median per call (%.1f GB/s); one launch per string: %.2f us each" %
+        (batch_ms, in_bytes / (batch_ms * 1e6), per_string_us))
+    return {"strings": n, "input_bytes": in_bytes, "errors": n_err, "reps": args.batch_reps,
+            "ms_p50": round(batch_ms, 4), "ms_p99": round(float(np.percentile(ms, 99)), 4),
+            "ms_min": round(float(ms.min()), 4), "GBps": round(in_bytes / (batch_ms * 1e6), 2),
+            "one_launch_per_string_us": round(per_string_us, 2), "one_launch_sample": k,
+            "speedup_vs_one_launch_per_string": round(per_string_us * n / (batch_ms * 1e3), 1),
+            "tuning_wgs_per_cu": ctx.get_tuning(utfx.OP_BATCH)[2]}
+
+
+def run_serving(args, log):
+    """Continuous-batching server (two steps in flight) on Poisson traces at each
+    offered rate, and one launch per request at the lowest rate."""
+    import numpy as np
+    import torch
+
+    import paper_2212_05098_amd as utfx
+    from paper_2212_05098_amd import serve
+
+    t0 = time.time()
+    pool = serve.PayloadPool(mib_per_pool=32, seed=0)
+    scratch = torch.empty(64 << 20, dtype=torch.uint8, pin_memory=True)
+    check = torch.empty(64 << 20, dtype=torch.uint8, pin_memory=True)
+    log("serving: payload pool in %.1fs" % (time.time() - t0))
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    out = {"server": {"inflight": 2, "arena_in_MiB": 256, "arena_out_MiB": 768, "device_cap_GiB": 32},
+           "duration_s": args.serve_seconds, "runs": []}
+    srv = utfx.Server(arena_in_bytes=256 << 20, arena_out_bytes=768 << 20, max_items=1 << 18, inflight=2)
+    for k, rate in enumerate(rates):
+        w = serve.make_workload(pool, rate, args.serve_seconds, seed=k, scratch_ptr=scratch.data_ptr(),
+                                check_every=1000, check_ptr=check.data_ptr(), check_bytes=check.numel())
+        lat, res, wall = srv.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
+        ok = int(np.sum(res["status"] == 0))
+        row = serve.summarize(w, lat, wall, rate)
+        row["ok"] = ok
+        out["runs"].append(row)
+        log("serving %7.0f req/s: %d requests, p50 %.1f us, p99 %.1f us, %.2f GB/s" %
+            (rate, row["requests"], row["p50_us"], row["p99_us"], row["delivered_GBps"]))
+    srv.close()
+    # one launch per request (max_items = 1) at the lowest rate, for comparison
+    one = utfx.Server(arena_in_bytes=64 << 20, arena_out_bytes=192 << 20, max_items=1, inflight=2)
+    rate = rates[0]
+    w = serve.make_workload(pool, rate, min(args.serve_seconds, 0.25), seed=99, scratch_ptr=scratch.data_ptr(),
+                            check_every=1000, check_ptr=check.data_ptr(), check_bytes=check.numel())
+    lat, res, wall = one.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
+    one.close()
+    row = serve.summarize(w, lat, wall, rate)
+    out["one_launch_per_request"] = row
+    log("one launch per request %7.0f req/s: p50 %.1f us, p99 %.1f us" % (rate, row["p50_us"], row["p99_us"]))
+    return out
 
 
 if __name__ == "__main__":
