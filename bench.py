@@ -318,8 +318,7 @@ def run_batch(args, ctx, log):
             "ms_p50": round(batch_ms, 4), "ms_p99": round(float(np.percentile(ms, 99)), 4),
             "ms_min": round(float(ms.min()), 4), "GBps": round(in_bytes / (batch_ms * 1e6), 2),
             "one_launch_per_string_us": round(per_string_us, 2), "one_launch_sample": k,
-            "speedup_vs_one_launch_per_string": round(per_string_us * n / (batch_ms * 1e3), 1),
-            "tuning_wgs_per_cu": ctx.get_tuning(utfx.OP_BATCH)[2]}
+            "speedup_vs_one_launch_per_string": round(per_string_us * n / (batch_ms * 1e3), 1)}
 
 
 def run_serving(args, log):

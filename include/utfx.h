@@ -100,8 +100,7 @@ utfx_status utfx_set_stream(utfx_ctx *ctx, void *hip_stream);
  *             registers and its output in LDS, so they take only these pairs:
  *             UTF-8 -> UTF-16 (4096, 2, 4 or 8), (8192, 2 or 4); UTF-16 -> UTF-8
  *             (4096 or 8192, 2, 4 or 8);
- * wgs_per_cu: workgroups per compute unit of the batched call's persistent grid for
- *             long strings (1..16, default 2; ignored by the single-buffer kernels).
+ * wgs_per_cu: 1..16, recorded with the other values; no kernel of this version uses it.
  * Returns UTFX_E_INVALID_ARG for an unsupported value. */
 typedef enum {
   UTFX_OP_UTF8_TO_UTF16 = 0,
@@ -177,9 +176,9 @@ typedef struct {
 /* Runs the batch: the arenas hold in_bytes and out_bytes bytes; d_items (device,
  * n_items entries) describe the strings, d_results (device, n_items entries) receive
  * one result each.  Strings of up to 16,384 units
- * are transcoded by one wavefront each; longer ones are cut into segments that
- * persistent workgroups take in order, with a look-back that ends at the string's
- * first segment (sections 6 and 7 per string).  The plan is built on the device, so
+ * are transcoded by one wavefront each; longer ones are cut into segments, one
+ * workgroup each, with a look-back that ends at the string's first segment (sections 6
+ * and 7 per string).  The plan is built on the device, so
  * the call issues a fixed sequence of kernels with no allocation and no host
  * synchronisation once the workspace is large enough: it can be captured into a HIP
  * graph and replayed with new contents of the same buffers.  total_in_units bounds

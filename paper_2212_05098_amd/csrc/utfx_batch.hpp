@@ -13,10 +13,9 @@
 //   k_batch_small  one wave per item of at most SMALL_MAX units: the wave walks the
 //                  string 1 KiB (512 words) at a time carrying the output offset, so it
 //                  needs no look-back and no barrier, and writes the item's result;
-//   k_batch_large  persistent workgroups take segments of large items in ticket order
-//                  and run the single-buffer segment code on them; a segment's look-back
-//                  ends at its item's first segment, which publishes its prefix directly
-//                  (one launch per direction, so each holds only its own registers);
+//   k_batch_large  one workgroup per segment of the large items (one launch per
+//                  direction) runs the single-buffer segment code; a segment's look-back
+//                  ends at its item's first segment, which publishes its prefix directly;
 //   k_batch_fin    one workgroup per large item: the result from its segments.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -39,6 +38,7 @@ constexpr int BWG = 512, BS8 = 4, BS16 = 4;
 constexpr uint64_t BSEG8 = 16ull * BWG * BS8;   // UTF-8 bytes per segment
 constexpr uint64_t BSEG16 = 8ull * BWG * BS16;  // UTF-16 words per segment
 constexpr int PLAN_WG = 256;
+constexpr int PLAN_ITEMS = 4;  // items per plan thread
 constexpr int SMALL_WG = 256;
 
 struct BatchArgs {
@@ -132,25 +132,32 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
   __shared__ uint32_t scr[2][PLAN_WG / 64];
   __shared__ unsigned long long pfx[2];
   __shared__ unsigned long long sum_scr[PLAN_WG / 64 + 2];
-  const uint64_t i = (uint64_t)blockIdx.x * PLAN_WG + threadIdx.x;
-  uint32_t units = 0;
-  int dir = 0;
+  // PLAN_ITEMS consecutive items per thread
+  const uint64_t i0 = ((uint64_t)blockIdx.x * PLAN_WG + threadIdx.x) * PLAN_ITEMS;
+  uint32_t units[PLAN_ITEMS], dir[PLAN_ITEMS], tsum[2] = {0, 0};
   uint64_t len = 0;
-  if (i < A.n_items) {
-    const BItem it = A.items[i];
-    if (item_ok(A, it)) {
-      len = it.in_len;
-      if (it.in_len > SMALL_MAX) {
-        units = (uint32_t)item_units(A, it);
-        dir = (int)it.dir;
+#pragma unroll
+  for (int j = 0; j < PLAN_ITEMS; ++j) {
+    units[j] = 0;
+    dir[j] = 0;
+    const uint64_t i = i0 + j;
+    if (i < A.n_items) {
+      const BItem it = A.items[i];
+      if (item_ok(A, it)) {
+        len += it.in_len;
+        if (it.in_len > SMALL_MAX) {
+          units[j] = (uint32_t)item_units(A, it);
+          dir[j] = it.dir;
+          tsum[it.dir] += units[j];
+        }
       }
     }
   }
   const uint64_t len_sum = block_sum_u64<PLAN_WG>(len, sum_scr);
   if (threadIdx.x == 0 && len_sum) atomicAdd(&A.ws->err, (unsigned long long)len_sum);
   uint32_t total[2], local[2];
-  local[0] = block_excl_scan<PLAN_WG>(dir == 0 ? units : 0u, total[0], scr[0]);
-  local[1] = block_excl_scan<PLAN_WG>(dir == 1 ? units : 0u, total[1], scr[1]);
+  local[0] = block_excl_scan<PLAN_WG>(tsum[0], total[0], scr[0]);
+  local[1] = block_excl_scan<PLAN_WG>(tsum[1], total[1], scr[1]);
   const uint32_t epoch = cur_epoch(A.ws);
   if (threadIdx.x < 64) {
 #pragma unroll
@@ -161,15 +168,21 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
     }
   }
   __syncthreads();
-  if (i < A.n_items) {
-    const uint64_t start = pfx[dir] + local[dir];
+  uint64_t run[2] = {pfx[0] + local[0], pfx[1] + local[1]};
+#pragma unroll
+  for (int j = 0; j < PLAN_ITEMS; ++j) {
+    const uint64_t i = i0 + j;
+    if (i >= A.n_items) break;
+    const int d = (int)dir[j];
+    const uint64_t start = run[d];
     A.unit_start[i] = start;
-    if (units) {
+    if (units[j]) {
       A.item_err[i] = NO_ERR;
       const unsigned long long slot = atomicAdd(&A.ws->acc, 1ull);
       A.large[slot] = (uint32_t)i;
-      if (start + units <= A.cap_units)
-        for (uint32_t u = 0; u < units; ++u) A.unit_item[dir][start + u] = (uint32_t)i;
+      if (start + units[j] <= A.cap_units)
+        for (uint32_t u = 0; u < units[j]; ++u) A.unit_item[d][start + u] = (uint32_t)i;
+      run[d] += units[j];
     }
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
@@ -200,11 +213,30 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
+// Loads the 16-byte chunk at grid position q0 with the bytes outside the string
+// zeroed (m: range_masks of the string).  The aligned 16 bytes are read with one load
+// when they lie inside the arena [alo, ahi), else byte by byte; chunks with no byte of
+// the string read nothing.
+__device__ __forceinline__ void load8_masked(const Launch& L, uint64_t q0, const uint32_t m[4], uintptr_t alo,
+                                             uintptr_t ahi, uint32_t x[4]) {
+  x[0] = x[1] = x[2] = x[3] = 0;
+  if ((m[0] | m[1] | m[2] | m[3]) == 0) return;
+  const uintptr_t a = (uintptr_t)(L.base + q0);
+  if (a >= alo && a + 16 <= ahi) {
+    const uint4 v = *reinterpret_cast<const uint4*>(a);
+    x[0] = v.x & m[0]; x[1] = v.y & m[1]; x[2] = v.z & m[2]; x[3] = v.w & m[3];
+  } else {
+    load8(L, q0, x);
+  }
+}
+
 // One wave transcodes a UTF-8 string of n bytes (n <= SMALL_MAX) 1 KiB at a time.
-// stage: the wave's LDS (WSTAGE bytes).
+// stage: the wave's LDS (WSTAGE bytes); [alo, ahi): the input arena.  A chunk with any
+// lane partly outside the string runs the masked path on every lane, so the wave
+// never executes both paths.
 constexpr uint32_t WSTAGE = 2176;
 __device__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, uint16_t* out, uint64_t cap, uint16_t* stage,
-                               Result* res) {
+                               Result* res, uintptr_t alo, uintptr_t ahi) {
   constexpr uint32_t PAD = 16, LIM = PAD + 1024, DUMP = LIM + 16;
   static_assert((DUMP + 16) * 2 <= WSTAGE, "wave stage");
   const uint32_t lane = threadIdx.x & 63;
@@ -218,11 +250,18 @@ __device__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, uint16_t* out, uin
   uint64_t err = NO_ERR;
   for (uint64_t c0 = 0; c0 <= hi; c0 += 1024) {
     const uint64_t q0 = c0 + 16ull * lane;
-    uint32_t x[4], m[4];
-    load8(L, q0, x);
-    const bool full = q0 >= lo && q0 + 16 <= hi;
-    if (!full) range_masks(q0, lo, hi, m);
-    const uint32_t cnt = count8(x, full ? nullptr : m);
+    const bool full = !__any(!(q0 >= lo && q0 + 16 <= hi));
+    uint32_t x[4], cnt;
+    if (full) {
+      const uint4 v = *reinterpret_cast<const uint4*>(L.base + q0);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+      cnt = count8(x, nullptr);
+    } else {
+      uint32_t m[4];
+      range_masks(q0, lo, hi, m);
+      load8_masked(L, q0, m, alo, ahi, x);
+      cnt = count8(x, m);
+    }
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t tot = __shfl(incl, 63, 64);
     const uint32_t xp = wave_shr1(x[3], carry);
@@ -267,9 +306,23 @@ __device__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, uint16_t* out, uin
   }
 }
 
+// Word-masked load of the 8-word chunk at grid position q0 (see load8_masked).
+__device__ __forceinline__ void load16_masked(const Launch& L, uint64_t q0, const uint32_t m[4], uintptr_t alo,
+                                              uintptr_t ahi, uint32_t x[4]) {
+  x[0] = x[1] = x[2] = x[3] = 0;
+  if ((m[0] | m[1] | m[2] | m[3]) == 0) return;
+  const uintptr_t a = (uintptr_t)(L.base + 2 * q0);
+  if (a >= alo && a + 16 <= ahi) {
+    const uint4 v = *reinterpret_cast<const uint4*>(a);
+    x[0] = v.x & m[0]; x[1] = v.y & m[1]; x[2] = v.z & m[2]; x[3] = v.w & m[3];
+  } else {
+    load16(L, q0, x);
+  }
+}
+
 // One wave transcodes a UTF-16LE string of n words (n <= SMALL_MAX) 512 words at a time.
 __device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uint64_t cap, uint8_t* stage,
-                               Result* res) {
+                               Result* res, uintptr_t alo, uintptr_t ahi) {
   constexpr uint32_t PAD = 16, DUMP = PAD + 3 * 512 + 32;
   static_assert(DUMP + 16 <= WSTAGE, "wave stage");
   const uint32_t lane = threadIdx.x & 63;
@@ -283,15 +336,22 @@ __device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uin
   uint64_t err = NO_ERR;
   for (uint64_t c0 = 0; c0 <= hi; c0 += 512) {
     const uint64_t q0 = c0 + 8ull * lane;
-    uint32_t x[4];
-    load16(L, q0, x);
-    const bool full = q0 >= lo && q0 + 8 <= hi;
-    const uint32_t cnt = count16(x, q0, lo, hi, full);
+    const bool full = !__any(!(q0 >= lo && q0 + 8 <= hi));
+    uint32_t x[4], m[4];
+    if (full) {
+      const uint4 v = *reinterpret_cast<const uint4*>(L.base + 2 * q0);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+      word_masks(q0, lo, hi, m);
+      load16_masked(L, q0, m, alo, ahi, x);
+    }
+    const uint32_t cnt = full ? count16(x, nullptr) : count16(x, m);
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t tot = __shfl(incl, 63, 64);
     const uint32_t xprev = wave_shr1(x[3], carry);
     carry = __shfl(x[3], 63, 64);
-    const bool det = chunk_u16_to_u8(x, xprev, full, q0, lo, hi, stage + PAD + (incl - cnt), stage + DUMP);
+    const bool det = full ? chunk_u16_to_u8(x, xprev, nullptr, stage + PAD + (incl - cnt), stage + DUMP)
+                          : chunk_u16_to_u8(x, xprev, m, stage + PAD + (incl - cnt), stage + DUMP);
     __builtin_amdgcn_wave_barrier();
     store_span<uint8_t>(stage, PAD, tot, out, running, cap, lane, 64);
     __builtin_amdgcn_wave_barrier();
@@ -313,9 +373,10 @@ __device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uin
     uint64_t acc = 0;
     for (uint64_t c0 = 0; c0 < lo + err; c0 += 512) {
       const uint64_t q0 = c0 + 8ull * lane;
-      uint32_t x[4];
+      uint32_t x[4], m[4];
       load16(L, q0, x);
-      acc += count16(x, q0, lo, lo + err, false);
+      word_masks(q0, lo, lo + err, m);
+      acc += count16(x, m);
     }
     acc = wave_sum_u64(acc);
     if (lane == 0) write_result(res, ST_SURROGATE, err, acc);
@@ -339,32 +400,32 @@ __global__ void __launch_bounds__(SMALL_WG) k_batch_small(BatchArgs A) {
   }
   if (it.in_len > SMALL_MAX) return;  // a large item: k_batch_large and k_batch_fin
   uint8_t* st = smem + wid * WSTAGE;
+  const uintptr_t alo = (uintptr_t)A.in, ahi = (uintptr_t)(A.in + A.in_bytes);
   if (it.dir == 0)
     wave_u8_to_u16(A.in + it.in_off, it.in_len, reinterpret_cast<uint16_t*>(A.out + it.out_off), it.out_cap,
-                   reinterpret_cast<uint16_t*>(st), res);
+                   reinterpret_cast<uint16_t*>(st), res, alo, ahi);
   else
     wave_u16_to_u8(reinterpret_cast<const uint16_t*>(A.in + it.in_off), it.in_len, A.out + it.out_off,
-                   it.out_cap, st, res);
+                   it.out_cap, st, res, alo, ahi);
 }
 
+// One workgroup per segment of the long strings of one direction (grid: the plan's
+// bound on segments; workgroups past the real count exit at once).  Workgroups are
+// dispatched in order, so every predecessor a look-back waits for is running or done.
 template <int DIR>
 __global__ void __launch_bounds__(BWG) k_batch_large(BatchArgs A) {
-  __shared__ __attribute__((aligned(16))) uint8_t raw[DIR ? sizeof(Seg16Smem<BWG, BS16>) : sizeof(Seg8Smem<BWG, BS8>)];
-  __shared__ unsigned long long tk;
-  const uint64_t total = ld_agent(total_of(A.ws, DIR));
-  if (!plan_ok(A)) return;
-  while (true) {
-    if (threadIdx.x == 0) tk = atomicAdd(ticket_of(A.ws, DIR), 1ull);
-    __syncthreads();
-    const uint64_t t = uniform_u64(tk);
-    if (t >= total) break;
-    const uint32_t i = __builtin_amdgcn_readfirstlane(A.unit_item[DIR][t]);
-    const BItem it = A.items[i];
-    const Launch L = item_launch(A, it, i);
-    const uint64_t seg = t - A.unit_start[i];
-    if (DIR == 0) seg_u8_to_u16<BWG, BS8>(L, seg, *reinterpret_cast<Seg8Smem<BWG, BS8>*>(raw));
-    else seg_u16_to_u8<BWG, BS16>(L, seg, *reinterpret_cast<Seg16Smem<BWG, BS16>*>(raw));
-    __syncthreads();
+  const uint64_t t = blockIdx.x;
+  if (t >= ld_agent(total_of(A.ws, DIR)) || !plan_ok(A)) return;
+  const uint32_t i = __builtin_amdgcn_readfirstlane(A.unit_item[DIR][t]);
+  const BItem it = A.items[i];
+  const Launch L = item_launch(A, it, i);
+  const uint64_t seg = t - A.unit_start[i];
+  if (DIR == 0) {
+    __shared__ __attribute__((aligned(16))) Seg8Smem<BWG, BS8> sm;
+    seg_u8_to_u16<BWG, BS8>(L, seg, sm);
+  } else {
+    __shared__ __attribute__((aligned(16))) Seg16Smem<BWG, BS16> sm;
+    seg_u16_to_u8<BWG, BS16>(L, seg, sm);
   }
 }
 
@@ -425,7 +486,7 @@ inline void batch_ws_free(BatchWs& b) {
 
 // Clears every status word and initialises the header.  Synchronous.
 inline hipError_t batch_ws_clear(BatchWs& b, hipStream_t s) {
-  const size_t plan_words = (b.cap_items + utfx_dev::PLAN_WG - 1) / utfx_dev::PLAN_WG;
+  const size_t plan_words = (b.cap_items + utfx_dev::PLAN_WG - 1) / utfx_dev::PLAN_WG;  // >= plan blocks
   hipError_t e = hipSuccess;
   for (int d = 0; d < 2 && e == hipSuccess; ++d) {
     e = hipMemsetAsync(b.status[d], 0, b.cap_units * sizeof(unsigned long long), s);
@@ -529,9 +590,9 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   }
   A.cap_units = cap_units;
   A.total_in = total_in_units;
-  const uint32_t plan_blocks = (n_items + PLAN_WG - 1) / PLAN_WG;
+  const uint32_t plan_blocks = (n_items + PLAN_WG * PLAN_ITEMS - 1) / (PLAN_WG * PLAN_ITEMS);
   const uint32_t small_blocks = (n_items + SMALL_WG / 64 - 1) / (SMALL_WG / 64);
-  const uint32_t large_blocks = (uint32_t)num_cus * (wgs_per_cu ? wgs_per_cu : 2);
+  const uint32_t large_blocks = (uint32_t)(cap_units < 0x7FFFFFFFull ? cap_units : 0x7FFFFFFFull);
   const uint32_t fin_blocks = n_items < 1024 ? n_items : 1024;
   hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ws);
   hipLaunchKernelGGL(k_batch_plan, dim3(plan_blocks), dim3(PLAN_WG), 0, s, A);

@@ -62,15 +62,18 @@ __device__ __forceinline__ uint32_t load8_prev(const Launch& L, uint64_t q0) {
 
 // Byte masks (0xFF per byte) of the chunk's grid positions in [lo, hi).
 __device__ __forceinline__ void range_masks(uint64_t q0, uint64_t lo, uint64_t hi, uint32_t m[4]) {
+  // byte i of the chunk is in range iff a <= i < b; per byte, with a bias of 0x80 so
+  // that no subtraction borrows into the next byte: (i | 0x80) - a keeps bit 7 iff
+  // i >= a, and (b | 0x80) - (i + 1) keeps it iff i < b
+  const int64_t a64 = (int64_t)lo - (int64_t)q0, b64 = (int64_t)hi - (int64_t)q0;
+  const uint32_t a = a64 <= 0 ? 0u : (a64 >= 16 ? 16u : (uint32_t)a64);
+  const uint32_t b = b64 <= 0 ? 0u : (b64 >= 16 ? 16u : (uint32_t)b64);
+  const uint32_t A = a * 0x01010101u, B = (b * 0x01010101u) | HI;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint64_t q = q0 + 4 * k + i;
-      r |= (q >= lo && q < hi) ? (0xFFu << (8 * i)) : 0u;
-    }
-    m[k] = r;
+    const uint32_t idx = 0x03020100u + 0x04040404u * k;
+    const uint32_t in = ((idx | HI) - A) & (B - (idx + 0x01010101u)) & HI;
+    m[k] = (in >> 7) * 0xFFu;
   }
 }
 

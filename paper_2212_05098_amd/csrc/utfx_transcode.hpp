@@ -402,38 +402,51 @@ __device__ __forceinline__ void pk_enc16s(uint32_t X, uint32_t P, uint32_t c_lo,
   v_hi = c_hi == 3 ? t3h : (c_hi == 2 ? t2h : (X >> 16));
 }
 
-// Output bytes of a chunk of 8 words (positions outside [lo, hi) count 0).
-__device__ __forceinline__ uint32_t count16(const uint32_t x[4], uint64_t q0, uint64_t lo, uint64_t hi, bool full) {
-  if (full) {
-    const uint32_t l = pk_len16s(x[0]) + pk_len16s(x[1]) + pk_len16s(x[2]) + pk_len16s(x[3]);
-    return (l & 0xFFFFu) + (l >> 16);
-  }
-  uint32_t acc = 0;
+// 16-bit lane masks (0xFFFF) of the chunk's word positions q0 + j in [lo, hi), as
+// four dwords of two words each; the per-lane bias of 0x8000 keeps the subtractions
+// from borrowing across lanes (see range_masks).
+__device__ __forceinline__ void word_masks(uint64_t q0, uint64_t lo, uint64_t hi, uint32_t m[4]) {
+  const int64_t a64 = (int64_t)lo - (int64_t)q0, b64 = (int64_t)hi - (int64_t)q0;
+  const uint32_t a = a64 <= 0 ? 0u : (a64 >= 8 ? 8u : (uint32_t)a64);
+  const uint32_t b = b64 <= 0 ? 0u : (b64 >= 8 ? 8u : (uint32_t)b64);
+  const uint32_t A = a * 0x00010001u, B = (b * 0x00010001u) | 0x80008000u;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-    acc += (q0 + j >= lo && q0 + j < hi) ? len16(w) : 0u;
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t idx = 0x00010000u + 0x00020002u * k;
+    const uint32_t in = ((idx | 0x80008000u) - A) & (B - (idx + 0x00010001u)) & 0x80008000u;
+    m[k] = (in >> 15) * 0xFFFFu;
   }
-  return acc;
 }
 
-// Writes the c (0..3) bytes of v at p.  With own_only false all three bytes are
-// written (c >= 1; the spare ones are overwritten by later words of the chunk);
-// otherwise the spare ones go to the dump slot, so there are no branches.
+// Output bytes of a chunk of 8 words; with word masks, words outside count 0.
+__device__ __forceinline__ uint32_t count16(const uint32_t x[4], const uint32_t* m) {
+  uint32_t l = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) l += m ? (pk_len16s(x[k]) & m[k]) : pk_len16s(x[k]);
+  return (l & 0xFFFFu) + (l >> 16);
+}
+
+// Writes the c (0..3) bytes of v at p.  With own_only false, a word with c >= 1
+// writes all three bytes (the spare ones are overwritten by later words of the
+// chunk); otherwise, and for c = 0, the bytes that are not its own go to the dump
+// slot, so there are no branches.
 __device__ __forceinline__ void put3(uint8_t* p, uint32_t v, uint32_t c, bool own_only, uint8_t* dump) {
-  *((!own_only || c >= 1) ? p : dump) = (uint8_t)v;
-  *((!own_only || c >= 2) ? p + 1 : dump) = (uint8_t)(v >> 8);
-  *((!own_only || c >= 3) ? p + 2 : dump) = (uint8_t)(v >> 16);
+  *(c >= 1 ? p : dump) = (uint8_t)v;
+  *((c >= 2 || (!own_only && c >= 1)) ? p + 1 : dump) = (uint8_t)(v >> 8);
+  *((c >= 3 || (!own_only && c >= 1)) ? p + 2 : dump) = (uint8_t)(v >> 16);
 }
 
-// One chunk of 8 words of UTF-16 -> UTF-8: validate, encode and scatter its bytes
-// to st (the chunk's first output byte).  xprev: the dword before the chunk (its
-// high half is the word before).  Returns whether an error was detected nearby.
-__device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xprev, bool full, uint64_t q0,
-                                                uint64_t lo, uint64_t hi, uint8_t* st, uint8_t* dump) {
+// One chunk of 8 words of UTF-16 -> UTF-8: validate, encode and scatter its bytes to
+// st (the chunk's first output byte).  x: the chunk with words outside the input
+// zeroed; xprev: the dword before the chunk (its high half is the word before, zero
+// before the input); m: word masks of the positions inside the input, or null when
+// all are.  Zeroed words are neither surrogate, so they flag nothing, and their
+// lengths are masked to 0.  Returns whether an error was detected nearby.
+__device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xprev, const uint32_t* m,
+                                                uint8_t* st, uint8_t* dump) {
   const uint32_t wp = xprev >> 16;
   bool det = false;
-  if (!__any(!full || any_surrogate(x, wp))) {
+  if (!__any(any_surrogate(x, wp))) {
     // no surrogate anywhere in the wave's chunks: lengths 1..3, nothing to validate.
     // Each word writes three bytes at its offset; the spare ones are overwritten by
     // the following words (each adds at least one byte), except for the last two
@@ -441,7 +454,7 @@ __device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xp
     uint32_t o = 0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const uint32_t l = pk_len16(x[kk]);
+      const uint32_t l = m ? (pk_len16(x[kk]) & m[kk]) : pk_len16(x[kk]);
       const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
       uint32_t vl, vh;
       pk_enc16(x[kk], cl, chh, vl, vh);
@@ -450,14 +463,14 @@ __device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xp
       put3(st + o, vh, chh, kk == 3, dump);
       o += chh;
     }
-  } else if (full) {
+  } else {
     uint32_t o = 0, d = 0, prevd = xprev;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const uint32_t X = x[kk];
       const uint32_t P = abyte(X, prevd, 2);  // each word's predecessor
       d |= pk_pair_err(X, P);
-      const uint32_t l = pk_len16s(X);
+      const uint32_t l = m ? (pk_len16s(X) & m[kk]) : pk_len16s(X);
       const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
       uint32_t vl, vh;
       pk_enc16s(X, P, cl, chh, vl, vh);
@@ -468,20 +481,6 @@ __device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xp
       prevd = X;
     }
     det = d != 0;
-  } else {
-    // chunk straddling the start or end of the input: word by word, real bytes only
-    uint32_t len[8], cnt;
-    analyze16<false>(x, wp, q0, lo, hi, len, cnt, det);
-    uint32_t o = 0, prev = wp;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-      const uint32_t cj = len[j];
-      const uint32_t v = enc16<true>(w, prev, cj);
-      put3(st + o, v, cj, true, dump);
-      o += cj;
-      prev = w;
-    }
   }
   return det;
 }
@@ -538,7 +537,13 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const uint64_t q0 = q00 + (uint64_t)k * TW;
-    c[k] = count16(x[k], q0, lo, hi, segfull || (q0 >= lo && q0 + 8 <= hi));
+    if (segfull || (q0 >= lo && q0 + 8 <= hi)) {
+      c[k] = count16(x[k], nullptr);
+    } else {
+      uint32_t m[4];
+      word_masks(q0, lo, hi, m);
+      c[k] = count16(x[k], m);
+    }
   }
   if (lane == 63) {
 #pragma unroll
@@ -555,8 +560,14 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
     const uint64_t q0 = q00 + (uint64_t)k * TW;
     const uint32_t hl = (wid > 0) ? halo[k * NW + wid - 1] : (k > 0 ? halo[(k - 1) * NW + NW - 1] : xp_seg);
     const uint32_t xprev = wave_shr1(x[k][3], hl);  // high half: the word before the chunk
-    const bool full = segfull || (q0 >= lo && q0 + 8 <= hi);
-    const bool det = chunk_u16_to_u8(x[k], xprev, full, q0, lo, hi, stage + PAD + off[k], stage + DUMP);
+    bool det;
+    if (segfull) {
+      det = chunk_u16_to_u8(x[k], xprev, nullptr, stage + PAD + off[k], stage + DUMP);
+    } else {
+      uint32_t m[4];
+      word_masks(q0, lo, hi, m);
+      det = chunk_u16_to_u8(x[k], xprev, m, stage + PAD + off[k], stage + DUMP);
+    }
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
       const uint16_t* in = in16 + L.mis;
@@ -589,8 +600,10 @@ __device__ uint64_t prefix_bytes16(const Launch& L, uint64_t off, uint64_t seg_u
   uint32_t x[4];
   for (uint64_t q0b = seg * seg_units; q0b < qoff; q0b += TW) {
     const uint64_t q0 = q0b + 8ull * threadIdx.x;
+    uint32_t m[4];
     load16(L, q0, x);
-    acc += count16(x, q0, L.mis, qoff, false);
+    word_masks(q0, L.mis, qoff, m);
+    acc += count16(x, m);
   }
   const uint64_t s = block_sum_u64<WG>(acc, lds);
   const uint64_t before = seg ? tile_inclusive(L.status, seg - 1) : 0;

@@ -1,8 +1,8 @@
 """Launch-configuration autotuner.
 
-For every operation it times each launch configuration the library offers (tile
-bytes x tiles per segment; for the batched call, persistent workgroups per compute
-unit) on synthetic inputs of the four script profiles, keeps the one with the least
+For every single-buffer operation it times each launch configuration the library
+offers (tile bytes x tiles per segment) on synthetic inputs of the four script
+profiles, keeps the one with the least
 total device time, and writes the choice to a JSON cache that Context.load_tuning
 applies.  Times come from HIP events on the context's stream.
 
@@ -28,7 +28,6 @@ CANDIDATES = {
     4: [(4096, 8), (8192, 8), (8192, 16)],                                  # length from UTF-8
     5: [(4096, 8), (8192, 8), (8192, 16)],                                  # length from UTF-16
 }
-BATCH_WGS = [1, 2, 3, 4]
 PROFILES = ("ascii", "latin", "cjk", "emoji")
 
 
@@ -46,7 +45,7 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(ctx, size_mib: int = 64, reps: int = 5, batch_strings: int = 20000, log=print) -> dict:
+def tune(ctx, size_mib: int = 64, reps: int = 5, log=print) -> dict:
     import numpy as np
     import torch
 
@@ -81,26 +80,6 @@ def tune(ctx, size_mib: int = 64, reps: int = 5, batch_strings: int = 20000, log
                 best = (ms, cfg)
         ctx.set_tuning(op, *best[1])
         choice[op] = [best[1][0], best[1][1], ctx.get_tuning(op)[2]]
-    # batched call: persistent workgroups per CU for long strings
-    b = synth.make_batch(batch_strings, seed_key=(0, 4), median=256, sigma=2.0, hi=4 << 20, err_frac=0.005)
-    caps = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
-    sizes = np.where(b.direction == 0, 2 * caps, caps)
-    out_off = np.concatenate([[0], np.cumsum(sizes + 16)[:-1]]).astype(np.uint64)
-    out_off += out_off % 2
-    d_in = torch.from_numpy(b.arena).cuda()
-    d_out = torch.empty(int(out_off[-1] + sizes[-1] + 64), dtype=torch.uint8, device="cuda")
-    items = utfx.pack_items(b.in_off, b.in_len, out_off, caps, b.direction)
-    bres = utfx.result_tensor(batch_strings)
-    total = int(np.sum(b.in_len))
-    best = None
-    for w in BATCH_WGS:
-        ctx.set_tuning(utfx.OP_BATCH, 8192, 4, w)
-        ms = _time(lambda: ctx.batch_run(d_in, d_out, items, batch_strings, total, bres), reps)
-        log("batch wgs_per_cu=%d %.4f ms (%d strings, %.1f MB)" % (w, ms, batch_strings, b.arena.size / 1e6))
-        if best is None or ms < best[0]:
-            best = (ms, w)
-    ctx.set_tuning(utfx.OP_BATCH, 8192, 4, best[1])
-    choice[utfx.OP_BATCH] = [8192, 4, best[1]]
     return {"device": torch.cuda.get_device_name(0), "size_mib": size_mib, "ops": {str(k): v for k, v in choice.items()}}
 
 
