@@ -101,6 +101,15 @@ __device__ __forceinline__ uint32_t zx_hi(uint32_t v) { return perm(0u, v, 0x0C0
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ us2 as_us2(uint32_t v) { return __builtin_bit_cast(us2, v); }
 __device__ __forceinline__ uint32_t as_u32(us2 v) { return __builtin_bit_cast(uint32_t, v); }
+// 1 in each nonzero 16-bit lane of x, 0 in each zero lane: one v_pk_min_u16 against
+// (1, 1).  Written out because the compiler turns min(x, 1) into a compare and a
+// select per lane.
+__device__ __forceinline__ uint32_t pk_nz(uint32_t x) {
+  uint32_t r;
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(x), "s"(0x00010001u));
+  return r;
+}
+
 // lane-wise a*m + c (mod 2^16), one v_pk_mad_u16
 __device__ __forceinline__ uint32_t pk_mad(uint32_t a, uint16_t m, uint32_t c) {
   us2 r = as_us2(a) * (us2)(m) + as_us2(c);

@@ -391,10 +391,7 @@ __device__ __forceinline__ uint32_t enc16(uint32_t w, uint32_t prev, uint32_t c)
 // in waves without surrogates.  Output bytes per word: 1 + [w >= 0x80] + [w >= 0x800].
 __device__ __forceinline__ uint32_t pk_len16(uint32_t X) {
   const us2 w = as_us2(X);
-  const us2 one = (us2)(1);
-  const us2 a = __builtin_elementwise_min(w >> (us2)(7), one);
-  const us2 b = __builtin_elementwise_min(w >> (us2)(11), one);
-  return as_u32(a + b + one);
+  return pk_nz(as_u32(w >> (us2)(7))) + pk_nz(as_u32(w >> (us2)(11))) + 0x00010001u;
 }
 
 // UTF-8 bytes of the two words of X (little-endian in a dword each), given their

@@ -353,21 +353,16 @@ typedef short ss2 __attribute__((ext_vector_type(2)));
 // 2 for each half of a surrogate pair, else 3 (section 7.3).
 __device__ __forceinline__ uint32_t pk_len16s(uint32_t X) {
   const us2 w = as_us2(X);
-  const us2 one = (us2)(1);
-  const us2 a = __builtin_elementwise_min(w >> (us2)(7), one);
-  const us2 b = __builtin_elementwise_min(w >> (us2)(11), one);
-  const us2 ns = __builtin_elementwise_min(as_us2((X & 0xF800F800u) ^ 0xD800D800u), one);  // not a surrogate
-  return as_u32(a + b + ns);
+  return pk_nz(as_u32(w >> (us2)(7))) + pk_nz(as_u32(w >> (us2)(11))) + pk_nz((X & 0xF800F800u) ^ 0xD800D800u);
 }
 
 // Lane-wise unpaired-surrogate detection for the words of X, with P holding each
 // word's predecessor: a word is flagged when "is a low surrogate" differs from "the
 // word before is a high surrogate" (sections 2.1 and 7.4).
 __device__ __forceinline__ uint32_t pk_pair_err(uint32_t X, uint32_t P) {
-  const us2 one = (us2)(1);
-  const us2 a = __builtin_elementwise_min(as_us2((X & 0xFC00FC00u) ^ 0xDC00DC00u), one);  // 0: low surrogate
-  const us2 b = __builtin_elementwise_min(as_us2((P & 0xFC00FC00u) ^ 0xD800D800u), one);  // 0: after a high
-  return as_u32(a ^ b);
+  const uint32_t a = pk_nz((X & 0xFC00FC00u) ^ 0xDC00DC00u);  // 0: a low surrogate
+  const uint32_t b = pk_nz((P & 0xFC00FC00u) ^ 0xD800D800u);  // 0: after a high surrogate
+  return a ^ b;  // nonzero lanes: unpaired
 }
 
 // UTF-8 bytes of the two words of X with surrogates (little-endian in a dword each),
@@ -382,9 +377,8 @@ __device__ __forceinline__ uint32_t pk_pair_err(uint32_t X, uint32_t P) {
 __device__ __forceinline__ void pk_enc16s(uint32_t X, uint32_t P, uint32_t c_lo, uint32_t c_hi, uint32_t& v_lo,
                                           uint32_t& v_hi) {
   const us2 w = as_us2(X);
-  const us2 one = (us2)(1);
-  const uint32_t ns = as_u32(__builtin_elementwise_min(as_us2((X & 0xF800F800u) ^ 0xD800D800u), one));
-  const uint32_t mS = as_u32(as_us2(ns) - one);                     // 0xFFFF: surrogate
+  const uint32_t ns = pk_nz((X & 0xF800F800u) ^ 0xD800D800u);      // 1: not a surrogate
+  const uint32_t mS = as_u32(as_us2(ns) - (us2)(1));                // 0xFFFF: surrogate
   const uint32_t b10 = as_u32(__builtin_bit_cast(us2, __builtin_bit_cast(ss2, X << 5) >> (ss2)(15)));
   const uint32_t mH = mS & ~b10, mL = mS & b10;                     // high / low surrogate lanes
   const uint32_t D = as_u32((w - (us2)(0xD7C0)) >> (us2)(2));
@@ -435,6 +429,12 @@ __device__ __forceinline__ void put3(uint8_t* p, uint32_t v, uint32_t c, bool ow
   *((c >= 2 || (!own_only && c >= 1)) ? p + 1 : dump) = (uint8_t)(v >> 8);
   *((c >= 3 || (!own_only && c >= 1)) ? p + 2 : dump) = (uint8_t)(v >> 16);
 }
+// The same for a word known to have c >= 1 that may write spare bytes.
+__device__ __forceinline__ void put3_all(uint8_t* p, uint32_t v) {
+  p[0] = (uint8_t)v;
+  p[1] = (uint8_t)(v >> 8);
+  p[2] = (uint8_t)(v >> 16);
+}
 
 // One chunk of 8 words of UTF-16 -> UTF-8: validate, encode and scatter its bytes to
 // st (the chunk's first output byte).  x: the chunk with words outside the input
@@ -442,47 +442,55 @@ __device__ __forceinline__ void put3(uint8_t* p, uint32_t v, uint32_t c, bool ow
 // before the input); m: word masks of the positions inside the input, or null when
 // all are.  Zeroed words are neither surrogate, so they flag nothing, and their
 // lengths are masked to 0.  Returns whether an error was detected nearby.
-__device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xprev, const uint32_t* m,
-                                                uint8_t* st, uint8_t* dump) {
+template <bool MASKED>
+__device__ __forceinline__ bool chunk_u16_to_u8_t(const uint32_t x[4], uint32_t xprev, const uint32_t* m,
+                                                  uint8_t* st, uint8_t* dump) {
   const uint32_t wp = xprev >> 16;
   bool det = false;
+  uint32_t o = 0;
+  // a word of an unmasked chunk has c >= 1, so words 0..5 may write all three bytes
+  auto put = [&](uint32_t v, uint32_t c, int kk) {
+    if (!MASKED && kk < 3) put3_all(st + o, v);
+    else put3(st + o, v, c, kk == 3, dump);
+    o += c;
+  };
   if (!__any(any_surrogate(x, wp))) {
     // no surrogate anywhere in the wave's chunks: lengths 1..3, nothing to validate.
     // Each word writes three bytes at its offset; the spare ones are overwritten by
     // the following words (each adds at least one byte), except for the last two
     // words of the chunk, which write only their own bytes.
-    uint32_t o = 0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const uint32_t l = m ? (pk_len16(x[kk]) & m[kk]) : pk_len16(x[kk]);
+      const uint32_t l = MASKED ? (pk_len16(x[kk]) & m[kk]) : pk_len16(x[kk]);
       const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
       uint32_t vl, vh;
       pk_enc16(x[kk], cl, chh, vl, vh);
-      put3(st + o, vl, cl, kk == 3, dump);
-      o += cl;
-      put3(st + o, vh, chh, kk == 3, dump);
-      o += chh;
+      put(vl, cl, kk);
+      put(vh, chh, kk);
     }
   } else {
-    uint32_t o = 0, d = 0, prevd = xprev;
+    uint32_t d = 0, prevd = xprev;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const uint32_t X = x[kk];
       const uint32_t P = abyte(X, prevd, 2);  // each word's predecessor
       d |= pk_pair_err(X, P);
-      const uint32_t l = m ? (pk_len16s(X) & m[kk]) : pk_len16s(X);
+      const uint32_t l = MASKED ? (pk_len16s(X) & m[kk]) : pk_len16s(X);
       const uint32_t cl = l & 0xFFFFu, chh = l >> 16;
       uint32_t vl, vh;
       pk_enc16s(X, P, cl, chh, vl, vh);
-      put3(st + o, vl, cl, kk == 3, dump);
-      o += cl;
-      put3(st + o, vh, chh, kk == 3, dump);
-      o += chh;
+      put(vl, cl, kk);
+      put(vh, chh, kk);
       prevd = X;
     }
     det = d != 0;
   }
   return det;
+}
+
+__device__ __forceinline__ bool chunk_u16_to_u8(const uint32_t x[4], uint32_t xprev, const uint32_t* m,
+                                                uint8_t* st, uint8_t* dump) {
+  return m ? chunk_u16_to_u8_t<true>(x, xprev, m, st, dump) : chunk_u16_to_u8_t<false>(x, xprev, m, st, dump);
 }
 
 // LDS of one UTF-16 -> UTF-8 segment: the stage holds the segment's output bytes.
