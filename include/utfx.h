@@ -100,7 +100,8 @@ utfx_status utfx_set_stream(utfx_ctx *ctx, void *hip_stream);
  *             registers and its output in LDS, so they take only these pairs:
  *             UTF-8 -> UTF-16 (4096, 2, 4 or 8), (8192, 2 or 4); UTF-16 -> UTF-8
  *             (4096 or 8192, 2, 4 or 8);
- * wgs_per_cu: 1..16, recorded with the other values; no kernel of this version uses it.
+ * wgs_per_cu: 0..16, recorded with the other values; no kernel of this version uses it
+ *             (every launch is one workgroup per segment).
  * Returns UTFX_E_INVALID_ARG for an unsupported value. */
 typedef enum {
   UTFX_OP_UTF8_TO_UTF16 = 0,
@@ -215,8 +216,11 @@ void utfx_graph_destroy(utfx_graph *graph);
  * arrival order) into one step: host-to-device copy, one utfx_batch_run, device-to-
  * host copy of results and outputs.  Requests arriving meanwhile join the next step
  * (continuous batching); with inflight >= 2, steps overlap.  When a step completes,
- * each request's output (its valid prefix, `written` units) is copied to its `out`
- * buffer and a completion {tag, result} is reported.  A request larger than an arena
+ * each request's output (its valid prefix, `written` units) is in its `out` buffer
+ * and a completion {tag, result} is reported.  Requests of 64 KiB or more whose
+ * payload or output buffer is pinned host memory skip the staging copy: that data
+ * moves by DMA straight between the buffer and the device (a direct output is copied
+ * whole, so out[written:out_cap] then holds unspecified values).  A request larger than an arena
  * completes with UTFX_E_INVALID_ARG.  Payloads and outputs must stay valid until the
  * request completes.  Single-threaded: one thread drives a server. */
 typedef struct utfx_server utfx_server;

@@ -190,7 +190,10 @@ class Context:
     def last_error(self) -> str:
         return (self._lib.utfx_last_error(self._h) or b"").decode()
 
-    def set_tuning(self, op: int, tile_bytes: int, tiles_per_segment: int = 8, wgs_per_cu: int = 4):
+    def set_tuning(self, op: int, tile_bytes: int, tiles_per_segment: int = 8, wgs_per_cu=None):
+        """wgs_per_cu None keeps the current value."""
+        if wgs_per_cu is None:
+            wgs_per_cu = self.get_tuning(op)[2]
         st = self._lib.utfx_set_tuning(self._h, op, tile_bytes, tiles_per_segment, wgs_per_cu)
         if st != OK:
             raise UtfxError("bad tuning %r" % ((op, tile_bytes, tiles_per_segment, wgs_per_cu),))

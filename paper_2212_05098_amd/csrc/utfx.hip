@@ -180,15 +180,17 @@ UTFX_DEFINE_LAUNCH(launch_val16, k_validate16)
 // Transcode kernels are instantiated per (workgroup size, tiles per segment); a whole
 // segment's output is staged in LDS (up to 96 KiB of the 160 KiB a gfx950 workgroup
 // may use).
+#define UTFX_LAUNCH_WS(K, WG, S) hipLaunchKernelGGL((K<WG, S>), g, dim3(WG), 0, s, L)
+
 hipError_t launch_u8u16(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {
   const dim3 g((uint32_t)grid);
   if (wg == 256) {
-    if (L.seg == 2) hipLaunchKernelGGL((k_u8_to_u16<256, 2>), g, dim3(256), 0, s, L);
-    else if (L.seg == 4) hipLaunchKernelGGL((k_u8_to_u16<256, 4>), g, dim3(256), 0, s, L);
-    else hipLaunchKernelGGL((k_u8_to_u16<256, 8>), g, dim3(256), 0, s, L);
+    if (L.seg == 2) UTFX_LAUNCH_WS(k_u8_to_u16, 256, 2);
+    else if (L.seg == 4) UTFX_LAUNCH_WS(k_u8_to_u16, 256, 4);
+    else UTFX_LAUNCH_WS(k_u8_to_u16, 256, 8);
   } else {
-    if (L.seg == 2) hipLaunchKernelGGL((k_u8_to_u16<512, 2>), g, dim3(512), 0, s, L);
-    else hipLaunchKernelGGL((k_u8_to_u16<512, 4>), g, dim3(512), 0, s, L);
+    if (L.seg == 2) UTFX_LAUNCH_WS(k_u8_to_u16, 512, 2);
+    else UTFX_LAUNCH_WS(k_u8_to_u16, 512, 4);
   }
   return hipGetLastError();
 }
@@ -196,13 +198,13 @@ hipError_t launch_u8u16(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t
 hipError_t launch_u16u8(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {
   const dim3 g((uint32_t)grid);
   if (wg == 256) {
-    if (L.seg == 2) hipLaunchKernelGGL((k_u16_to_u8<256, 2>), g, dim3(256), 0, s, L);
-    else if (L.seg == 4) hipLaunchKernelGGL((k_u16_to_u8<256, 4>), g, dim3(256), 0, s, L);
-    else hipLaunchKernelGGL((k_u16_to_u8<256, 8>), g, dim3(256), 0, s, L);
+    if (L.seg == 2) UTFX_LAUNCH_WS(k_u16_to_u8, 256, 2);
+    else if (L.seg == 4) UTFX_LAUNCH_WS(k_u16_to_u8, 256, 4);
+    else UTFX_LAUNCH_WS(k_u16_to_u8, 256, 8);
   } else {
-    if (L.seg == 2) hipLaunchKernelGGL((k_u16_to_u8<512, 2>), g, dim3(512), 0, s, L);
-    else if (L.seg == 4) hipLaunchKernelGGL((k_u16_to_u8<512, 4>), g, dim3(512), 0, s, L);
-    else hipLaunchKernelGGL((k_u16_to_u8<512, 8>), g, dim3(512), 0, s, L);
+    if (L.seg == 2) UTFX_LAUNCH_WS(k_u16_to_u8, 512, 2);
+    else if (L.seg == 4) UTFX_LAUNCH_WS(k_u16_to_u8, 512, 4);
+    else UTFX_LAUNCH_WS(k_u16_to_u8, 512, 8);
   }
   return hipGetLastError();
 }
@@ -372,13 +374,12 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
   for (int i = 0; i < UTFX_OP_COUNT_; ++i) {
     c->tile_bytes[i] = 8192;
     c->seg_tiles[i] = 8;
-    c->wgs_per_cu[i] = 4;
+    c->wgs_per_cu[i] = 0;
   }
   c->tile_bytes[UTFX_OP_UTF8_TO_UTF16] = 8192;
   c->seg_tiles[UTFX_OP_UTF8_TO_UTF16] = 4;
   c->tile_bytes[UTFX_OP_UTF16_TO_UTF8] = 8192;
   c->seg_tiles[UTFX_OP_UTF16_TO_UTF8] = 4;
-  c->wgs_per_cu[UTFX_OP_BATCH] = 2;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
     int cus = 0;
@@ -420,7 +421,7 @@ utfx_status utfx_set_stream(utfx_ctx* c, void* hip_stream) {
 utfx_status utfx_set_tuning(utfx_ctx* c, int op, uint32_t tile_bytes, uint32_t tiles_per_segment,
                             uint32_t wgs_per_cu) {
   if (!c || op < 0 || op >= UTFX_OP_COUNT_ || !valid_tile(tile_bytes) || tiles_per_segment < 1 ||
-      tiles_per_segment > 256 || wgs_per_cu < 1 || wgs_per_cu > 16 ||
+      tiles_per_segment > 256 || wgs_per_cu > 16 ||
       !transcode_config_ok(op, tile_bytes, tiles_per_segment))
     return UTFX_E_INVALID_ARG;
   c->tile_bytes[op] = tile_bytes;
@@ -483,7 +484,7 @@ utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes
                            utfx_result* d_results) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
-  utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, c->wgs_per_cu[UTFX_OP_BATCH], in_arena,
+  utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, in_arena,
                              in_bytes, out_arena, out_bytes, d_items, n_items, total_in_units, d_results, c->err,
                              sizeof(c->err));
   if (st == UTFX_OK && c->capturing) c->cap_batches++;

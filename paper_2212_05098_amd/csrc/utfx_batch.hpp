@@ -191,13 +191,6 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
   }
 }
 
-// A value the whole wave holds, moved to scalar registers.
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
@@ -422,10 +415,14 @@ __global__ void __launch_bounds__(BWG) k_batch_large(BatchArgs A) {
   const uint64_t seg = t - A.unit_start[i];
   if (DIR == 0) {
     __shared__ __attribute__((aligned(16))) Seg8Smem<BWG, BS8> sm;
-    seg_u8_to_u16<BWG, BS8>(L, seg, sm);
+    uint32_t x[BS8][4];
+    load_seg8<BWG, BS8>(L, seg, x);
+    seg_u8_to_u16<BWG, BS8>(L, seg, sm, x);
   } else {
     __shared__ __attribute__((aligned(16))) Seg16Smem<BWG, BS16> sm;
-    seg_u16_to_u8<BWG, BS16>(L, seg, sm);
+    uint32_t x[BS16][4];
+    load_seg16<BWG, BS16>(L, seg, x);
+    seg_u16_to_u8<BWG, BS16>(L, seg, sm, x);
   }
 }
 
@@ -547,7 +544,7 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   return batch_ws_clear(b, s);
 }
 
-inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_cus, uint32_t wgs_per_cu,
+inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_cus,
                              const uint8_t* in,
                              uint64_t in_bytes, uint8_t* out, uint64_t out_bytes, const utfx_item* d_items,
                              uint32_t n_items, uint64_t total_in_units, utfx_result* d_results, char* err,

@@ -46,8 +46,25 @@ struct Slot {
   utfx_result* h_res = nullptr;
   utfx_result* d_res = nullptr;
   std::vector<Req> reqs;
+  std::vector<uint8_t> direct_out;  // per request: output copied straight to its buffer
+  std::vector<uint64_t> direct_in_off, direct_out_off;
   bool busy = false;
 };
+
+// Requests at least this large whose host buffers are pinned skip the staging copy:
+// their payload and output move by DMA straight between the request's buffer and the
+// device arena.
+constexpr uint64_t kDirectMin = 64 << 10;
+
+inline bool is_pinned(const void* p) {
+  hipPointerAttribute_t a;
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory: clear the error the query left
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
 
 inline uint64_t now_ns() {
   timespec ts;
@@ -111,18 +128,44 @@ inline uint64_t out_bytes(const Req& r) { return r.out_cap * (r.dir ? 1 : 2); }
 // UTFX_E_INVALID_ARG on the next progress call).
 inline uint32_t launch_step(utfx_server* S, Slot& s, utfx_status* st) {
   const utfx_server_config& c = S->cfg;
-  uint64_t in_used = 0, out_used = 0, units = 0;
+  // staged data grows from the start of each arena, direct data from its end
+  uint64_t in_lo = 0, out_lo = 0, in_hi = c.arena_in_bytes, out_hi = c.arena_out_bytes, units = 0;
   s.reqs.clear();
+  s.direct_out.clear();
+  s.direct_in_off.clear();
+  s.direct_out_off.clear();
+  std::vector<uint32_t> direct_in_idx;
   while (!S->pending.empty() && s.reqs.size() < c.max_items) {
     const Req& r = S->pending.front();
-    const uint64_t io = al16(in_used), oo = al16(out_used);
     if (r.dir > 1 || in_bytes(r) > c.arena_in_bytes || out_bytes(r) > c.arena_out_bytes) {
       S->rejected.push_back(r.tag);
       S->pending.pop_front();
       continue;
     }
-    if (io + in_bytes(r) > c.arena_in_bytes || oo + out_bytes(r) > c.arena_out_bytes) break;
-    if (in_bytes(r)) memcpy(s.h_in + io, r.data, in_bytes(r));
+    const bool din = in_bytes(r) >= kDirectMin && is_pinned(r.data);
+    const bool dout = out_bytes(r) >= kDirectMin && is_pinned(r.out);
+    uint64_t io, oo, nlo = in_lo, nhi = in_hi, olo = out_lo, ohi = out_hi;
+    if (din) {
+      if (in_bytes(r) > nhi) break;
+      io = nhi = (nhi - in_bytes(r)) & ~15ull;
+    } else {
+      io = al16(nlo);
+      nlo = io + in_bytes(r);
+    }
+    if (dout) {
+      if (out_bytes(r) > ohi) break;
+      oo = ohi = (ohi - out_bytes(r)) & ~15ull;
+    } else {
+      oo = al16(olo);
+      olo = oo + out_bytes(r);
+    }
+    if (nlo > nhi || olo > ohi) break;  // no room left in this step
+    in_lo = nlo;
+    in_hi = nhi;
+    out_lo = olo;
+    out_hi = ohi;
+    if (din) direct_in_idx.push_back((uint32_t)s.reqs.size());
+    else if (in_bytes(r)) memcpy(s.h_in + io, r.data, in_bytes(r));
     utfx_item& it = s.h_items[s.reqs.size()];
     it.in_off = io;
     it.in_len = r.len;
@@ -130,23 +173,32 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, utfx_status* st) {
     it.out_cap = r.out_cap;
     it.dir = r.dir;
     it.pad = 0;
-    in_used = io + in_bytes(r);
-    out_used = oo + out_bytes(r);
     units += r.len;
     s.reqs.push_back(r);
+    s.direct_out.push_back(dout ? 1 : 0);
     S->pending.pop_front();
   }
   const uint32_t n = (uint32_t)s.reqs.size();
   if (!n) return 0;
   hipError_t e = hipMemcpyAsync(s.d_items, s.h_items, n * sizeof(utfx_item), hipMemcpyHostToDevice, s.stream);
-  if (e == hipSuccess && in_used) e = hipMemcpyAsync(s.d_in, s.h_in, in_used, hipMemcpyHostToDevice, s.stream);
+  if (e == hipSuccess && in_lo) e = hipMemcpyAsync(s.d_in, s.h_in, in_lo, hipMemcpyHostToDevice, s.stream);
+  for (uint32_t k : direct_in_idx) {
+    if (e != hipSuccess) break;
+    e = hipMemcpyAsync(s.d_in + s.h_items[k].in_off, s.reqs[k].data, in_bytes(s.reqs[k]), hipMemcpyHostToDevice,
+                       s.stream);
+  }
   utfx_status bs = UTFX_OK;
   if (e == hipSuccess)
     bs = utfx_batch_run(s.ctx, s.d_in, c.arena_in_bytes, s.d_out, c.arena_out_bytes, s.d_items, n, units, s.d_res);
   if (e == hipSuccess && bs == UTFX_OK)
     e = hipMemcpyAsync(s.h_res, s.d_res, n * sizeof(utfx_result), hipMemcpyDeviceToHost, s.stream);
-  if (e == hipSuccess && bs == UTFX_OK && out_used)
-    e = hipMemcpyAsync(s.h_out, s.d_out, out_used, hipMemcpyDeviceToHost, s.stream);
+  if (e == hipSuccess && bs == UTFX_OK && out_lo)
+    e = hipMemcpyAsync(s.h_out, s.d_out, out_lo, hipMemcpyDeviceToHost, s.stream);
+  for (uint32_t k = 0; k < n && e == hipSuccess && bs == UTFX_OK; ++k) {
+    if (s.direct_out[k])
+      e = hipMemcpyAsync(s.reqs[k].out, s.d_out + s.h_items[k].out_off, out_bytes(s.reqs[k]), hipMemcpyDeviceToHost,
+                         s.stream);
+  }
   if (e == hipSuccess && bs == UTFX_OK) e = hipEventRecord(s.done, s.stream);
   if (e != hipSuccess || bs != UTFX_OK) {
     snprintf(S->err, sizeof(S->err), "step launch: %s / status %d", hipGetErrorString(e), (int)bs);
@@ -229,7 +281,8 @@ utfx_status utfx_server_progress(utfx_server* S, utfx_completion* done, uint32_t
       const utfx_result& res = s.h_res[i];
       const uint64_t w = res.written < r.out_cap ? res.written : r.out_cap;
       const uint64_t ob = w * (r.dir ? 1 : 2);
-      if (ob && res.status != UTFX_E_OUTPUT_TOO_SMALL) memcpy(r.out, s.h_out + s.h_items[i].out_off, ob);
+      if (ob && res.status != UTFX_E_OUTPUT_TOO_SMALL && !s.direct_out[i])
+        memcpy(r.out, s.h_out + s.h_items[i].out_off, ob);
       utfx_completion& c = done[(*n_done)++];
       c.tag = r.tag;
       c.result = res;

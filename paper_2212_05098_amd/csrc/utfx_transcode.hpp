@@ -20,6 +20,13 @@
 
 namespace utfx_dev {
 
+// A value the whole wave holds, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // DPP wave_shr:1 -- lane i gets lane i-1's v; lane 0 gets `first`.
 __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t first) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x138, 0xF, 0xF, false);
@@ -212,9 +219,30 @@ struct Seg8Smem {
   uint32_t bounds[2];
 };
 
-// One segment of a UTF-8 -> UTF-16LE transcode (segment `seg` of the buffer L).
+// Loads segment `seg` of a UTF-8 buffer: chunk k of thread t is the 16 bytes at grid
+// position seg * SEGB + 16 * (k * WG + t); bytes outside the input read as 0.
 template <int WG, int S>
-__device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg8Smem<WG, S>& sm) {
+__device__ __forceinline__ void load_seg8(const Launch& L, uint64_t seg, uint32_t (&x)[S][4]) {
+  constexpr uint32_t T = 16u * WG;
+  const uint64_t s0 = seg * (uint64_t)(T * S);
+  const uint64_t q00 = s0 + 16ull * threadIdx.x;
+  if (s0 >= L.mis && s0 + T * S <= L.mis + L.n) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint4 v = *reinterpret_cast<const uint4*>(L.base + q00 + (uint64_t)k * T);
+      x[k][0] = v.x; x[k][1] = v.y; x[k][2] = v.z; x[k][3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < S; ++k) load8(L, q00 + (uint64_t)k * T, x[k]);
+  }
+}
+
+// One segment of a UTF-8 -> UTF-16LE transcode (segment `seg` of the buffer L, loaded
+// into x).
+template <int WG, int S>
+__device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg8Smem<WG, S>& sm,
+                                              const uint32_t (&x)[S][4]) {
   typedef Seg8Smem<WG, S> M;
   constexpr int NW = M::NW;
   constexpr uint32_t T = 16u * WG;
@@ -232,18 +260,7 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
   const uint64_t lo = L.mis, hi = L.mis + L.n;
   const bool segfull = s0 >= lo && s0 + SEGB <= hi;
 
-  // ---- phase A: load the segment, count, scan
-  uint32_t x[S][4];
-  if (segfull) {
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-      const uint4 v = *reinterpret_cast<const uint4*>(L.base + q00 + (uint64_t)k * T);
-      x[k][0] = v.x; x[k][1] = v.y; x[k][2] = v.z; x[k][3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < S; ++k) load8(L, q00 + (uint64_t)k * T, x[k]);
-  }
+  // ---- phase A: the segment is in x (loaded by the caller); count, scan
   const uint32_t xp_seg = (threadIdx.x == 0) ? load8_prev(L, s0) : 0u;
   uint32_t c[S];
 #pragma unroll
@@ -302,7 +319,9 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
 template <int WG, int S>
 __global__ void __launch_bounds__(WG) k_u8_to_u16(Launch L) {
   __shared__ __attribute__((aligned(16))) Seg8Smem<WG, S> sm;
-  seg_u8_to_u16<WG, S>(L, blockIdx.x, sm);
+  uint32_t x[S][4];
+  load_seg8<WG, S>(L, blockIdx.x, x);
+  seg_u8_to_u16<WG, S>(L, blockIdx.x, sm, x);
 }
 
 // Words of the valid prefix in[0:off]: the exclusive prefix of off's segment plus the
@@ -507,9 +526,29 @@ struct Seg16Smem {
   unsigned long long seg_base;
 };
 
-// One segment of a UTF-16LE -> UTF-8 transcode.
+// Loads segment `seg` of a UTF-16 buffer (words outside the input read as 0).
 template <int WG, int S>
-__device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg16Smem<WG, S>& sm) {
+__device__ __forceinline__ void load_seg16(const Launch& L, uint64_t seg, uint32_t (&x)[S][4]) {
+  constexpr uint32_t TW = 8u * WG;
+  const uint64_t s0 = seg * (uint64_t)(TW * S);
+  const uint64_t q00 = s0 + 8ull * threadIdx.x;
+  const uint16_t* in16 = reinterpret_cast<const uint16_t*>(L.base);
+  if (s0 >= L.mis && s0 + TW * S <= L.mis + L.n) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const uint4 v = *reinterpret_cast<const uint4*>(in16 + q00 + (uint64_t)k * TW);
+      x[k][0] = v.x; x[k][1] = v.y; x[k][2] = v.z; x[k][3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < S; ++k) load16(L, q00 + (uint64_t)k * TW, x[k]);
+  }
+}
+
+// One segment of a UTF-16LE -> UTF-8 transcode (loaded into x; see seg_u8_to_u16).
+template <int WG, int S>
+__device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg16Smem<WG, S>& sm,
+                                              const uint32_t (&x)[S][4]) {
   typedef Seg16Smem<WG, S> M;
   constexpr int NW = M::NW;
   constexpr uint32_t TW = 8u * WG;      // words per tile
@@ -527,18 +566,7 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
   const bool segfull = s0 >= lo && s0 + SEGW <= hi;
   const uint16_t* in16 = reinterpret_cast<const uint16_t*>(L.base);
 
-  // ---- phase A
-  uint32_t x[S][4];
-  if (segfull) {
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-      const uint4 v = *reinterpret_cast<const uint4*>(in16 + q00 + (uint64_t)k * TW);
-      x[k][0] = v.x; x[k][1] = v.y; x[k][2] = v.z; x[k][3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < S; ++k) load16(L, q00 + (uint64_t)k * TW, x[k]);
-  }
+  // ---- phase A: the segment is in x (loaded by the caller)
   // the word before the segment, in the high half (the layout of a chunk's last dword)
   const uint32_t xp_seg = (threadIdx.x == 0) ? (load16_prev(L, s0) << 16) : 0u;
   uint32_t c[S];
@@ -596,7 +624,9 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
 template <int WG, int S>
 __global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
   __shared__ __attribute__((aligned(16))) Seg16Smem<WG, S> sm;
-  seg_u16_to_u8<WG, S>(L, blockIdx.x, sm);
+  uint32_t x[S][4];
+  load_seg16<WG, S>(L, blockIdx.x, x);
+  seg_u16_to_u8<WG, S>(L, blockIdx.x, sm, x);
 }
 
 template <int WG>

@@ -13,7 +13,7 @@ kernel sources; bench.py reports the traffic only while the sources still match.
 Usage:
   python -m paper_2212_05098_amd.profsum stats DIR --cmd "..."             > summary.txt
   python -m paper_2212_05098_amd.profsum traffic FETCH_DIR WRITE_DIR --kernel NAME
-         --case "emoji utf16le->utf8" --copy-bytes 268435456 --cmd "..." > summary.txt
+         --case "utf8->utf16le, one launch per profile (ascii,latin,cjk,emoji)" --copy-bytes 268435456 --cmd "..." > summary.txt
 """
 from __future__ import annotations
 
@@ -26,7 +26,8 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ("csrc/utfx.hip", "csrc/utfx_kernels.hpp", "csrc/utfx_device.hpp", "csrc/utfx_batch.hpp")
+SOURCES = ("csrc/utfx.hip", "csrc/utfx_kernels.hpp", "csrc/utfx_device.hpp", "csrc/utfx_transcode.hpp",
+           "csrc/utfx_batch.hpp")
 COPY_KERNEL = "copyBuffer"
 
 
@@ -71,7 +72,7 @@ def stats_text(d: str, cmd: str, cycle=None) -> str:
     if cycle:
         out.append("# per input (dispatch i of a kernel ran on input i mod %d)" % len(cycle))
         for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
-            if not k.startswith("void utfx_dev::k_") or "fin" in k or len(v) % len(cycle):
+            if not ("k_u8_to_u16<" in k or "k_u16_to_u8<" in k) or len(v) % len(cycle):
                 continue
             for j, name in enumerate(cycle):
                 w = v[j::len(cycle)]

@@ -22,6 +22,7 @@ TILES = (
     {"u8": (4096, 4), "u16": (4096, 8), "other": (8192, 3)},
     {"u8": (8192, 2), "u16": (8192, 4), "other": (8192, 8)},
     {"u8": (4096, 8), "u16": (8192, 8), "other": (4096, 32)},
+    {"u8": (8192, 2), "u16": (4096, 2), "other": (8192, 4)},
 )
 OPS = (utfx.OP_UTF8_TO_UTF16, utfx.OP_UTF16_TO_UTF8, utfx.OP_VALIDATE_UTF8, utfx.OP_VALIDATE_UTF16,
        utfx.OP_LENGTH_UTF8, utfx.OP_LENGTH_UTF16)
@@ -177,7 +178,7 @@ def test_utf16_error_at_every_chunk_offset(ctx):
             assert r.count == off
 
 
-@pytest.mark.parametrize("T,seg", [(4096, 2), (4096, 8), (8192, 4)])
+@pytest.mark.parametrize("T,seg", [(4096, 2), (4096, 8), (8192, 4), (8192, 2)])
 def test_tile_edges(ctx, T, seg):
     rng = synth.rng_for(16, T, seg)
     set_tile(ctx, (T, seg))
