@@ -1,7 +1,7 @@
 // utfx.hip -- host runtime and C ABI of libutfx.so (see include/utfx.h).
 //
 // The context owns a device workspace (a 64-byte header of counters and a status
-// word per tile for the look-back), a device result slot and a pinned host copy of
+// word per segment for the look-back, STATUS_STRIDE words apart), a device result slot and a pinned host copy of
 // it.  A call checks its arguments, sizes the grid, launches one kernel on the
 // context's stream and, for the synchronous entry points, copies the 24-byte result
 // back.  Kernels reset the workspace counters themselves (the last workgroup of every
@@ -81,7 +81,7 @@ void set_msg(utfx_ctx* c, const char* what) {
 
 // (Re)initialises the header and clears every status word.  Synchronous.
 utfx_status init_ws(utfx_ctx* c) {
-  hipError_t e = hipMemsetAsync(c->status, 0, c->cap_tiles * sizeof(unsigned long long), c->stream);
+  hipError_t e = hipMemsetAsync(c->status, 0, c->cap_tiles * STATUS_STRIDE * sizeof(unsigned long long), c->stream);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, c->stream, c->ws);
     e = hipGetLastError();
@@ -97,7 +97,7 @@ utfx_status init_ws(utfx_ctx* c) {
 
 utfx_status alloc_ws(utfx_ctx* c, uint64_t tiles) {
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, sizeof(WsHeader) + tiles * sizeof(unsigned long long));
+  hipError_t e = hipMalloc(&p, sizeof(WsHeader) + tiles * STATUS_STRIDE * sizeof(unsigned long long));
   if (e != hipSuccess) {
     set_err(c, "workspace allocation", e);
     return UTFX_E_DEVICE;

@@ -54,10 +54,10 @@ struct BatchArgs {
   WsHeader* ws;
   unsigned long long* unit_start;    // n_items: an item's first segment in its direction's numbering
   unsigned long long* item_err;      // n_items: first error of a large item
-  unsigned long long* status[2];     // cap_units each: look-back status word per segment
+  unsigned long long* status[2];     // cap_units each: look-back status word per segment (strided)
   uint32_t* unit_item[2];            // cap_units each: item of each segment
   uint32_t* large;                   // n_items: list of large items
-  unsigned long long* plan_status[2];  // one status word per plan workgroup and direction
+  unsigned long long* plan_status[2];  // one status word per plan workgroup and direction (strided)
   uint64_t cap_units;
   uint64_t total_in;                 // the caller's bound on the sum of in_len
 };
@@ -105,7 +105,7 @@ __device__ __forceinline__ Launch item_launch(const BatchArgs& A, const BItem& i
   L.cap = it.out_cap;
   L.ws = A.ws;
   L.err = A.item_err + i;
-  L.status = A.status[it.dir] + A.unit_start[i];
+  L.status = A.status[it.dir] + A.unit_start[i] * STATUS_STRIDE;
   L.result = A.results + i;
   L.ntiles = item_units(A, it);
   L.seg_units = it.dir ? BSEG16 : BSEG8;
@@ -486,8 +486,8 @@ inline hipError_t batch_ws_clear(BatchWs& b, hipStream_t s) {
   const size_t plan_words = (b.cap_items + utfx_dev::PLAN_WG - 1) / utfx_dev::PLAN_WG;  // >= plan blocks
   hipError_t e = hipSuccess;
   for (int d = 0; d < 2 && e == hipSuccess; ++d) {
-    e = hipMemsetAsync(b.status[d], 0, b.cap_units * sizeof(unsigned long long), s);
-    if (e == hipSuccess) e = hipMemsetAsync(b.plan_status[d], 0, plan_words * sizeof(unsigned long long), s);
+    e = hipMemsetAsync(b.status[d], 0, b.cap_units * utfx_dev::STATUS_STRIDE * sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = hipMemsetAsync(b.plan_status[d], 0, plan_words * utfx_dev::STATUS_STRIDE * sizeof(unsigned long long), s);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(utfx_dev::k_ws_init, dim3(1), dim3(64), 0, s, b.ws);
@@ -520,8 +520,8 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   const uint64_t o_large = o; o += al(ni * 4);
   uint64_t o_plan[2], o_status[2], o_uitem[2];
   for (int d = 0; d < 2; ++d) {
-    o_plan[d] = o; o += al(plan_words * 8);
-    o_status[d] = o; o += al(nu * 8);
+    o_plan[d] = o; o += al(plan_words * 8 * utfx_dev::STATUS_STRIDE);
+    o_status[d] = o; o += al(nu * 8 * utfx_dev::STATUS_STRIDE);
     o_uitem[d] = o; o += al(nu * 4);
   }
   e = hipMalloc(&b.mem, o);

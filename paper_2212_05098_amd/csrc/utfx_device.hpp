@@ -26,6 +26,9 @@ constexpr uint64_t FLAG_PFX = 2;  // inclusive prefix available
 constexpr uint32_t EPOCH_BITS = 25;
 constexpr uint32_t EPOCH_MASK = (1u << EPOCH_BITS) - 1;
 constexpr uint32_t SPIN_LIMIT = 1u << 22;  // look-back watchdog (iterations of s_sleep)
+// Look-back status words sit one per 128-byte line: the words that concurrent
+// look-backs poll then spread over many memory channels instead of a few lines.
+constexpr uint64_t STATUS_STRIDE = 16;
 
 // Device workspace header (one per context).  The finalisation kernel that ends every
 // call resets err and acc and advances the epoch, so a launch always starts from the
@@ -199,7 +202,7 @@ __device__ __forceinline__ uint64_t block_min_u64(uint64_t v, unsigned long long
 __device__ __forceinline__ void publish_aggregate(unsigned long long* status, uint64_t tile, uint64_t agg,
                                                   uint32_t epoch) {
   const unsigned long long tag = (unsigned long long)(epoch & EPOCH_MASK) << (VAL_BITS + 2);
-  st_agent(&status[tile], tag | ((tile == 0 ? FLAG_PFX : FLAG_AGG) << VAL_BITS) | agg);
+  st_agent(&status[tile * STATUS_STRIDE], tag | ((tile == 0 ? FLAG_PFX : FLAG_AGG) << VAL_BITS) | agg);
 }
 
 // Decoupled look-back (Merrill & Garland), run by one whole wave after the tile has
@@ -225,7 +228,7 @@ __device__ __forceinline__ uint64_t lookback_wave(unsigned long long* status, ui
 #pragma unroll
     for (int j = 0; j < LB_PER_LANE; ++j) {
       const int64_t idx = top - (LB_PER_LANE * lane + j);
-      s[j] = (idx >= 0) ? ld_agent(&status[idx]) : (tag | (FLAG_PFX << VAL_BITS));
+      s[j] = (idx >= 0) ? ld_agent(&status[idx * STATUS_STRIDE]) : (tag | (FLAG_PFX << VAL_BITS));
     }
     int lane_first = LB_PER_LANE;  // first inclusive prefix among this lane's words
     bool ok_upto = true;           // every word up to it (or all four) is ready
@@ -264,13 +267,13 @@ __device__ __forceinline__ uint64_t lookback_wave(unsigned long long* status, ui
     top -= 64 * LB_PER_LANE;
     spins = 0;
   }
-  if (lane == 0) st_agent(&status[tile], tag | (FLAG_PFX << VAL_BITS) | (excl + agg));
+  if (lane == 0) st_agent(&status[tile * STATUS_STRIDE], tag | (FLAG_PFX << VAL_BITS) | (excl + agg));
   return excl;
 }
 
 // Inclusive prefix of a finished tile (valid after every tile of the launch is done).
 __device__ __forceinline__ uint64_t tile_inclusive(unsigned long long* status, uint64_t tile) {
-  return ld_agent(&status[tile]) & VAL_MASK;
+  return ld_agent(&status[tile * STATUS_STRIDE]) & VAL_MASK;
 }
 
 }  // namespace utfx_dev
