@@ -223,7 +223,26 @@ __device__ __forceinline__ void load8_masked(const Launch& L, uint64_t q0, const
   }
 }
 
-// One wave transcodes a UTF-8 string of n bytes (n <= SMALL_MAX) 1 KiB at a time.
+// Loads the wave's 1 KiB step at grid position c0 of a UTF-8 string [lo, hi) into x
+// (bytes outside the string read as 0) and returns whether every lane's chunk lies
+// wholly inside it (wave-uniform).
+__device__ __forceinline__ bool wave_load8(const Launch& L, uint64_t c0, uint64_t lo, uint64_t hi, uintptr_t alo,
+                                           uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
+  const uint64_t q0 = c0 + 16ull * lane;
+  const bool full = !__any(!(q0 >= lo && q0 + 16 <= hi));
+  if (full) {
+    const uint4 v = *reinterpret_cast<const uint4*>(L.base + q0);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else {
+    uint32_t m[4];
+    range_masks(q0, lo, hi, m);
+    load8_masked(L, q0, m, alo, ahi, x);
+  }
+  return full;
+}
+
+// One wave transcodes a UTF-8 string of n bytes (n <= SMALL_MAX) 1 KiB at a time; the
+// next step's bytes are loaded while the current step is decoded and stored.
 // stage: the wave's LDS (WSTAGE bytes); [alo, ahi): the input arena.  A chunk with any
 // lane partly outside the string runs the masked path on every lane, so the wave
 // never executes both paths.
@@ -241,18 +260,19 @@ __device__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, uint16_t* out, uin
   uint64_t running = 0;  // formula units before the chunk
   uint32_t carry = 0;    // the 4 bytes before the chunk
   uint64_t err = NO_ERR;
+  uint32_t xn[4];
+  bool fulln = wave_load8(L, 0, lo, hi, alo, ahi, lane, xn);
   for (uint64_t c0 = 0; c0 <= hi; c0 += 1024) {
     const uint64_t q0 = c0 + 16ull * lane;
-    const bool full = !__any(!(q0 >= lo && q0 + 16 <= hi));
-    uint32_t x[4], cnt;
+    const bool full = fulln;
+    uint32_t x[4] = {xn[0], xn[1], xn[2], xn[3]};
+    if (c0 + 1024 <= hi) fulln = wave_load8(L, c0 + 1024, lo, hi, alo, ahi, lane, xn);
+    uint32_t cnt;
     if (full) {
-      const uint4 v = *reinterpret_cast<const uint4*>(L.base + q0);
-      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
       cnt = count8(x, nullptr);
     } else {
       uint32_t m[4];
       range_masks(q0, lo, hi, m);
-      load8_masked(L, q0, m, alo, ahi, x);
       cnt = count8(x, m);
     }
     const uint32_t incl = wave_incl_scan(cnt);
@@ -313,7 +333,25 @@ __device__ __forceinline__ void load16_masked(const Launch& L, uint64_t q0, cons
   }
 }
 
-// One wave transcodes a UTF-16LE string of n words (n <= SMALL_MAX) 512 words at a time.
+// Loads the wave's 512-word step at grid position c0 of a UTF-16 string [lo, hi) into x
+// (words outside the string read as 0); returns whether it lies wholly inside.
+__device__ __forceinline__ bool wave_load16(const Launch& L, uint64_t c0, uint64_t lo, uint64_t hi, uintptr_t alo,
+                                            uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
+  const uint64_t q0 = c0 + 8ull * lane;
+  const bool full = !__any(!(q0 >= lo && q0 + 8 <= hi));
+  if (full) {
+    const uint4 v = *reinterpret_cast<const uint4*>(L.base + 2 * q0);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else {
+    uint32_t m[4];
+    word_masks(q0, lo, hi, m);
+    load16_masked(L, q0, m, alo, ahi, x);
+  }
+  return full;
+}
+
+// One wave transcodes a UTF-16LE string of n words (n <= SMALL_MAX) 512 words at a
+// time, loading the next step while the current one is encoded and stored.
 __device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uint64_t cap, uint8_t* stage,
                                Result* res, uintptr_t alo, uintptr_t ahi) {
   constexpr uint32_t PAD = 16, DUMP = PAD + 3 * 512 + 32;
@@ -327,17 +365,15 @@ __device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uin
   uint64_t running = 0;
   uint32_t carry = 0;  // high half: the word before the chunk
   uint64_t err = NO_ERR;
+  uint32_t xn[4];
+  bool fulln = wave_load16(L, 0, lo, hi, alo, ahi, lane, xn);
   for (uint64_t c0 = 0; c0 <= hi; c0 += 512) {
     const uint64_t q0 = c0 + 8ull * lane;
-    const bool full = !__any(!(q0 >= lo && q0 + 8 <= hi));
-    uint32_t x[4], m[4];
-    if (full) {
-      const uint4 v = *reinterpret_cast<const uint4*>(L.base + 2 * q0);
-      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
-    } else {
-      word_masks(q0, lo, hi, m);
-      load16_masked(L, q0, m, alo, ahi, x);
-    }
+    const bool full = fulln;
+    uint32_t x[4] = {xn[0], xn[1], xn[2], xn[3]};
+    if (c0 + 512 <= hi) fulln = wave_load16(L, c0 + 512, lo, hi, alo, ahi, lane, xn);
+    uint32_t m[4];
+    if (!full) word_masks(q0, lo, hi, m);
     const uint32_t cnt = full ? count16(x, nullptr) : count16(x, m);
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t tot = __shfl(incl, 63, 64);
