@@ -53,6 +53,7 @@ def main():
     ap.add_argument("--serve-rates", default="20000,50000,100000,200000,500000",
                     help="offered request rates of the serving runs (empty = skip)")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
+    ap.add_argument("--serve-inflight", type=int, default=3, help="server steps in flight")
     ap.add_argument("--no-tune-cache", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
@@ -332,8 +333,9 @@ def run_batch(args, ctx, log):
 
 
 def run_serving(args, log):
-    """Continuous-batching server (two steps in flight) on Poisson traces at each
-    offered rate, and one launch per request at the lowest rate."""
+    """Continuous-batching server (--serve-inflight steps in flight) on Poisson traces at
+    each offered rate, and one launch per request at the lowest rate; each server
+    first replays an unrecorded 0.2 s warm-up trace."""
     import numpy as np
     import torch
 
@@ -346,9 +348,21 @@ def run_serving(args, log):
     check = torch.empty(64 << 20, dtype=torch.uint8, pin_memory=True)
     log("serving: payload pool in %.1fs" % (time.time() - t0))
     rates = [float(r) for r in args.serve_rates.split(",") if r]
-    out = {"server": {"inflight": 2, "arena_in_MiB": 256, "arena_out_MiB": 768, "device_cap_GiB": 32},
+    out = {"server": {"inflight": args.serve_inflight, "arena_in_MiB": 256, "arena_out_MiB": 768,
+                      "device_cap_GiB": 32},
            "duration_s": args.serve_seconds, "runs": []}
-    srv = utfx.Server(arena_in_bytes=256 << 20, arena_out_bytes=768 << 20, max_items=1 << 18, inflight=2)
+    srv = utfx.Server(arena_in_bytes=256 << 20, arena_out_bytes=768 << 20, max_items=1 << 18,
+                      inflight=args.serve_inflight)
+
+    def warm(server):
+        # an unrecorded replay first: the HIP runtime sets up each pinned host buffer
+        # the first time a copy uses it (several ms), which would otherwise land in the
+        # first measured trace
+        w = serve.make_workload(pool, 200000, 0.2, seed=1000, scratch_ptr=scratch.data_ptr(), check_every=50,
+                                check_ptr=check.data_ptr(), check_bytes=check.numel())
+        server.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
+
+    warm(srv)
     for k, rate in enumerate(rates):
         w = serve.make_workload(pool, rate, args.serve_seconds, seed=k, scratch_ptr=scratch.data_ptr(),
                                 check_every=1000, check_ptr=check.data_ptr(), check_bytes=check.numel())
@@ -362,6 +376,7 @@ def run_serving(args, log):
     srv.close()
     # one launch per request (max_items = 1) at the lowest rate, for comparison
     one = utfx.Server(arena_in_bytes=64 << 20, arena_out_bytes=192 << 20, max_items=1, inflight=2)
+    warm(one)
     rate = rates[0]
     w = serve.make_workload(pool, rate, min(args.serve_seconds, 0.25), seed=99, scratch_ptr=scratch.data_ptr(),
                             check_every=1000, check_ptr=check.data_ptr(), check_bytes=check.numel())

@@ -215,7 +215,10 @@ void utfx_graph_destroy(utfx_graph *graph);
  * that fits the slot's arenas and item count (admission by free arena bytes, in
  * arrival order) into one step: host-to-device copy, one utfx_batch_run, device-to-
  * host copy of results and outputs.  Requests arriving meanwhile join the next step
- * (continuous batching); with inflight >= 2, steps overlap.  When a step completes,
+ * (continuous batching); with inflight >= 2, steps overlap.  Requests of 1 MiB of input
+ * or more are batched apart from smaller ones, in steps of their own with one such
+ * step in flight while smaller requests wait, so that those do not wait behind large
+ * transfers.  When a step completes,
  * each request's output (its valid prefix, `written` units) is in its `out` buffer
  * and a completion {tag, result} is reported.  Requests of 64 KiB or more whose
  * payload or output buffer is pinned host memory skip the staging copy: that data

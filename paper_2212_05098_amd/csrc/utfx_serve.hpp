@@ -6,7 +6,9 @@
 // buffer, and on the slot's own stream copies them to the device, runs one batched
 // call, and copies results and outputs back.  Requests that arrive while steps run
 // join the next step (continuous batching); with two or more slots a step is packed
-// and launched while earlier ones are still on the GPU.  Completion copies each
+// and launched while earlier ones are still on the GPU.  Requests of kBulkMin input
+// bytes or more queue apart and go to bulk steps, one in flight while small requests
+// wait, so that the many small requests never wait behind a multi-MiB transfer.  Completion copies each
 // request's output to its destination and reports its result.  Single-threaded: the
 // caller drives it with utfx_server_progress, or replays a whole arrival trace in real
 // time with utfx_server_replay.
@@ -49,12 +51,16 @@ struct Slot {
   std::vector<uint8_t> direct_out;  // per request: output copied straight to its buffer
   std::vector<uint64_t> direct_in_off, direct_out_off;
   bool busy = false;
+  bool bulk = false;  // the step in flight holds bulk requests
 };
 
 // Requests at least this large whose host buffers are pinned skip the staging copy:
 // their payload and output move by DMA straight between the request's buffer and the
 // device arena.
 constexpr uint64_t kDirectMin = 64 << 10;
+
+// Requests at least this large (input bytes) are bulk requests.
+constexpr uint64_t kBulkMin = 1 << 20;
 
 inline bool is_pinned(const void* p) {
   hipPointerAttribute_t a;
@@ -78,7 +84,8 @@ inline uint64_t al16(uint64_t x) { return (x + 15) & ~15ull; }
 
 struct utfx_server {
   utfx_server_config cfg;
-  std::deque<utfx_srv::Req> pending;
+  std::deque<utfx_srv::Req> pending;       // small requests, arrival order
+  std::deque<utfx_srv::Req> pending_bulk;  // bulk requests, arrival order
   std::deque<uint64_t> rejected;  // tags of requests no slot can ever hold
   std::vector<utfx_srv::Slot> slots;
   uint64_t steps = 0;
@@ -119,14 +126,31 @@ inline hipError_t alloc_slot(Slot& s, const utfx_server_config& c) {
   return e;
 }
 
+// Host<->device copies of every size class a step issues, on the slot's stream.
+inline hipError_t warm_copies(Slot& s, const utfx_server_config& c) {
+  const uint64_t sizes[] = {64, 4096, 64 << 10, 1 << 20, 16 << 20, 1ull << 62};
+  hipError_t e = hipSuccess;
+  for (uint64_t z : sizes) {
+    const uint64_t zi = z < c.arena_in_bytes ? z : c.arena_in_bytes;
+    const uint64_t zo = z < c.arena_out_bytes ? z : c.arena_out_bytes;
+    if (e == hipSuccess) e = hipMemcpyAsync(s.d_in, s.h_in, zi, hipMemcpyHostToDevice, s.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.h_out, s.d_out, zo, hipMemcpyDeviceToHost, s.stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s.h_res, s.d_res, c.max_items * sizeof(utfx_result), hipMemcpyDeviceToHost, s.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s.d_items, s.h_items, c.max_items * sizeof(utfx_item), hipMemcpyHostToDevice, s.stream);
+  return e;
+}
+
 // Bytes a request needs in the input and output arenas.
 inline uint64_t in_bytes(const Req& r) { return r.len * (r.dir ? 2 : 1); }
 inline uint64_t out_bytes(const Req& r) { return r.out_cap * (r.dir ? 1 : 2); }
 
-// Packs every queued request that fits into slot s and launches the step.  Returns the
-// number of requests taken.  A request no slot can hold is rejected (it completes with
-// UTFX_E_INVALID_ARG on the next progress call).
-inline uint32_t launch_step(utfx_server* S, Slot& s, utfx_status* st) {
+// Packs every request of queue q that fits into slot s and launches the step.  Returns
+// the number of requests taken.  A request no slot can hold is rejected (it completes
+// with UTFX_E_INVALID_ARG on the next progress call).
+inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bulk, utfx_status* st) {
   const utfx_server_config& c = S->cfg;
   // staged data grows from the start of each arena, direct data from its end
   uint64_t in_lo = 0, out_lo = 0, in_hi = c.arena_in_bytes, out_hi = c.arena_out_bytes, units = 0;
@@ -135,11 +159,11 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, utfx_status* st) {
   s.direct_in_off.clear();
   s.direct_out_off.clear();
   std::vector<uint32_t> direct_in_idx;
-  while (!S->pending.empty() && s.reqs.size() < c.max_items) {
-    const Req& r = S->pending.front();
+  while (!q.empty() && s.reqs.size() < c.max_items) {
+    const Req& r = q.front();
     if (r.dir > 1 || in_bytes(r) > c.arena_in_bytes || out_bytes(r) > c.arena_out_bytes) {
       S->rejected.push_back(r.tag);
-      S->pending.pop_front();
+      q.pop_front();
       continue;
     }
     const bool din = in_bytes(r) >= kDirectMin && is_pinned(r.data);
@@ -176,7 +200,7 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, utfx_status* st) {
     units += r.len;
     s.reqs.push_back(r);
     s.direct_out.push_back(dout ? 1 : 0);
-    S->pending.pop_front();
+    q.pop_front();
   }
   const uint32_t n = (uint32_t)s.reqs.size();
   if (!n) return 0;
@@ -205,6 +229,7 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, utfx_status* st) {
     *st = UTFX_E_DEVICE;
   }
   s.busy = true;
+  s.bulk = bulk;
   S->steps++;
   S->items_total += n;
   return n;
@@ -235,6 +260,9 @@ utfx_status utfx_server_create(utfx_server** out, const utfx_server_config* cfg)
     if (ok)
       ok = utfx_batch_run(s.ctx, s.d_in, cfg->arena_in_bytes, s.d_out, cfg->arena_out_bytes, s.d_items,
                           cfg->max_items, cfg->arena_in_bytes, s.d_res) == UTFX_OK;
+    // and run every copy a step makes once, small and arena-sized, so that the runtime
+    // sets up its copy engines now rather than inside the first steps that need them
+    if (ok) ok = warm_copies(s, *cfg) == hipSuccess;
     if (ok) ok = hipStreamSynchronize(s.stream) == hipSuccess;
     if (!ok) {
       for (auto& t : S->slots) free_slot(t);
@@ -257,8 +285,9 @@ const char* utfx_server_last_error(const utfx_server* S) { return S ? S->err : "
 utfx_status utfx_server_submit(utfx_server* S, uint64_t tag, const void* data, uint64_t len_units, uint32_t dir,
                                void* out, uint64_t out_cap_units) {
   if (!S || (len_units && !data) || (out_cap_units && !out)) return UTFX_E_INVALID_ARG;
-  S->pending.push_back(utfx_srv::Req{tag, static_cast<const uint8_t*>(data), len_units, dir,
-                                     static_cast<uint8_t*>(out), out_cap_units});
+  const utfx_srv::Req r{tag, static_cast<const uint8_t*>(data), len_units, dir, static_cast<uint8_t*>(out),
+                        out_cap_units};
+  (utfx_srv::in_bytes(r) >= utfx_srv::kBulkMin ? S->pending_bulk : S->pending).push_back(r);
   return UTFX_OK;
 }
 
@@ -300,11 +329,21 @@ utfx_status utfx_server_progress(utfx_server* S, utfx_completion* done, uint32_t
     c.result.written = 0;
     S->rejected.pop_front();
   }
-  // then launch steps on free slots while requests wait
+  // then launch steps on free slots while requests wait: a bulk step when none is in
+  // flight, small steps otherwise, and more bulk steps only while no small request
+  // waits
+  bool bulk_busy = false;
+  for (auto& s : S->slots) bulk_busy |= s.busy && s.bulk;
   for (auto& s : S->slots) {
-    if (S->pending.empty()) break;
     if (s.busy) continue;
-    launch_step(S, s, &st);
+    if (!S->pending_bulk.empty() && (!bulk_busy || S->pending.empty())) {
+      launch_step(S, s, S->pending_bulk, true, &st);
+      bulk_busy = true;
+    } else if (!S->pending.empty()) {
+      launch_step(S, s, S->pending, false, &st);
+    } else {
+      continue;
+    }
     if (st != UTFX_OK) return st;
   }
   return st;
