@@ -93,6 +93,60 @@ def test_server_replay_trace_fully_checked():
         _check(data, d, outs[int(w.check_off[j]):], r)
 
 
+def test_server_bulk_and_direct_requests():
+    """Small requests interleaved with bulk ones (1 MiB of input or more), pageable and
+    pinned host buffers (staged and direct copies), one bulk request with an error and
+    one larger than the arenas: every request matches the oracle, the oversized one is
+    rejected."""
+    import torch
+
+    rng = synth.rng_for(31, 2)
+    srv = utfx.Server(arena_in_bytes=8 << 20, arena_out_bytes=24 << 20, max_items=256, inflight=3)
+    reqs, keep = [], []
+    for i in range(60):
+        d = i % 2
+        prof = synth.SCRIPT_PROFILES[i % 4]
+        bulk = i % 10 in (3, 6)
+        pinned = i % 4 < 2
+        n = int(rng.integers(1 << 20, 3 << 20)) if bulk else int(rng.integers(1, 5000))
+        if d == 0:
+            data = synth.utf8_buffer(prof, n, rng)
+            if i == 16:
+                data[n // 2] = 0xFF
+            cap, ob = data.size, 2 * data.size + 2
+        else:
+            data = synth.utf16_buffer(prof, max(n // 2, 1), rng)
+            if i == 23:
+                data[data.size // 3 - 1:data.size // 3 + 1] = (0x41, 0xDC00)
+            cap, ob = 3 * data.size, 3 * data.size + 1
+        if pinned:
+            t_in = torch.from_numpy(data.view(np.uint8).copy()).pin_memory()
+            t_out = torch.zeros(ob, dtype=torch.uint8).pin_memory()
+            keep += [t_in, t_out]
+            in_ptr, out_arr, out_ptr = t_in.data_ptr(), t_out.numpy(), t_out.data_ptr()
+        else:
+            out_arr = np.zeros(ob, dtype=np.uint8)
+            in_ptr, out_ptr = data.ctypes.data, out_arr.ctypes.data
+        reqs.append((data, d, cap, out_arr))
+        assert srv.submit(i, in_ptr, data.size, d, out_ptr, cap) == utfx.OK
+    big = np.full(9 << 20, 0x41, dtype=np.uint8)
+    big_out = np.zeros(2 * big.size, dtype=np.uint8)
+    assert srv.submit(len(reqs), big.ctypes.data, big.size, 0, big_out.ctypes.data, big.size) == utfx.OK
+    note("server bulk/direct: %d requests" % (len(reqs) + 1))
+    got = {}
+    for _ in range(5_000_000):
+        for tag, r in srv.progress():
+            got[tag] = r
+        if len(got) == len(reqs) + 1:
+            break
+    assert len(got) == len(reqs) + 1
+    assert got[len(reqs)].status == utfx.E_INVALID_ARG
+    assert got[16].status != utfx.OK and got[23].status == utfx.E_SURROGATE
+    for i, (data, d, cap, out) in enumerate(reqs):
+        _check(data, d, out, got[i])
+    srv.close()
+
+
 def test_server_device_cap():
     with pytest.raises(utfx.UtfxError):
         utfx.Server(arena_in_bytes=1 << 30, arena_out_bytes=2 << 30, inflight=2, device_cap_bytes=4 << 30)
