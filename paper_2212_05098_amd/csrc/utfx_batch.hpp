@@ -415,7 +415,8 @@ __device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uin
   }
 }
 
-__global__ void __launch_bounds__(SMALL_WG) k_batch_small(BatchArgs A) {
+// At most 96 VGPRs: five waves per SIMD (left to itself the compiler takes 102 and four).
+__global__ void __launch_bounds__(SMALL_WG) __attribute__((amdgpu_waves_per_eu(5))) k_batch_small(BatchArgs A) {
   constexpr int NW = SMALL_WG / 64;
   __shared__ __attribute__((aligned(16))) uint8_t smem[NW * WSTAGE];
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -442,7 +443,7 @@ __global__ void __launch_bounds__(SMALL_WG) k_batch_small(BatchArgs A) {
 // bound on segments; workgroups past the real count exit at once).  Workgroups are
 // dispatched in order, so every predecessor a look-back waits for is running or done.
 template <int DIR>
-__global__ void __launch_bounds__(BWG) k_batch_large(BatchArgs A) {
+__global__ void __launch_bounds__(BWG) __attribute__((amdgpu_waves_per_eu(DIR == 1 ? 6 : 1))) k_batch_large(BatchArgs A) {
   const uint64_t t = blockIdx.x;
   if (t >= ld_agent(total_of(A.ws, DIR)) || !plan_ok(A)) return;
   const uint32_t i = __builtin_amdgcn_readfirstlane(A.unit_item[DIR][t]);

@@ -621,8 +621,10 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
                       WG);
 }
 
+// Segments of up to four tiles fit in 80 VGPRs: six waves per SIMD, so that the LDS
+// (not the registers) bounds the workgroups per CU.
 template <int WG, int S>
-__global__ void __launch_bounds__(WG) k_u16_to_u8(Launch L) {
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 6 : 1))) k_u16_to_u8(Launch L) {
   __shared__ __attribute__((aligned(16))) Seg16Smem<WG, S> sm;
   uint32_t x[S][4];
   load_seg16<WG, S>(L, blockIdx.x, x);
