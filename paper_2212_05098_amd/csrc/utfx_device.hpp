@@ -30,6 +30,11 @@ constexpr uint32_t SPIN_LIMIT = 1u << 22;  // look-back watchdog (iterations of 
 // look-backs poll then spread over many memory channels instead of a few lines.
 constexpr uint64_t STATUS_STRIDE = 16;
 
+// Whether a window starting at input position p (may be negative) begins before the
+// error offset e (NO_ERR: no error, so every window does).
+__device__ __forceinline__ bool before(int64_t p, uint64_t e) { return e == NO_ERR || p < (int64_t)e; }
+
+
 // Device workspace header (one per context).  The finalisation kernel that ends every
 // call resets err and acc and advances the epoch, so a launch always starts from the
 // same state without any memset.
@@ -126,6 +131,14 @@ __device__ __forceinline__ unsigned long long ld_agent(unsigned long long* p) {
 }
 __device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reports a workgroup's first error e (NO_ERR: none) to the launch's minimum.  Atomics
+// on one word serialise at the memory side (tens of ns each), so a workgroup reads the
+// word first and only lowers it when its error is smaller; with dense errors, most
+// workgroups find a smaller one already there.
+__device__ __forceinline__ void report_err(unsigned long long* err, uint64_t e) {
+  if (e != NO_ERR && e < ld_agent(err)) atomicMin(err, (unsigned long long)e);
 }
 
 // ---------------------------------------------------------------- scans

@@ -587,11 +587,14 @@ __global__ void __launch_bounds__(WG) k_fin_len(Launch L) {
 template <int WG>
 __global__ void __launch_bounds__(WG) k_validate8(Launch L) {
   constexpr uint64_t T = 16ull * WG;
+  __shared__ unsigned long long werr;  // the workgroup's first error (see report_err)
   const uint64_t seg = blockIdx.x;
   const uint64_t q00 = seg * L.seg * T + 16ull * threadIdx.x;
   uint32_t x[4], xn[4], inE[4], inD[4], E[4], W[8], cnt, det;
   Chunk8 c;
+  if (threadIdx.x == 0) werr = NO_ERR;
   load8(L, q00, x);
+  __syncthreads();
   for (uint32_t s = 0; s < L.seg; ++s) {
     const uint64_t q0 = q00 + s * T;
     if (s + 1 < L.seg) load8(L, q0 + T, xn);
@@ -600,12 +603,16 @@ __global__ void __launch_bounds__(WG) k_validate8(Launch L) {
     process8_any<false>(cls, full, c, inE, inD, E, cnt, det, W);
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
-      const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
-      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
+      if (before(p0 - 3, werr)) {
+        const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
+        if (e != NO_ERR) atomicMin(&werr, (unsigned long long)e);
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = xn[k];
   }
+  __syncthreads();
+  if (threadIdx.x == 0) report_err(L.err, werr);
 }
 
 __global__ void k_fin_validate8(Launch L) {
@@ -621,12 +628,15 @@ __global__ void k_fin_validate8(Launch L) {
 template <int WG>
 __global__ void __launch_bounds__(WG) k_validate16(Launch L) {
   constexpr uint64_t TW = 8ull * WG;
+  __shared__ unsigned long long werr;  // the workgroup's first error (see report_err)
   const uint64_t seg = blockIdx.x;
   const uint64_t q00 = seg * L.seg * TW + 8ull * threadIdx.x;
   const uint64_t lo = L.mis, hi = L.mis + L.n;
   uint32_t x[4], xn[4], len[8], cnt;
   bool det;
+  if (threadIdx.x == 0) werr = NO_ERR;
   load16(L, q00, x);
+  __syncthreads();
   for (uint32_t s = 0; s < L.seg; ++s) {
     const uint64_t q0 = q00 + s * TW;
     if (s + 1 < L.seg) load16(L, q0 + TW, xn);
@@ -636,13 +646,17 @@ __global__ void __launch_bounds__(WG) k_validate16(Launch L) {
     else analyze16<false>(x, wp, q0, lo, hi, len, cnt, det);
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
-      const uint16_t* in = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
-      const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
-      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
+      if (before(p0 - 1, werr)) {
+        const uint16_t* in = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
+        const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
+        if (e != NO_ERR) atomicMin(&werr, (unsigned long long)e);
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = xn[k];
   }
+  __syncthreads();
+  if (threadIdx.x == 0) report_err(L.err, werr);
 }
 
 __global__ void k_fin_validate16(Launch L) {

@@ -216,6 +216,7 @@ struct Seg8Smem {
   uint32_t wtot[NW * (S / 2)];
   uint32_t halo[S * NW];
   unsigned long long seg_base;
+  unsigned long long werr;  // first error found by this workgroup
   uint32_t bounds[2];
 };
 
@@ -240,6 +241,10 @@ __device__ __forceinline__ void load_seg8(const Launch& L, uint64_t seg, uint32_
 
 // One segment of a UTF-8 -> UTF-16LE transcode (segment `seg` of the buffer L, loaded
 // into x).
+//
+// Errors: a flagged chunk is located only while it could still lower the workgroup's
+// minimum, which is kept in LDS; at the end one thread reports it (report_err), so
+// that dense errors do not serialise every lane on the launch's shared word.
 template <int WG, int S>
 __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg8Smem<WG, S>& sm,
                                               const uint32_t (&x)[S][4]) {
@@ -278,6 +283,7 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
 #pragma unroll
     for (int k = 0; k < S; ++k) halo[k * NW + wid] = x[k][3];
   }
+  if (threadIdx.x == 0) sm.werr = NO_ERR;
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);  // contains a barrier
 
@@ -296,8 +302,10 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
     if (k == S - 1 && threadIdx.x == WG - 1) bounds[1] = idx;
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
-      const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
-      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
+      if (before(p0 - 3, sm.werr)) {
+        const uint64_t e = locate8(L.base + L.mis, L.n, p0 - 3, p0 + 16);
+        if (e != NO_ERR) atomicMin(&sm.werr, (unsigned long long)e);
+      }
     }
   }
   if (wid == 0) {
@@ -306,6 +314,8 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
     if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
+
+  if (threadIdx.x == 0) report_err(L.err, sm.werr);
 
   // ---- store the segment's output
   const uint32_t st0 = bounds[0];
@@ -524,6 +534,7 @@ struct Seg16Smem {
   uint32_t wtot[NW * (S / 2)];
   uint32_t halo[S * NW];
   unsigned long long seg_base;
+  unsigned long long werr;  // first error found by this workgroup
 };
 
 // Loads segment `seg` of a UTF-16 buffer (words outside the input read as 0).
@@ -545,7 +556,8 @@ __device__ __forceinline__ void load_seg16(const Launch& L, uint64_t seg, uint32
   }
 }
 
-// One segment of a UTF-16LE -> UTF-8 transcode (loaded into x; see seg_u8_to_u16).
+// One segment of a UTF-16LE -> UTF-8 transcode (loaded into x; errors as in
+// seg_u8_to_u16).
 template <int WG, int S>
 __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg16Smem<WG, S>& sm,
                                               const uint32_t (&x)[S][4]) {
@@ -585,6 +597,7 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
 #pragma unroll
     for (int k = 0; k < S; ++k) halo[k * NW + wid] = x[k][3];
   }
+  if (threadIdx.x == 0) sm.werr = NO_ERR;
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);
 
@@ -606,9 +619,11 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
     }
     if (det) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
-      const uint16_t* in = in16 + L.mis;
-      const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
-      if (e != NO_ERR) atomicMin(L.err, (unsigned long long)e);
+      if (before(p0 - 1, sm.werr)) {
+        const uint16_t* in = in16 + L.mis;
+        const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
+        if (e != NO_ERR) atomicMin(&sm.werr, (unsigned long long)e);
+      }
     }
   }
   if (wid == 0) {
@@ -617,6 +632,7 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
     if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
+  if (threadIdx.x == 0) report_err(L.err, sm.werr);
   store_span<uint8_t>(stage, PAD, seg_total, reinterpret_cast<uint8_t*>(L.out), sm.seg_base, L.cap, threadIdx.x,
                       WG);
 }
