@@ -168,6 +168,16 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
     }
   }
   __syncthreads();
+  // slots in the list of large items: one atomicAdd per wave (the list's order is free)
+  uint32_t nlarge = 0;
+#pragma unroll
+  for (int j = 0; j < PLAN_ITEMS; ++j) nlarge += units[j] != 0;
+  const uint32_t lincl = wave_incl_scan(nlarge);
+  const uint32_t lwave = __shfl(lincl, 63, 64);
+  unsigned long long lbase = 0;
+  if ((threadIdx.x & 63) == 63 && lwave) lbase = atomicAdd(&A.ws->acc, (unsigned long long)lwave);
+  lbase = __shfl(lbase, 63, 64);
+  unsigned long long slot = lbase + (lincl - nlarge);
   uint64_t run[2] = {pfx[0] + local[0], pfx[1] + local[1]};
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) {
@@ -178,8 +188,7 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
     A.unit_start[i] = start;
     if (units[j]) {
       A.item_err[i] = NO_ERR;
-      const unsigned long long slot = atomicAdd(&A.ws->acc, 1ull);
-      A.large[slot] = (uint32_t)i;
+      A.large[slot++] = (uint32_t)i;
       if (start + units[j] <= A.cap_units)
         for (uint32_t u = 0; u < units[j]; ++u) A.unit_item[d][start + u] = (uint32_t)i;
       run[d] += units[j];
