@@ -227,6 +227,7 @@ def main():
                "sample": "first %d MiB of each of the %d (profile, direction) inputs, cut at a character "
                              "boundary; best of 2; single thread" % (args.cpu_sample_mib, len(cases))}
 
+    small = run_small(ctx, log)
     batch = run_batch(args, ctx, log) if args.batch_strings else None
     serving = run_serving(args, log) if args.serve_rates else None
 
@@ -256,11 +257,46 @@ def main():
         "device_copy_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
         "per_case": per_case,
+        "small_64KiB": small,
         "batched": batch,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def run_small(ctx, log, reps=200):
+    """The 64 KiB mixed buffer (characters of all four UTF-8 lengths): synchronous
+    UTF-8 -> UTF-16LE and back, the latency a caller sees per call (launch, kernels,
+    result copy); the round trip is checked to reproduce the input."""
+    import numpy as np
+    import torch
+
+    import paper_2212_05098_amd as utfx
+    from paper_2212_05098_amd import synth
+
+    data = synth.config1_buffer()
+    src = torch.from_numpy(data).cuda()
+    w = torch.empty(data.size, dtype=torch.int16, device="cuda")
+    back = torch.empty(data.size, dtype=torch.uint8, device="cuda")
+    r = ctx.utf8_to_utf16le(src, w)
+    r2 = ctx.utf16le_to_utf8(w[: r.written], back)
+    ok = r.status == utfx.OK and r2.status == utfx.OK and r2.written == data.size and \
+        bool(torch.equal(back[: data.size].cpu(), src.cpu()))
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = ctx.utf8_to_utf16le(src, w)
+        t1 = time.perf_counter()
+        ctx.utf16le_to_utf8(w[: r.written], back)
+        t2 = time.perf_counter()
+        ts.append((t1 - t0, t2 - t1))
+    ts = np.array(ts) * 1e6
+    out = {"round_trip_ok": ok, "utf8_to_utf16le_us_p50": round(float(np.median(ts[:, 0])), 1),
+           "utf16le_to_utf8_us_p50": round(float(np.median(ts[:, 1])), 1), "calls": reps}
+    log("64 KiB sync calls: utf8->utf16le %.1f us, utf16le->utf8 %.1f us (p50), round trip %s" %
+        (out["utf8_to_utf16le_us_p50"], out["utf16le_to_utf8_us_p50"], "ok" if ok else "MISMATCH"))
+    return out
 
 
 def run_batch(args, ctx, log):
