@@ -54,6 +54,7 @@ def main():
                     help="offered request rates of the serving runs (empty = skip)")
     ap.add_argument("--serve-seconds", type=float, default=0.5)
     ap.add_argument("--serve-inflight", type=int, default=3, help="server steps in flight")
+    ap.add_argument("--small-calls", type=int, default=200, help="64 KiB synchronous calls timed (0 = skip)")
     ap.add_argument("--no-tune-cache", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
@@ -227,7 +228,7 @@ def main():
                "sample": "first %d MiB of each of the %d (profile, direction) inputs, cut at a character "
                              "boundary; best of 2; single thread" % (args.cpu_sample_mib, len(cases))}
 
-    small = run_small(ctx, log)
+    small = run_small(ctx, log, args.small_calls) if args.small_calls else None
     batch = run_batch(args, ctx, log) if args.batch_strings else None
     serving = run_serving(args, log) if args.serve_rates else None
 
