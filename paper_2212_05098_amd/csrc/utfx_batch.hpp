@@ -2,9 +2,9 @@
 //
 // Every string (item) gets the result the single-buffer call would give on its bytes.
 // Kernels, in stream order:
-//   k_batch_begin  advance the batch epoch; clear the segment ticket, the large-item
-//                  count and the fault flag (one thread, so the call needs no memset
-//                  and can be captured into a graph);
+//   k_batch_begin  advance the batch epoch; clear the segment totals, the large-item
+//                  count, the length sum and the fault flag (one thread, so the call
+//                  needs no memset and can be captured into a graph);
 //   k_batch_plan   per item: check its descriptor and, for a large item (more than
 //                  SMALL_MAX input units), count its segments; exclusive scans of the
 //                  counts over items, one per direction (workgroup scan + decoupled
@@ -49,8 +49,7 @@ struct BatchArgs {
   Result* results;
   uint64_t n_items;
   // ws: epoch, fault; acc = large items; err = sum of in_len over the valid items;
-  // spare0 / pad[0] = segment tickets and spare1 / pad[1] = segment totals of the
-  // UTF-8 / UTF-16 large items
+  // spare1 / pad[1] = segment totals of the UTF-8 / UTF-16 large items
   WsHeader* ws;
   unsigned long long* unit_start;    // n_items: an item's first segment in its direction's numbering
   unsigned long long* item_err;      // n_items: first error of a large item
@@ -69,9 +68,6 @@ __device__ __forceinline__ bool plan_ok(const BatchArgs& A) {
          ld_agent(&A.ws->pad[1]) <= A.cap_units;
 }
 
-__device__ __forceinline__ unsigned long long* ticket_of(WsHeader* ws, int dir) {
-  return dir ? &ws->pad[0] : &ws->spare0;
-}
 __device__ __forceinline__ unsigned long long* total_of(WsHeader* ws, int dir) {
   return dir ? &ws->pad[1] : &ws->spare1;
 }
@@ -118,9 +114,7 @@ __global__ void k_batch_begin(WsHeader* ws) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const uint32_t ep = __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ws->epoch, (ep + 1) & EPOCH_MASK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    st_agent(&ws->spare0, 0);
     st_agent(&ws->spare1, 0);
-    st_agent(&ws->pad[0], 0);
     st_agent(&ws->pad[1], 0);
     st_agent(&ws->acc, 0);
     st_agent(&ws->err, 0);
