@@ -9,8 +9,11 @@
 //                  SMALL_MAX input units), count its segments; exclusive scans of the
 //                  counts over items, one per direction (workgroup scan + decoupled
 //                  look-back across workgroups); each large item writes the segment ->
-//                  item map of its segments and enters the large-item list;
-//   k_batch_small  one wave per item of at most SMALL_MAX units: the wave walks the
+//                  item map of its segments and enters the large-item list; each tiny
+//                  item enters its direction's tiny-item list;
+//   k_batch_tiny   four tiny items (at most TINY8 bytes / TINY16 words) per wave, one per
+//                  16-lane row: a row holds the whole string in one step;
+//   k_batch_small  one wave per other item of at most SMALL_MAX units: the wave walks the
 //                  string 1 KiB (512 words) at a time carrying the output offset, so it
 //                  needs no look-back and no barrier, and writes the item's result;
 //   k_batch_large  one workgroup per segment of the large items (one launch per
@@ -49,13 +52,15 @@ struct BatchArgs {
   Result* results;
   uint64_t n_items;
   // ws: epoch, fault; acc = large items; err = sum of in_len over the valid items;
-  // spare1 / pad[1] = segment totals of the UTF-8 / UTF-16 large items
+  // spare1 / pad[1] = segment totals and spare0 / pad[0] = tiny-item counts of the
+  // UTF-8 / UTF-16 items
   WsHeader* ws;
   unsigned long long* unit_start;    // n_items: an item's first segment in its direction's numbering
   unsigned long long* item_err;      // n_items: first error of a large item
   unsigned long long* status[2];     // cap_units each: look-back status word per segment (strided)
   uint32_t* unit_item[2];            // cap_units each: item of each segment
   uint32_t* large;                   // n_items: list of large items
+  uint32_t* tiny[2];                 // n_items each: list of tiny items per direction
   unsigned long long* plan_status[2];  // one status word per plan workgroup and direction (strided)
   uint64_t cap_units;
   uint64_t total_in;                 // the caller's bound on the sum of in_len
@@ -71,6 +76,14 @@ __device__ __forceinline__ bool plan_ok(const BatchArgs& A) {
 __device__ __forceinline__ unsigned long long* total_of(WsHeader* ws, int dir) {
   return dir ? &ws->pad[1] : &ws->spare1;
 }
+__device__ __forceinline__ unsigned long long* ntiny_of(WsHeader* ws, int dir) {
+  return dir ? &ws->pad[0] : &ws->spare0;
+}
+
+// Tiny items: with the start's misalignment (< 16 bytes) and the end position, the
+// whole string lies in one 16-lane row step (256 bytes / 128 words).
+constexpr uint64_t TINY8 = 240, TINY16 = 120;
+__device__ __forceinline__ bool item_tiny(const BItem& it) { return it.in_len <= (it.dir ? TINY16 : TINY8); }
 
 __device__ __forceinline__ bool item_ok(const BatchArgs& A, const BItem& it) {
   if (it.dir > 1 || it.in_len > (1ull << 35) || it.out_cap > (3ull << 35)) return false;
@@ -114,7 +127,9 @@ __global__ void k_batch_begin(WsHeader* ws) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const uint32_t ep = __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ws->epoch, (ep + 1) & EPOCH_MASK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    st_agent(&ws->spare0, 0);
     st_agent(&ws->spare1, 0);
+    st_agent(&ws->pad[0], 0);
     st_agent(&ws->pad[1], 0);
     st_agent(&ws->acc, 0);
     st_agent(&ws->err, 0);
@@ -123,12 +138,12 @@ __global__ void k_batch_begin(WsHeader* ws) {
 }
 
 __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
-  __shared__ uint32_t scr[2][PLAN_WG / 64];
-  __shared__ unsigned long long pfx[2];
+  __shared__ uint32_t scr[4][PLAN_WG / 64];
+  __shared__ unsigned long long pfx[2], lbase[3];
   __shared__ unsigned long long sum_scr[PLAN_WG / 64 + 2];
   // PLAN_ITEMS consecutive items per thread
   const uint64_t i0 = ((uint64_t)blockIdx.x * PLAN_WG + threadIdx.x) * PLAN_ITEMS;
-  uint32_t units[PLAN_ITEMS], dir[PLAN_ITEMS], tsum[2] = {0, 0};
+  uint32_t units[PLAN_ITEMS], dir[PLAN_ITEMS], tsum[2] = {0, 0}, tiny = 0, ntiny[2] = {0, 0};
   uint64_t len = 0;
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) {
@@ -139,6 +154,10 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
       const BItem it = A.items[i];
       if (item_ok(A, it)) {
         len += it.in_len;
+        if (item_tiny(it)) {
+          tiny |= (1u + it.dir) << (2 * j);  // 1: UTF-8, 2: UTF-16
+          ntiny[it.dir]++;
+        }
         if (it.in_len > SMALL_MAX) {
           units[j] = (uint32_t)item_units(A, it);
           dir[j] = it.dir;
@@ -161,22 +180,30 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
       if (threadIdx.x == 0) pfx[d] = b;
     }
   }
-  __syncthreads();
-  // slots in the list of large items: one atomicAdd per wave (the list's order is free)
+  // slots in the lists of large and tiny items (their order is free): the workgroup's
+  // counts are scanned and one thread takes each list's range with one atomicAdd
   uint32_t nlarge = 0;
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) nlarge += units[j] != 0;
-  const uint32_t lincl = wave_incl_scan(nlarge);
-  const uint32_t lwave = __shfl(lincl, 63, 64);
-  unsigned long long lbase = 0;
-  if ((threadIdx.x & 63) == 63 && lwave) lbase = atomicAdd(&A.ws->acc, (unsigned long long)lwave);
-  lbase = __shfl(lbase, 63, 64);
-  unsigned long long slot = lbase + (lincl - nlarge);
+  uint32_t ctot[2];
+  const uint32_t c0 = block_excl_scan<PLAN_WG>(nlarge | (ntiny[0] << 16), ctot[0], scr[2]);
+  const uint32_t c1 = block_excl_scan<PLAN_WG>(ntiny[1], ctot[1], scr[3]);
+  if (threadIdx.x == 0) {
+    const uint32_t want[3] = {ctot[0] & 0xFFFFu, ctot[0] >> 16, ctot[1]};
+    unsigned long long* ctr[3] = {&A.ws->acc, ntiny_of(A.ws, 0), ntiny_of(A.ws, 1)};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) lbase[q] = want[q] ? atomicAdd(ctr[q], (unsigned long long)want[q]) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long slot = lbase[0] + (c0 & 0xFFFFu);
+  unsigned long long tslot[2] = {lbase[1] + (c0 >> 16), lbase[2] + c1};
   uint64_t run[2] = {pfx[0] + local[0], pfx[1] + local[1]};
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) {
     const uint64_t i = i0 + j;
     if (i >= A.n_items) break;
+    const uint32_t tj = (tiny >> (2 * j)) & 3u;
+    if (tj) A.tiny[tj - 1][tslot[tj - 1]++] = (uint32_t)i;
     const int d = (int)dir[j];
     const uint64_t start = run[d];
     A.unit_start[i] = start;
@@ -250,7 +277,7 @@ __device__ __forceinline__ bool wave_load8(const Launch& L, uint64_t c0, uint64_
 // lane partly outside the string runs the masked path on every lane, so the wave
 // never executes both paths.
 constexpr uint32_t WSTAGE = 2176;
-__device__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, uint16_t* out, uint64_t cap, uint16_t* stage,
+__device__ __forceinline__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, uint16_t* out, uint64_t cap, uint16_t* stage,
                                Result* res, uintptr_t alo, uintptr_t ahi) {
   constexpr uint32_t PAD = 16, LIM = PAD + 1024, DUMP = LIM + 16;
   static_assert((DUMP + 16) * 2 <= WSTAGE, "wave stage");
@@ -355,7 +382,7 @@ __device__ __forceinline__ bool wave_load16(const Launch& L, uint64_t c0, uint64
 
 // One wave transcodes a UTF-16LE string of n words (n <= SMALL_MAX) 512 words at a
 // time, loading the next step while the current one is encoded and stored.
-__device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uint64_t cap, uint8_t* stage,
+__device__ __forceinline__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uint64_t cap, uint8_t* stage,
                                Result* res, uintptr_t alo, uintptr_t ahi) {
   constexpr uint32_t PAD = 16, DUMP = PAD + 3 * 512 + 32;
   static_assert(DUMP + 16 <= WSTAGE, "wave stage");
@@ -418,6 +445,152 @@ __device__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uin
   }
 }
 
+// ---------------------------------------------------------------- tiny items, by rows
+
+// Inclusive scan over the 16 lanes of each row, and the lane before in the row (0 for
+// the row's first lane).
+__device__ __forceinline__ uint32_t row_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  return x;
+}
+__device__ __forceinline__ uint32_t row_prev(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint64_t row_min_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 8; d >= 1; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint32_t row_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 8; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Per row: its item (mine = the row holds one), LDS stage bytes of one row.
+constexpr uint32_t TROW = 608;  // >= 2 * (16 + 256 + 32) and 16 + 3 * 128 + 32 + 16
+
+// One step of wave_u8_to_u16 for four strings at once, one per 16-lane row.  The same
+// per-chunk code runs on every lane; rows without an item see an empty string.
+__device__ __forceinline__ void rows_u8_to_u16(const BatchArgs& A, const BItem& it, bool mine, Result* res,
+                                               uint16_t* stage, uintptr_t alo, uintptr_t ahi) {
+  constexpr uint32_t PAD = 16, LIM = PAD + 256, DUMP = LIM + 16;
+  static_assert((DUMP + 16) * 2 <= TROW, "row stage");
+  const uint32_t lane = threadIdx.x & 63, rl = lane & 15, rb = lane & 48;
+  const uint8_t* in = A.in + it.in_off;
+  Launch L = {};
+  L.base = reinterpret_cast<const uint8_t*>((uintptr_t)in & ~(uintptr_t)15);
+  L.mis = (uintptr_t)in & 15;
+  L.n = mine ? it.in_len : 0;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const uint64_t q0 = 16ull * rl;
+  uint32_t x[4], m[4];
+  range_masks(q0, lo, hi, m);
+  load8_masked(L, q0, m, alo, ahi, x);
+  const uint32_t cnt = count8(x, m);
+  const uint32_t incl = row_incl_scan(cnt);
+  const uint32_t tot = __shfl(incl, rb + 15, 64);
+  uint32_t first, det;
+  const uint32_t end = chunk_u8_to_u16<PAD, LIM, DUMP>(x, row_prev(x[3]), false, q0, lo, hi, incl - cnt, stage,
+                                                       &first, &det);
+  const uint32_t st0 = __shfl(first, rb, 64);
+  uint32_t st1 = __shfl(end, rb + 15, 64);
+  st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
+  __builtin_amdgcn_wave_barrier();
+  if (mine)
+    store_span<uint16_t>(stage, st0, st1 - st0, reinterpret_cast<uint16_t*>(A.out + it.out_off), st0 - PAD,
+                         it.out_cap, rl, 16);
+  uint64_t err = NO_ERR;
+  if (__any(det)) {
+    uint64_t e = NO_ERR;
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)lo;
+      e = locate8(in, L.n, p0 - 3, p0 + 16);
+    }
+    err = row_min_u64(e);
+  }
+  // words of the valid prefix: the length formula over [0, err)
+  uint32_t mp[4];
+  range_masks(q0, lo, err == NO_ERR ? hi : lo + err, mp);
+  const uint32_t acc = row_sum_u32(count8(x, mp));
+  if (mine && rl == 0) {
+    if (err != NO_ERR) write_result(res, utf8_kind_at(in, L.n, err), err, acc);
+    else if (tot > it.out_cap) write_result(res, ST_OUTPUT_TOO_SMALL, tot, 0);
+    else write_result(res, ST_OK, tot, tot);
+  }
+}
+
+// The same for UTF-16LE -> UTF-8 (one step of wave_u16_to_u8 per row).
+__device__ __forceinline__ void rows_u16_to_u8(const BatchArgs& A, const BItem& it, bool mine, Result* res,
+                                               uint8_t* stage, uintptr_t alo, uintptr_t ahi) {
+  constexpr uint32_t PAD = 16, DUMP = PAD + 3 * 128 + 32;
+  static_assert(DUMP + 16 <= TROW, "row stage");
+  const uint32_t lane = threadIdx.x & 63, rl = lane & 15, rb = lane & 48;
+  const uint16_t* in = reinterpret_cast<const uint16_t*>(A.in + it.in_off);
+  Launch L = {};
+  L.base = reinterpret_cast<const uint8_t*>((uintptr_t)in & ~(uintptr_t)15);
+  L.mis = ((uintptr_t)in & 15) / 2;
+  L.n = mine ? it.in_len : 0;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const uint64_t q0 = 8ull * rl;
+  uint32_t x[4], m[4];
+  word_masks(q0, lo, hi, m);
+  load16_masked(L, q0, m, alo, ahi, x);
+  const uint32_t cnt = count16(x, m);
+  const uint32_t incl = row_incl_scan(cnt);
+  const uint32_t tot = __shfl(incl, rb + 15, 64);
+  const bool det = chunk_u16_to_u8(x, row_prev(x[3]), m, stage + PAD + (incl - cnt), stage + DUMP);
+  __builtin_amdgcn_wave_barrier();
+  if (mine) store_span<uint8_t>(stage, PAD, tot, A.out + it.out_off, 0, it.out_cap, rl, 16);
+  uint64_t err = NO_ERR;
+  if (__any(det)) {
+    uint64_t e = NO_ERR;
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)lo;
+      e = locate16(in, L.n, p0 - 1, p0 + 8);
+    }
+    err = row_min_u64(e);
+  }
+  uint32_t mp[4];
+  word_masks(q0, lo, err == NO_ERR ? hi : lo + err, mp);
+  const uint32_t acc = row_sum_u32(count16(x, mp));
+  if (mine && rl == 0) {
+    if (err != NO_ERR) write_result(res, ST_SURROGATE, err, acc);
+    else if (tot > it.out_cap) write_result(res, ST_OUTPUT_TOO_SMALL, tot, 0);
+    else write_result(res, ST_OK, tot, tot);
+  }
+}
+
+// Waves [0, W8) take four UTF-8 tiny items each from the UTF-8 list, the next waves four
+// UTF-16 items each; waves past both lists exit.
+constexpr int TINY_WG = 256;
+__global__ void __launch_bounds__(TINY_WG) k_batch_tiny(BatchArgs A) {
+  constexpr int NW = TINY_WG / 64;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[NW * 4 * TROW];
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t lane = threadIdx.x & 63, row = lane >> 4;
+  const uint64_t w = (uint64_t)blockIdx.x * NW + wid;
+  const uint64_t n8 = ld_agent(ntiny_of(A.ws, 0)), n16 = ld_agent(ntiny_of(A.ws, 1));
+  const uint64_t w8 = (n8 + 3) / 4, w16 = (n16 + 3) / 4;
+  if (w >= w8 + w16) return;
+  const int d = w < w8 ? 0 : 1;  // wave-uniform
+  const uint64_t k = 4 * (d ? w - w8 : w) + row;
+  const bool mine = k < (d ? n16 : n8);
+  const uint32_t i = mine ? A.tiny[d][k] : 0u;
+  BItem it = A.items[i];
+  Result* res = A.results + i;
+  uint8_t* st = smem + (wid * 4 + row) * TROW;
+  const uintptr_t alo = (uintptr_t)A.in, ahi = (uintptr_t)(A.in + A.in_bytes);
+  if (d == 0) rows_u8_to_u16(A, it, mine, res, reinterpret_cast<uint16_t*>(st), alo, ahi);
+  else rows_u16_to_u8(A, it, mine, res, st, alo, ahi);
+}
+
 // At most 96 VGPRs: five waves per SIMD (left to itself the compiler takes 102 and four).
 __global__ void __launch_bounds__(SMALL_WG) __attribute__((amdgpu_waves_per_eu(5))) k_batch_small(BatchArgs A) {
   constexpr int NW = SMALL_WG / 64;
@@ -432,6 +605,7 @@ __global__ void __launch_bounds__(SMALL_WG) __attribute__((amdgpu_waves_per_eu(5
     return;
   }
   if (it.in_len > SMALL_MAX) return;  // a large item: k_batch_large and k_batch_fin
+  if (item_tiny(it)) return;          // k_batch_tiny
   uint8_t* st = smem + wid * WSTAGE;
   const uintptr_t alo = (uintptr_t)A.in, ahi = (uintptr_t)(A.in + A.in_bytes);
   if (it.dir == 0)
@@ -509,6 +683,7 @@ struct BatchWs {
   unsigned long long* status[2] = {nullptr, nullptr};
   uint32_t* unit_item[2] = {nullptr, nullptr};
   uint32_t* large = nullptr;
+  uint32_t* tiny[2] = {nullptr, nullptr};
   unsigned long long* plan_status[2] = {nullptr, nullptr};
   uint64_t cap_items = 0, cap_units = 0;
   uint64_t launches = 0;
@@ -558,8 +733,9 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   const uint64_t o_start = o; o += al(ni * 8);
   const uint64_t o_err = o; o += al(ni * 8);
   const uint64_t o_large = o; o += al(ni * 4);
-  uint64_t o_plan[2], o_status[2], o_uitem[2];
+  uint64_t o_plan[2], o_status[2], o_uitem[2], o_tiny[2];
   for (int d = 0; d < 2; ++d) {
+    o_tiny[d] = o; o += al(ni * 4);
     o_plan[d] = o; o += al(plan_words * 8 * utfx_dev::STATUS_STRIDE);
     o_status[d] = o; o += al(nu * 8 * utfx_dev::STATUS_STRIDE);
     o_uitem[d] = o; o += al(nu * 4);
@@ -575,6 +751,7 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   b.item_err = reinterpret_cast<unsigned long long*>(m + o_err);
   b.large = reinterpret_cast<uint32_t*>(m + o_large);
   for (int d = 0; d < 2; ++d) {
+    b.tiny[d] = reinterpret_cast<uint32_t*>(m + o_tiny[d]);
     b.plan_status[d] = reinterpret_cast<unsigned long long*>(m + o_plan[d]);
     b.status[d] = reinterpret_cast<unsigned long long*>(m + o_status[d]);
     b.unit_item[d] = reinterpret_cast<uint32_t*>(m + o_uitem[d]);
@@ -621,6 +798,7 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   A.item_err = b.item_err;
   A.large = b.large;
   for (int d = 0; d < 2; ++d) {
+    A.tiny[d] = b.tiny[d];
     A.status[d] = b.status[d];
     A.unit_item[d] = b.unit_item[d];
     A.plan_status[d] = b.plan_status[d];
@@ -629,10 +807,13 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   A.total_in = total_in_units;
   const uint32_t plan_blocks = (n_items + PLAN_WG * PLAN_ITEMS - 1) / (PLAN_WG * PLAN_ITEMS);
   const uint32_t small_blocks = (n_items + SMALL_WG / 64 - 1) / (SMALL_WG / 64);
+  // tiny waves: at most n/4 + 2 (four items per wave, per direction, rounded up)
+  const uint32_t tiny_blocks = (uint32_t)((n_items / 4 + 2 + TINY_WG / 64 - 1) / (TINY_WG / 64));
   const uint32_t large_blocks = (uint32_t)(cap_units < 0x7FFFFFFFull ? cap_units : 0x7FFFFFFFull);
   const uint32_t fin_blocks = n_items < 1024 ? n_items : 1024;
   hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ws);
   hipLaunchKernelGGL(k_batch_plan, dim3(plan_blocks), dim3(PLAN_WG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_tiny, dim3(tiny_blocks), dim3(TINY_WG), 0, s, A);
   hipLaunchKernelGGL(k_batch_small, dim3(small_blocks), dim3(SMALL_WG), 0, s, A);
   hipLaunchKernelGGL(k_batch_large<0>, dim3(large_blocks), dim3(BWG), 0, s, A);
   hipLaunchKernelGGL(k_batch_large<1>, dim3(large_blocks), dim3(BWG), 0, s, A);
