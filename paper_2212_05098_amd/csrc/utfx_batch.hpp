@@ -64,6 +64,7 @@ struct BatchArgs {
   unsigned long long* plan_status[2];  // one status word per plan workgroup and direction (strided)
   uint64_t cap_units;
   uint64_t total_in;                 // the caller's bound on the sum of in_len
+  uint32_t rows;                     // tiny items go to k_batch_tiny (large calls only)
 };
 
 // Whether the plan holds: the items add up to at most the caller's bound, and so
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
       const BItem it = A.items[i];
       if (item_ok(A, it)) {
         len += it.in_len;
-        if (item_tiny(it)) {
+        if (A.rows && item_tiny(it)) {
           tiny |= (1u + it.dir) << (2 * j);  // 1: UTF-8, 2: UTF-16
           ntiny[it.dir]++;
         }
@@ -570,6 +571,7 @@ __device__ __forceinline__ void rows_u16_to_u8(const BatchArgs& A, const BItem& 
 // Waves [0, W8) take four UTF-8 tiny items each from the UTF-8 list, the next waves four
 // UTF-16 items each; waves past both lists exit.
 constexpr int TINY_WG = 256;
+constexpr uint32_t TINY_ROWS_MIN = 4096;  // items per call from which tiny items use rows
 __global__ void __launch_bounds__(TINY_WG) k_batch_tiny(BatchArgs A) {
   constexpr int NW = TINY_WG / 64;
   __shared__ __attribute__((aligned(16))) uint8_t smem[NW * 4 * TROW];
@@ -605,7 +607,7 @@ __global__ void __launch_bounds__(SMALL_WG) __attribute__((amdgpu_waves_per_eu(5
     return;
   }
   if (it.in_len > SMALL_MAX) return;  // a large item: k_batch_large and k_batch_fin
-  if (item_tiny(it)) return;          // k_batch_tiny
+  if (A.rows && item_tiny(it)) return;  // k_batch_tiny
   uint8_t* st = smem + wid * WSTAGE;
   const uintptr_t alo = (uintptr_t)A.in, ahi = (uintptr_t)(A.in + A.in_bytes);
   if (it.dir == 0)
@@ -805,6 +807,8 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   }
   A.cap_units = cap_units;
   A.total_in = total_in_units;
+  // rows pay off on many strings; a call with few (a serving step) saves the launch
+  A.rows = n_items >= TINY_ROWS_MIN;
   const uint32_t plan_blocks = (n_items + PLAN_WG * PLAN_ITEMS - 1) / (PLAN_WG * PLAN_ITEMS);
   const uint32_t small_blocks = (n_items + SMALL_WG / 64 - 1) / (SMALL_WG / 64);
   // tiny waves: at most n/4 + 2 (four items per wave, per direction, rounded up)
@@ -813,7 +817,7 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   const uint32_t fin_blocks = n_items < 1024 ? n_items : 1024;
   hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ws);
   hipLaunchKernelGGL(k_batch_plan, dim3(plan_blocks), dim3(PLAN_WG), 0, s, A);
-  hipLaunchKernelGGL(k_batch_tiny, dim3(tiny_blocks), dim3(TINY_WG), 0, s, A);
+  if (A.rows) hipLaunchKernelGGL(k_batch_tiny, dim3(tiny_blocks), dim3(TINY_WG), 0, s, A);
   hipLaunchKernelGGL(k_batch_small, dim3(small_blocks), dim3(SMALL_WG), 0, s, A);
   hipLaunchKernelGGL(k_batch_large<0>, dim3(large_blocks), dim3(BWG), 0, s, A);
   hipLaunchKernelGGL(k_batch_large<1>, dim3(large_blocks), dim3(BWG), 0, s, A);

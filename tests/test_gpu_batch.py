@@ -85,10 +85,12 @@ def run_and_check(ctx, arena, in_off, in_len, dirs, caps, rng, total=None, expec
     return got
 
 
-def test_batch_mixed_profiles_and_errors(ctx):
-    """3,000 strings, log-normal lengths (median 256 B, sigma 2), mixed profiles and
-    directions, 5 % with an injected error, random output caps on 5 %."""
-    b = synth.make_batch(3000, seed_key=(7, 1), median=256, sigma=2.0, hi=256 << 10, err_frac=0.05)
+@pytest.mark.parametrize("n", [3000, 6000])
+def test_batch_mixed_profiles_and_errors(ctx, n):
+    """n strings, log-normal lengths (median 256 B, sigma 2), mixed profiles and
+    directions, 5 % with an injected error, random output caps on 5 %.  With 6,000
+    strings (calls of 4,096 or more) the tiny ones go through the row kernel."""
+    b = synth.make_batch(n, seed_key=(7, 1, n), median=256, sigma=2.0, hi=256 << 10, err_frac=0.05)
     rng = synth.rng_for(7, 2)
     need = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
     caps = need.copy()
