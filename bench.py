@@ -55,6 +55,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=0.5)
     ap.add_argument("--serve-inflight", type=int, default=3, help="server steps in flight")
     ap.add_argument("--small-calls", type=int, default=200, help="64 KiB synchronous calls timed (0 = skip)")
+    ap.add_argument("--run-mib", type=int, default=64, help="run-structured buffers per profile (MiB, 0 = skip)")
     ap.add_argument("--no-tune-cache", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
@@ -229,6 +230,7 @@ def main():
                              "boundary; best of 2; single thread" % (args.cpu_sample_mib, len(cases))}
 
     small = run_small(ctx, log, args.small_calls) if args.small_calls else None
+    runs = run_structured(ctx, log, args.run_mib) if args.run_mib else None
     batch = run_batch(args, ctx, log) if args.batch_strings else None
     serving = run_serving(args, log) if args.serve_rates else None
 
@@ -259,6 +261,7 @@ def main():
         "cpu_baseline": cpu,
         "per_case": per_case,
         "small_64KiB": small,
+        "run_structured": runs,
         "batched": batch,
         "serving": serving,
     }
@@ -297,6 +300,55 @@ def run_small(ctx, log, reps=200):
            "utf16le_to_utf8_us_p50": round(float(np.median(ts[:, 1])), 1), "calls": reps}
     log("64 KiB sync calls: utf8->utf16le %.1f us, utf16le->utf8 %.1f us (p50), round trip %s" %
         (out["utf8_to_utf16le_us_p50"], out["utf16le_to_utf8_us_p50"], "ok" if ok else "MISMATCH"))
+    return out
+
+
+def run_structured(ctx, log, mib, reps=5):
+    """Run-structured text (words in same-script sentences, closer to the paper's lipsum
+    files) per profile and direction: device time per call and input GB/s, beside an
+    i.i.d. buffer of the same profile and size.  The wave-uniform content classes make
+    uniform stretches cheaper."""
+    import numpy as np
+    import torch
+
+    import paper_2212_05098_amd as utfx
+    from paper_2212_05098_amd import synth
+
+    n = mib << 20
+    res = utfx.result_tensor(1)
+    out = {"mib": mib, "cases": []}
+
+    def timed(host, d):
+        if d == synth.DIR_8TO16:
+            src = torch.from_numpy(host).cuda()
+            dst = torch.empty(n, dtype=torch.int16, device="cuda")
+            f = ctx.utf8_to_utf16le_async
+        else:
+            src = torch.from_numpy(host.view(np.int16)).cuda()
+            dst = torch.empty(3 * (n // 2), dtype=torch.uint8, device="cuda")
+            f = ctx.utf16le_to_utf8_async
+        f(src, dst, res)
+        torch.cuda.synchronize()
+        assert utfx.results_from_tensor(res)[0].status == utfx.OK
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f(src, dst, res)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for prof in synth.SCRIPT_PROFILES:
+        rng = synth.rng_for(0, 7, synth.PROFILE_IDS[prof])
+        for d in (synth.DIR_8TO16, synth.DIR_16TO8):
+            run = synth.run_utf8_buffer(prof, n, rng) if d == synth.DIR_8TO16 else synth.run_utf16_buffer(prof, n // 2, rng)
+            ms = timed(run, d)
+            ms_iid = timed(synth.config_buffer(prof, d, n, config=7), d)
+            case = {"profile": prof, "dir": "utf8->utf16le" if d == 0 else "utf16le->utf8", "ms_avg": round(ms, 4),
+                    "in_GBps": round(n / (ms * 1e6), 1), "iid_ms_avg": round(ms_iid, 4)}
+            out["cases"].append(case)
+            log("run-structured %-6s %-14s %8.3f ms  in %7.1f GB/s  (i.i.d. same size %.3f ms)" %
+                (prof, case["dir"], ms, case["in_GBps"], ms_iid))
     return out
 
 

@@ -103,6 +103,61 @@ def utf16_buffer(profile: str, n_words: int, rng: np.random.Generator) -> np.nda
     return out.astype(np.uint16)
 
 
+# Run-structured text, closer to the paper's lipsum files than the i.i.d. profiles:
+# words of 1..9 characters (mean 5) separated by single spaces, sentences of 5..20 words
+# each written in one script drawn from the profile's ranges (lower-case Latin letters for
+# the ASCII profile).  Waves of such text are often uniform in their byte classes.
+RUN_SCRIPTS: Dict[str, List[Tuple[int, int]]] = {
+    "ascii": [(0x61, 0x7A)],
+    "latin": [(0xC0, 0xFF), (0x400, 0x4FF), (0x600, 0x6FF)],
+    "cjk": [(0x4E00, 0x9FFF)],
+    "emoji": [(0x1F300, 0x1FAFF)],
+}
+
+
+def run_codepoints(profile: str, k: int, rng: np.random.Generator) -> np.ndarray:
+    """At least k code points of run-structured text of the profile, as uint32."""
+    scripts = RUN_SCRIPTS[profile]
+    n_words = k // 5 + 16
+    wl = rng.integers(1, 10, size=n_words)                      # word lengths
+    sl = rng.integers(5, 21, size=n_words // 5 + 2)             # sentence lengths in words
+    sent = np.repeat(np.arange(sl.size), sl)[:n_words]          # sentence of each word
+    script = rng.integers(0, len(scripts), size=sl.size)[sent]  # script of each word
+    lo = np.array([a for a, _ in scripts], dtype=np.int64)[script]
+    hi = np.array([b for _, b in scripts], dtype=np.int64)[script]
+    per_char_lo = np.repeat(lo, wl)
+    per_char_hi = np.repeat(hi, wl)
+    chars = per_char_lo + (rng.random(per_char_lo.size) * (per_char_hi - per_char_lo + 1)).astype(np.int64)
+    # a space after every word
+    ends = np.cumsum(wl)
+    out = np.insert(chars, ends, 0x20)
+    return out.astype(np.uint32)
+
+
+def run_utf8_buffer(profile: str, n_bytes: int, rng: np.random.Generator) -> np.ndarray:
+    """Exactly n_bytes of valid run-structured UTF-8 (cut at a character, ASCII pad)."""
+    if n_bytes == 0:
+        return np.zeros(0, dtype=np.uint8)
+    b = b""
+    while len(b) < n_bytes:
+        b += cps_to_str(run_codepoints(profile, max(n_bytes // 2, 64), rng)).encode("utf-8")
+    cut = b[:n_bytes].decode("utf-8", errors="ignore").encode("utf-8")
+    cut += _ascii_pad(rng, n_bytes - len(cut))
+    return np.frombuffer(cut, dtype=np.uint8).copy()
+
+
+def run_utf16_buffer(profile: str, n_words: int, rng: np.random.Generator) -> np.ndarray:
+    """Exactly n_words of valid run-structured UTF-16LE."""
+    if n_words == 0:
+        return np.zeros(0, dtype=np.uint16)
+    b = b""
+    while len(b) < 2 * n_words:
+        b += cps_to_str(run_codepoints(profile, max(n_words // 2, 64), rng)).encode("utf-16-le")
+    cut = b[: 2 * n_words].decode("utf-16-le", errors="ignore").encode("utf-16-le")
+    pad = np.frombuffer(_ascii_pad(rng, n_words - len(cut) // 2), dtype=np.uint8).astype("<u2")
+    return np.concatenate([np.frombuffer(cut, dtype="<u2"), pad]).astype(np.uint16)
+
+
 def config_buffer(profile: str, direction: int, n_bytes: int, config: int = 2) -> np.ndarray:
     """Input for one (config, profile, direction): uint8 for UTF-8, uint16 for UTF-16."""
     rng = rng_for(0, config, PROFILE_IDS[profile], direction)

@@ -115,6 +115,20 @@ def test_profiles_ragged_sizes(ctx, prof):
         check_u16_to_u8(ctx, synth.utf16_buffer(prof, n, rng))
 
 
+@pytest.mark.parametrize("prof", synth.SCRIPT_PROFILES)
+def test_run_structured_text(ctx, prof):
+    """Run-structured text (same-script words), where whole waves fall into one content
+    class, in several launch configurations."""
+    rng = synth.rng_for(17, synth.PROFILE_IDS[prof])
+    for T in (TILES[0], TILES[2]):
+        set_tile(ctx, T)
+        for n in (255, 65_537, 1_000_003):
+            note("run-structured %s n=%d T=%s" % (prof, n, T))
+            check_u8_to_u16(ctx, synth.run_utf8_buffer(prof, n, rng))
+            check_u16_to_u8(ctx, synth.run_utf16_buffer(prof, n // 2 + 1, rng))
+    set_tile(ctx, TILES[1])
+
+
 @pytest.mark.parametrize("shift", list(range(0, 16)))
 def test_misaligned_pointers(ctx, shift):
     rng = synth.rng_for(12, shift)
