@@ -157,6 +157,26 @@ utfx_status utfx_utf8_to_utf16le_async(utfx_ctx *ctx, const uint8_t *in, size_t 
 utfx_status utfx_utf16le_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
                                        uint8_t *out, size_t cap_bytes, utfx_result *d_result);
 
+/* ---- UTF-16BE ------------------------------------------------------------------
+ * The same operations with big-endian UTF-16 code units (section 3: the paper's
+ * UTF-16 is little-endian, and big-endian input or output differs only by the byte
+ * order within each 16-bit unit, which the kernels swap on load or on store).
+ * Arguments, results and errors are exactly those of the UTF-16LE calls above. */
+utfx_result utfx_utf8_length_from_utf16be(utfx_ctx *ctx, const uint16_t *in, size_t n_words);
+utfx_result utfx_validate_utf16be(utfx_ctx *ctx, const uint16_t *in, size_t n_words);
+utfx_result utfx_utf8_to_utf16be(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                 uint16_t *out, size_t cap_words);
+utfx_result utfx_utf16be_to_utf8(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                 uint8_t *out, size_t cap_bytes);
+utfx_status utfx_utf8_length_from_utf16be_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                                utfx_result *d_result);
+utfx_status utfx_validate_utf16be_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                        utfx_result *d_result);
+utfx_status utfx_utf8_to_utf16be_async(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                       uint16_t *out, size_t cap_words, utfx_result *d_result);
+utfx_status utfx_utf16be_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                       uint8_t *out, size_t cap_bytes, utfx_result *d_result);
+
 /* ---- batched: many independent strings in one call ---------------------------- */
 /* One string.  in_off/out_off are byte offsets into the arenas; in_len is in input
  * units and out_cap in output units; dir 0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8.

@@ -1,4 +1,4 @@
-"""Scalar CPU oracle for validating UTF-8 <-> UTF-16LE transcoding.
+"""Scalar CPU oracle for validating UTF-8 <-> UTF-16LE (and UTF-16BE) transcoding.
 
 TEST INFRASTRUCTURE ONLY.  The test suite, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` are the only callers.  The GPU library never
@@ -165,6 +165,37 @@ def utf16le_to_utf8(data, cap: Optional[int] = None):
     out = np.zeros(cap, dtype=np.uint8)
     r = _res(lib().utfx_ref_utf16le_to_utf8(_ptr(a), a.size, _ptr(out), cap))
     return r, out
+
+
+# ---- UTF-16BE (section 2.2: the same code units, most significant byte first) ------
+# A UTF-16BE buffer is handled as the uint16 array that holds its bytes in memory; on
+# a little-endian host each element is then the byte-swapped code unit, so these
+# wrappers swap every element and defer to the functions above.
+
+def _be_words(data) -> np.ndarray:
+    if isinstance(data, (bytes, bytearray, memoryview)):
+        b = bytes(data)
+        assert len(b) % 2 == 0
+        return np.frombuffer(b, dtype=">u2").astype(np.uint16)
+    return _u16(data).byteswap()
+
+
+def utf8_length_from_utf16be(data) -> Result:
+    return utf8_length_from_utf16le(_be_words(data))
+
+
+def validate_utf16be(data) -> Result:
+    return validate_utf16le(_be_words(data))
+
+
+def utf8_to_utf16be(data, cap: Optional[int] = None):
+    """Returns (Result, out): out holds the UTF-16BE bytes as a uint16 array."""
+    r, out = utf8_to_utf16le(data, cap)
+    return r, out.byteswap()
+
+
+def utf16be_to_utf8(data, cap: Optional[int] = None):
+    return utf16le_to_utf8(_be_words(data), cap)
 
 
 def validate_utf8_fixed(buf: np.ndarray, length: int, want_arrays: bool = True):

@@ -110,6 +110,14 @@ def lib() -> ctypes.CDLL:
         "utfx_validate_utf16le_async": (I, [P, P, Z, P]),
         "utfx_utf8_to_utf16le_async": (I, [P, P, Z, P, Z, P]),
         "utfx_utf16le_to_utf8_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_utf8_length_from_utf16be": (CResult, [P, P, Z]),
+        "utfx_validate_utf16be": (CResult, [P, P, Z]),
+        "utfx_utf8_to_utf16be": (CResult, [P, P, Z, P, Z]),
+        "utfx_utf16be_to_utf8": (CResult, [P, P, Z, P, Z]),
+        "utfx_utf8_length_from_utf16be_async": (I, [P, P, Z, P]),
+        "utfx_validate_utf16be_async": (I, [P, P, Z, P]),
+        "utfx_utf8_to_utf16be_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_utf16be_to_utf8_async": (I, [P, P, Z, P, Z, P]),
         "utfx_batch_run": (I, [P, P, Z, P, Z, P, U32, U64, P]),
         "utfx_capture_begin": (I, [P]),
         "utfx_capture_end": (I, [P, ctypes.POINTER(P)]),
@@ -277,6 +285,43 @@ class Context:
     def utf8_length_from_utf16le_async(self, src, d_result) -> int:
         p, n = _ptr_len(src, 2)
         return int(self._lib.utfx_utf8_length_from_utf16le_async(self._h, p, n, d_result.data_ptr()))
+
+    # ---- UTF-16BE: the same kernels with byte-swapped 16-bit loads or stores --------
+    def utf8_length_from_utf16be(self, src) -> Result:
+        p, n = _ptr_len(src, 2)
+        return _res(self._lib.utfx_utf8_length_from_utf16be(self._h, p, n))
+
+    def validate_utf16be(self, src) -> Result:
+        p, n = _ptr_len(src, 2)
+        return _res(self._lib.utfx_validate_utf16be(self._h, p, n))
+
+    def utf8_to_utf16be(self, src, dst) -> Result:
+        p, n = _ptr_len(src, 1)
+        q, cap = _ptr_len(dst, 2)
+        return _res(self._lib.utfx_utf8_to_utf16be(self._h, p, n, q, cap))
+
+    def utf16be_to_utf8(self, src, dst) -> Result:
+        p, n = _ptr_len(src, 2)
+        q, cap = _ptr_len(dst, 1)
+        return _res(self._lib.utfx_utf16be_to_utf8(self._h, p, n, q, cap))
+
+    def utf8_to_utf16be_async(self, src, dst, d_result) -> int:
+        p, n = _ptr_len(src, 1)
+        q, cap = _ptr_len(dst, 2)
+        return int(self._lib.utfx_utf8_to_utf16be_async(self._h, p, n, q, cap, d_result.data_ptr()))
+
+    def utf16be_to_utf8_async(self, src, dst, d_result) -> int:
+        p, n = _ptr_len(src, 2)
+        q, cap = _ptr_len(dst, 1)
+        return int(self._lib.utfx_utf16be_to_utf8_async(self._h, p, n, q, cap, d_result.data_ptr()))
+
+    def validate_utf16be_async(self, src, d_result) -> int:
+        p, n = _ptr_len(src, 2)
+        return int(self._lib.utfx_validate_utf16be_async(self._h, p, n, d_result.data_ptr()))
+
+    def utf8_length_from_utf16be_async(self, src, d_result) -> int:
+        p, n = _ptr_len(src, 2)
+        return int(self._lib.utfx_utf8_length_from_utf16be_async(self._h, p, n, d_result.data_ptr()))
 
     def batch_run(self, in_arena, out_arena, d_items, n_items: int, total_in_units: int, d_results) -> int:
         """Queue a batch (see utfx_batch_run); the arenas are uint8 device tensors."""
@@ -495,3 +540,30 @@ def utf16le_to_utf8(src, dst=None):
         n = (src.numel() * src.element_size()) // 2
         dst = torch.empty(max(3 * n, 1), dtype=torch.uint8, device=src.device)
     return default_context().utf16le_to_utf8(src, dst), dst
+
+
+def utf8_length_from_utf16be(src) -> Result:
+    return default_context().utf8_length_from_utf16be(src)
+
+
+def validate_utf16be(src) -> Result:
+    return default_context().validate_utf16be(src)
+
+
+def utf8_to_utf16be(src, dst=None):
+    """Returns (Result, dst).  dst defaults to n words (always large enough)."""
+    import torch
+
+    if dst is None:
+        dst = torch.empty(max(src.numel() * src.element_size(), 1), dtype=torch.int16, device=src.device)
+    return default_context().utf8_to_utf16be(src, dst), dst
+
+
+def utf16be_to_utf8(src, dst=None):
+    """Returns (Result, dst).  dst defaults to 3n bytes (always large enough)."""
+    import torch
+
+    if dst is None:
+        n = (src.numel() * src.element_size()) // 2
+        dst = torch.empty(max(3 * n, 1), dtype=torch.uint8, device=src.device)
+    return default_context().utf16be_to_utf8(src, dst), dst

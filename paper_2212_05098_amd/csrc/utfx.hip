@@ -146,6 +146,7 @@ utfx_status prep(utfx_ctx* c, int op, const void* in, uint64_t n, uint32_t unit,
   wg = c->tile_bytes[op] / 16;
   L.seg = c->seg_tiles[op];
   L.wg = wg;
+  L.be = 0;
   const uint64_t per_seg = static_cast<uint64_t>(wg) * (16 / unit) * L.seg;
   L.seg_units = per_seg;
   L.ntiles = (L.mis + n + extra + per_seg - 1) / per_seg;
@@ -265,7 +266,9 @@ hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
   }
 }
 
-utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, uint64_t cap, void* d_result) {
+// be: the UTF-16 side (input or output) is big-endian.
+utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, uint64_t cap, void* d_result,
+                bool be = false) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
   const bool in16 = (kind == LEN16 || kind == VAL16 || kind == U16U8);
@@ -314,6 +317,7 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
   if (s != UTFX_OK) return s;
   L.out = out;
   L.cap = cap;
+  L.be = be ? 1u : 0u;
   if (L.ntiles > 0x7FFFFFFFull) {
     set_msg(c, "grid too large");
     return UTFX_E_INVALID_ARG;
@@ -337,13 +341,14 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
   return UTFX_OK;
 }
 
-utfx_result run_sync(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, uint64_t cap) {
+utfx_result run_sync(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, uint64_t cap,
+                     bool be = false) {
   if (!c) return mkres(UTFX_E_INVALID_ARG, 0, 0);
   if (c->capturing) {
     set_msg(c, "synchronous call during graph capture");
     return mkres(UTFX_E_INVALID_ARG, 0, 0);
   }
-  utfx_status s = run(c, kind, in, n, out, cap, c->d_result);
+  utfx_status s = run(c, kind, in, n, out, cap, c->d_result, be);
   if (s != UTFX_OK) return mkres(s, 0, 0);
   hipError_t e = hipMemcpyAsync(c->h_result, c->d_result, sizeof(Result), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -477,6 +482,33 @@ utfx_status utfx_utf8_to_utf16le_async(utfx_ctx* c, const uint8_t* in, size_t n,
 utfx_status utfx_utf16le_to_utf8_async(utfx_ctx* c, const uint16_t* in, size_t n, uint8_t* out, size_t cap,
                                        utfx_result* r) {
   return run(c, U16U8, in, n, out, cap, r);
+}
+
+utfx_result utfx_utf8_length_from_utf16be(utfx_ctx* c, const uint16_t* in, size_t n) {
+  return run_sync(c, LEN16, in, n, nullptr, 0, true);
+}
+utfx_result utfx_validate_utf16be(utfx_ctx* c, const uint16_t* in, size_t n) {
+  return run_sync(c, VAL16, in, n, nullptr, 0, true);
+}
+utfx_result utfx_utf8_to_utf16be(utfx_ctx* c, const uint8_t* in, size_t n, uint16_t* out, size_t cap) {
+  return run_sync(c, U8U16, in, n, out, cap, true);
+}
+utfx_result utfx_utf16be_to_utf8(utfx_ctx* c, const uint16_t* in, size_t n, uint8_t* out, size_t cap) {
+  return run_sync(c, U16U8, in, n, out, cap, true);
+}
+utfx_status utfx_utf8_length_from_utf16be_async(utfx_ctx* c, const uint16_t* in, size_t n, utfx_result* r) {
+  return run(c, LEN16, in, n, nullptr, 0, r, true);
+}
+utfx_status utfx_validate_utf16be_async(utfx_ctx* c, const uint16_t* in, size_t n, utfx_result* r) {
+  return run(c, VAL16, in, n, nullptr, 0, r, true);
+}
+utfx_status utfx_utf8_to_utf16be_async(utfx_ctx* c, const uint8_t* in, size_t n, uint16_t* out, size_t cap,
+                                       utfx_result* r) {
+  return run(c, U8U16, in, n, out, cap, r, true);
+}
+utfx_status utfx_utf16be_to_utf8_async(utfx_ctx* c, const uint16_t* in, size_t n, uint8_t* out, size_t cap,
+                                       utfx_result* r) {
+  return run(c, U16U8, in, n, out, cap, r, true);
 }
 
 utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes, uint8_t* out_arena,

@@ -121,6 +121,7 @@ __device__ __forceinline__ Launch item_launch(const BatchArgs& A, const BItem& i
   L.seg_units = it.dir ? BSEG16 : BSEG8;
   L.seg = it.dir ? BS16 : BS8;
   L.wg = BWG;
+  L.be = 0;
   return L;
 }
 

@@ -63,7 +63,13 @@ struct Launch {
   uint64_t seg_units;   // input units per segment
   uint32_t seg;         // tiles (one 16-byte chunk per thread) per segment
   uint32_t wg;          // threads per workgroup of the main kernel
+  uint32_t be;          // UTF-16 side is big-endian: input words (UTF-16 -> UTF-8) or
+                        // output words (UTF-8 -> UTF-16) have their bytes swapped
 };
+
+// Swaps the bytes of both 16-bit halves (UTF-16BE <-> UTF-16LE code units).
+__device__ __forceinline__ uint32_t bswap16x2(uint32_t v) { return __builtin_amdgcn_perm(v, v, 0x02030001u); }
+__device__ __forceinline__ uint32_t bswap16(uint32_t w) { return ((w & 0xFFu) << 8) | ((w >> 8) & 0xFFu); }
 
 // Result record layout (matches utfx_result in utfx.h).
 struct Result {

@@ -348,6 +348,10 @@ __device__ __forceinline__ void load16(const Launch& L, uint64_t q0, uint32_t x[
       if (q >= lo && q < hi) x[i >> 1] |= (uint32_t)b[q] << (16 * (i & 1));
     }
   }
+  if (L.be) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = bswap16x2(x[k]);
+  }
 }
 
 __device__ __forceinline__ uint32_t load16_prev(const Launch& L, uint64_t q0) {
@@ -355,7 +359,8 @@ __device__ __forceinline__ uint32_t load16_prev(const Launch& L, uint64_t q0) {
   const uint64_t lo = L.mis, hi = L.mis + L.n;
   const uint64_t q = q0 - 1;
   const uint16_t* b = reinterpret_cast<const uint16_t*>(L.base);
-  return (q >= lo && q < hi) ? (uint32_t)b[q] : 0u;
+  if (!(q >= lo && q < hi)) return 0u;
+  return L.be ? bswap16(b[q]) : (uint32_t)b[q];
 }
 
 __device__ __forceinline__ bool is_hi(uint32_t w) { return (w & 0xFC00u) == 0xD800u; }
@@ -423,13 +428,14 @@ __device__ __forceinline__ bool any_surrogate(const uint32_t x[4], uint32_t wp) 
 }
 
 // Exact first unpaired surrogate among [p_lo, p_hi) clipped to [0, n) (sections 2.1, 7.4).
-__device__ uint64_t locate16(const uint16_t* in, uint64_t n, int64_t p_lo, int64_t p_hi) {
+__device__ uint64_t locate16(const uint16_t* in, uint64_t n, int64_t p_lo, int64_t p_hi, bool be = false) {
   if (p_lo < 0) p_lo = 0;
   if (p_hi > (int64_t)n) p_hi = (int64_t)n;
+  auto rd = [&](int64_t j) { return be ? bswap16(in[j]) : (uint32_t)in[j]; };
   for (int64_t j = p_lo; j < p_hi; ++j) {
-    const uint32_t w = in[j];
-    if (is_hi(w) && ((uint64_t)j + 1 >= n || !is_lo(in[j + 1]))) return (uint64_t)j;
-    if (is_lo(w) && (j == 0 || !is_hi(in[j - 1]))) return (uint64_t)j;
+    const uint32_t w = rd(j);
+    if (is_hi(w) && ((uint64_t)j + 1 >= n || !is_lo(rd(j + 1)))) return (uint64_t)j;
+    if (is_lo(w) && (j == 0 || !is_hi(rd(j - 1)))) return (uint64_t)j;
   }
   return NO_ERR;
 }
@@ -648,7 +654,7 @@ __global__ void __launch_bounds__(WG) k_validate16(Launch L) {
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
       if (before(p0 - 1, werr)) {
         const uint16_t* in = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
-        const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
+        const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8, L.be != 0);
         if (e != NO_ERR) atomicMin(&werr, (unsigned long long)e);
       }
     }

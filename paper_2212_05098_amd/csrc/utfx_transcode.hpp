@@ -38,7 +38,7 @@ __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t first) {
 // beyond cap are never stored.  The stage must hold 16 readable bytes past s0 + total.
 template <typename U>
 __device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t total, U* out, uint64_t base,
-                                           uint64_t cap, uint32_t tid, uint32_t nthr) {
+                                           uint64_t cap, uint32_t tid, uint32_t nthr, bool swap16 = false) {
   constexpr uint32_t PER = 16 / sizeof(U);
   const uint32_t d = (uint32_t)((((uintptr_t)out / sizeof(U)) + base) & (PER - 1));
   const uint32_t nch = (d + total + PER - 1) / PER;
@@ -56,13 +56,22 @@ __device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t
       o.y = abyte(v2, v1, sh);
       o.z = abyte(v3, v2, sh);
       o.w = abyte(v4, v3, sh);
+      if (sizeof(U) == 2 && swap16) {
+        o.x = bswap16x2(o.x);
+        o.y = bswap16x2(o.y);
+        o.z = bswap16x2(o.z);
+        o.w = bswap16x2(o.w);
+      }
       *reinterpret_cast<uint4*>(out + g0) = o;
     } else {
 #pragma unroll
       for (uint32_t i = 0; i < PER; ++i) {
         const int64_t l = (int64_t)(l0 + i) - (int64_t)d;
         const int64_t g = g0 + (int64_t)i;
-        if (l >= 0 && l < (int64_t)total && g >= 0 && g < (int64_t)cap) out[g] = stage[s0 + (uint32_t)l];
+        if (l >= 0 && l < (int64_t)total && g >= 0 && g < (int64_t)cap) {
+          const U v = stage[s0 + (uint32_t)l];
+          out[g] = (sizeof(U) == 2 && swap16) ? (U)bswap16(v) : v;
+        }
       }
     }
   }
@@ -323,7 +332,7 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
   st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
   const int64_t g = (int64_t)sm.seg_base + (int64_t)st0 - (int64_t)PAD;
   store_span<uint16_t>(stage, st0, st1 - st0, reinterpret_cast<uint16_t*>(L.out), (uint64_t)g, L.cap,
-                       threadIdx.x, WG);
+                       threadIdx.x, WG, L.be != 0);
 }
 
 template <int WG, int S>
@@ -550,6 +559,12 @@ __device__ __forceinline__ void load_seg16(const Launch& L, uint64_t seg, uint32
       const uint4 v = *reinterpret_cast<const uint4*>(in16 + q00 + (uint64_t)k * TW);
       x[k][0] = v.x; x[k][1] = v.y; x[k][2] = v.z; x[k][3] = v.w;
     }
+    if (L.be) {
+#pragma unroll
+      for (int k = 0; k < S; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[k][j] = bswap16x2(x[k][j]);
+    }
   } else {
 #pragma unroll
     for (int k = 0; k < S; ++k) load16(L, q00 + (uint64_t)k * TW, x[k]);
@@ -621,7 +636,7 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
       const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
       if (before(p0 - 1, sm.werr)) {
         const uint16_t* in = in16 + L.mis;
-        const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8);
+        const uint64_t e = locate16(in, L.n, p0 - 1, p0 + 8, L.be != 0);
         if (e != NO_ERR) atomicMin(&sm.werr, (unsigned long long)e);
       }
     }

@@ -93,3 +93,44 @@ def check_u16_to_u8(ctx, words, cap=None, in_shift=0, out_shift=0, guard=64):
     ln = ctx.utf8_length_from_utf16le(src)
     assert tuple(ln) == tuple(O.utf8_length_from_utf16le(words))
     return r
+
+
+def check_u8_to_u16be(ctx, data, cap=None, in_shift=0, out_shift=0, guard=64):
+    """UTF-8 -> UTF-16BE on the GPU against the oracle; `out` compared as the bytes
+    in memory, and nothing written outside [0, cap)."""
+    import torch
+
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    cap = data.size if cap is None else cap
+    src, _ = dev_u8(data, pad_front=in_shift)
+    out_back = torch.full((out_shift + cap + guard,), 0x5A5A, dtype=torch.int16, device="cuda")
+    dst = out_back[out_shift:out_shift + cap]
+    r = ctx.utf8_to_utf16be(src, dst)
+    want, ref = O.utf8_to_utf16be(data, cap=cap)
+    assert tuple(r) == tuple(want), (r, want)
+    got = host_u16(out_back)
+    w = min(r.written, cap)
+    assert np.array_equal(got[out_shift:out_shift + w], ref[:w])
+    assert np.all(got[:out_shift] == 0x5A5A) and np.all(got[out_shift + cap:] == 0x5A5A)
+    return r
+
+
+def check_u16be_to_u8(ctx, words_be, cap=None, in_shift=0, out_shift=0, guard=64):
+    """`words_be` is the UTF-16BE buffer as the uint16 array that holds its bytes."""
+    import torch
+
+    words_be = np.ascontiguousarray(words_be, dtype=np.uint16)
+    cap = 3 * words_be.size if cap is None else cap
+    src, _ = dev_u16(words_be, pad_front_words=in_shift)
+    out_back = torch.full((out_shift + cap + guard,), 0xA5, dtype=torch.uint8, device="cuda")
+    dst = out_back[out_shift:out_shift + cap]
+    r = ctx.utf16be_to_utf8(src, dst)
+    want, ref = O.utf16be_to_utf8(words_be, cap=cap)
+    assert tuple(r) == tuple(want), (r, want)
+    got = host_u8(out_back)
+    w = min(r.written, cap)
+    assert np.array_equal(got[out_shift:out_shift + w], ref[:w])
+    assert np.all(got[:out_shift] == 0xA5) and np.all(got[out_shift + cap:] == 0xA5)
+    assert tuple(ctx.validate_utf16be(src)) == tuple(O.validate_utf16be(words_be))
+    assert tuple(ctx.utf8_length_from_utf16be(src)) == tuple(O.utf8_length_from_utf16be(words_be))
+    return r

@@ -118,6 +118,36 @@ def test_all_scalar_values_against_python_codecs():
     assert O.validate_utf16le(u16) == O.Result(O.OK, u16.size, u16.size)
 
 
+def test_utf16be_against_python_codecs():
+    """UTF-16BE (section 2.2, bytes of each code unit in the other order): all scalar
+    values against CPython's utf-16-be codec both ways, and every string of length <= 4
+    over the 12 representative words against its strict decoder's verdict and offset."""
+    s = all_scalar_values_str()
+    u8 = np.frombuffer(s.encode("utf-8"), dtype=np.uint8)
+    be = s.encode("utf-16-be")
+    words = np.frombuffer(be, dtype=np.uint16)  # the buffer as it sits in memory
+    r, out = O.utf8_to_utf16be(u8)
+    assert r == O.Result(O.OK, words.size, words.size)
+    assert out[: r.written].tobytes() == be
+    r, out = O.utf16be_to_utf8(words)
+    assert r == O.Result(O.OK, u8.size, u8.size)
+    assert np.array_equal(out[: r.written], u8)
+    assert O.utf8_length_from_utf16be(words).count == u8.size
+    assert O.validate_utf16be(words) == O.Result(O.OK, words.size, words.size)
+    assert O.utf16be_to_utf8(be)[0] == O.Result(O.OK, u8.size, u8.size)
+    for L in range(1, 5):
+        strs = _all_strings(ALPHA16, L).astype(np.uint16)
+        for i in range(strs.shape[0]):
+            b = strs[i].astype(">u2").tobytes()
+            try:
+                b.decode("utf-16-be")
+                want = (O.OK, L)
+            except UnicodeDecodeError as e:
+                want = (O.E_SURROGATE, e.start // 2)
+            got = O.validate_utf16be(np.frombuffer(b, dtype=np.uint16))
+            assert (got.status, got.count) == want, strs[i]
+
+
 def test_encoded_surrogates_rejected():
     """Rule 6: the 2,048 surrogate code points in 3-byte form (built by Python's
     surrogatepass handler) are each a SURROGATE error at offset 0."""
