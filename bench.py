@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--serve-inflight", type=int, default=3, help="server steps in flight")
     ap.add_argument("--small-calls", type=int, default=200, help="64 KiB synchronous calls timed (0 = skip)")
     ap.add_argument("--run-mib", type=int, default=64, help="run-structured buffers per profile (MiB, 0 = skip)")
+    ap.add_argument("--stream-chunks", default="1,16",
+                    help="chunk sizes (MiB) of the stream runs over one mixed buffer (empty = skip)")
+    ap.add_argument("--stream-mib", type=int, default=256, help="stream length (MiB)")
     ap.add_argument("--no-tune-cache", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
@@ -231,6 +234,7 @@ def main():
 
     small = run_small(ctx, log, args.small_calls) if args.small_calls else None
     runs = run_structured(ctx, log, args.run_mib) if args.run_mib else None
+    streamed = run_stream(ctx, log, args.stream_mib, args.stream_chunks) if args.stream_chunks else None
     batch = run_batch(args, ctx, log) if args.batch_strings else None
     serving = run_serving(args, log) if args.serve_rates else None
 
@@ -262,6 +266,7 @@ def main():
         "per_case": per_case,
         "small_64KiB": small,
         "run_structured": runs,
+        "stream": streamed,
         "batched": batch,
         "serving": serving,
     }
@@ -300,6 +305,59 @@ def run_small(ctx, log, reps=200):
            "utf16le_to_utf8_us_p50": round(float(np.median(ts[:, 1])), 1), "calls": reps}
     log("64 KiB sync calls: utf8->utf16le %.1f us, utf16le->utf8 %.1f us (p50), round trip %s" %
         (out["utf8_to_utf16le_us_p50"], out["utf16le_to_utf8_us_p50"], "ok" if ok else "MISMATCH"))
+    return out
+
+
+def run_stream(ctx, log, mib, chunk_list, reps=3):
+    """One mixed-profile UTF-8 buffer passed as a stream of chunks (each chunk one byte
+    longer than a whole number of MiB, so cuts fall inside characters), UTF-8 ->
+    UTF-16LE: wall time of the whole stream beside one synchronous call on the buffer;
+    the streamed output is checked against the one-call output."""
+    import numpy as np
+    import torch
+
+    import paper_2212_05098_amd as utfx
+    from paper_2212_05098_amd import synth
+
+    data = synth.config_buffer("mixed4", synth.DIR_8TO16, mib << 20, config=2)
+    n = data.size
+    src = torch.from_numpy(data).cuda()
+    whole = torch.empty(n, dtype=torch.int16, device="cuda")
+    dst = torch.empty(n, dtype=torch.int16, device="cuda")
+    r = ctx.utf8_to_utf16le(src, whole)
+    assert r.status == utfx.OK
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.utf8_to_utf16le(src, whole)
+        ts.append(time.perf_counter() - t0)
+    one = float(np.median(ts))
+    out = {"mib": mib, "profile": "mixed4", "dir": "utf8->utf16le", "one_call_ms": round(one * 1e3, 3),
+           "runs": []}
+    log("stream %d MiB mixed4 utf8->utf16le: one synchronous call %.3f ms" % (mib, one * 1e3))
+    for c in [int(x) for x in chunk_list.split(",") if x]:
+        chunk = (c << 20) + 1
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.open_stream(utfx.STREAM_UTF8_TO_UTF16LE)
+            pos, calls = 0, 0
+            for a in range(0, n, chunk):
+                b = min(n, a + chunk)
+                rr = st.transcode(src[a:b], dst[pos:pos + st.n_carry + (b - a)], final=b == n)
+                pos += rr.written
+                calls += 1
+            ts.append(time.perf_counter() - t0)
+            assert rr.status == utfx.OK and pos == r.written
+        ok = bool(torch.equal(dst[:pos], whole[:pos]))
+        t = float(np.median(ts))
+        out["runs"].append({"chunk_bytes": chunk, "calls": calls, "ms": round(t * 1e3, 3),
+                            "in_GBps": round(n / t / 1e9, 1), "us_per_call": round(t / calls * 1e6, 1),
+                            "matches_one_call": ok})
+        log("stream chunks of %d MiB + 1 B: %d calls, %.3f ms (%.1f GB/s, %.1f us per call), output %s" %
+            (c, calls, t * 1e3, n / t / 1e9, t / calls * 1e6, "matches" if ok else "MISMATCH"))
     return out
 
 

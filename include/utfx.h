@@ -158,9 +158,9 @@ utfx_status utfx_utf16le_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t
                                        uint8_t *out, size_t cap_bytes, utfx_result *d_result);
 
 /* ---- UTF-16BE ------------------------------------------------------------------
- * The same operations with big-endian UTF-16 code units (section 3: the paper's
- * UTF-16 is little-endian, and big-endian input or output differs only by the byte
- * order within each 16-bit unit, which the kernels swap on load or on store).
+ * The same operations with big-endian UTF-16 code units (section 2: the paper works
+ * in UTF-16LE, and big-endian input or output differs only by the byte order within
+ * each 16-bit unit, which the kernels swap on load or on store).
  * Arguments, results and errors are exactly those of the UTF-16LE calls above. */
 utfx_result utfx_utf8_length_from_utf16be(utfx_ctx *ctx, const uint16_t *in, size_t n_words);
 utfx_result utfx_validate_utf16be(utfx_ctx *ctx, const uint16_t *in, size_t n_words);
@@ -176,6 +176,65 @@ utfx_status utfx_utf8_to_utf16be_async(utfx_ctx *ctx, const uint8_t *in, size_t 
                                        uint16_t *out, size_t cap_words, utfx_result *d_result);
 utfx_status utfx_utf16be_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
                                        uint8_t *out, size_t cap_bytes, utfx_result *d_result);
+
+/* ---- streams: input in chunks cut at any unit offset -------------------------
+ * A stream transcodes input that arrives in pieces.  Its result is the result of the
+ * single-buffer call on the concatenation of all its chunks: the same output, split
+ * over the calls, and the same first error at the same stream offset.  Each call
+ * transcodes every character that is complete by the end of its chunk and carries
+ * the unfinished one (at most 3 bytes of UTF-8, or one high surrogate of UTF-16) in
+ * the stream state to the next call, so that, as in section 6, the input advances by
+ * whole sequences only, and, as with the surrogate carry of section 7.4, a high
+ * surrogate at the end of a chunk is paired with the first word of the next.  The
+ * state lives on the host and holds no device memory. */
+typedef enum {
+  UTFX_STREAM_UTF8_TO_UTF16LE = 0,
+  UTFX_STREAM_UTF16LE_TO_UTF8 = 1,
+  UTFX_STREAM_UTF8_TO_UTF16BE = 2,
+  UTFX_STREAM_UTF16BE_TO_UTF8 = 3
+} utfx_stream_format;
+
+typedef struct {
+  uint64_t in_units;   /* input units passed in so far (carried units included) */
+  uint64_t out_units;  /* output units written so far */
+  uint64_t err_offset; /* stream offset of the encoding error that ended the stream */
+  int32_t format;      /* utfx_stream_format */
+  int32_t status;      /* UTFX_OK, or that encoding error */
+  uint32_t n_carry;    /* units carried into the next call: 0..3 bytes, or 0..1 word */
+  uint32_t finished;   /* 1 after a successful call with final != 0 */
+  uint8_t carry[4];    /* the carried units as they were in memory */
+  uint8_t carry_need;  /* units the carried character still needs */
+  uint8_t carry_out;   /* output units it makes once complete and valid */
+  uint16_t reserved;
+} utfx_stream;
+
+/* Starts a stream (any previous state is discarded).  UTFX_E_INVALID_ARG for a null
+ * state or an unknown format.  Host only: launches nothing. */
+utfx_status utfx_stream_init(utfx_stream *st, int format);
+
+/* Passes the next chunk: in (device; UTF-16 2-byte aligned) holds n_units input
+ * units, out (device; UTF-16 2-byte aligned) has room for cap_units output units.
+ * final != 0 marks the last chunk: a character left unfinished there is an error
+ * (UTFX_E_MISSING_CONT, or UTFX_E_SURROGATE for a high surrogate) instead of being
+ * carried.  Room for (n_carry + n_units) units of output (UTF-16 out), or three times
+ * that (UTF-8 out), always suffices.  Synchronous: it blocks until the result is on
+ * the host; not allowed during graph capture.
+ *   OK:               count = written = output units stored by this call in
+ *                     out[0:written]; the state advances (in_units += n_units).
+ *   encoding error:   count = offset of the first invalid unit in the whole stream
+ *                     (stream offsets start at 0 with the first chunk's first unit);
+ *                     written = output units of the valid characters before it that
+ *                     this call produced, in out[0:min(written, cap)].  The stream is
+ *                     then over: later calls return the same status and offset with
+ *                     written = 0 until utfx_stream_init.
+ *   OUTPUT_TOO_SMALL: count = output units this call needs, written = 0; the state
+ *                     does not change, so the same chunk can be passed again with a
+ *                     larger buffer.
+ *   INVALID_ARG:      null or malformed state, bad pointers, or a call after the
+ *                     final chunk; the state does not change.
+ * Output beyond `written` is unspecified; nothing is stored at or beyond cap. */
+utfx_result utfx_stream_transcode(utfx_ctx *ctx, utfx_stream *st, const void *in, size_t n_units,
+                                  void *out, size_t cap_units, int final);
 
 /* ---- batched: many independent strings in one call ---------------------------- */
 /* One string.  in_off/out_off are byte offsets into the arenas; in_len is in input

@@ -167,7 +167,7 @@ def utf16le_to_utf8(data, cap: Optional[int] = None):
     return r, out
 
 
-# ---- UTF-16BE (section 2.2: the same code units, most significant byte first) ------
+# ---- UTF-16BE (section 2: the same code units, most significant byte first) --------
 # A UTF-16BE buffer is handled as the uint16 array that holds its bytes in memory; on
 # a little-endian host each element is then the byte-swapped code unit, so these
 # wrappers swap every element and defer to the functions above.

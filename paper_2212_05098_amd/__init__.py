@@ -53,6 +53,29 @@ class CResult(ctypes.Structure):
     ]
 
 
+class CStream(ctypes.Structure):
+    """utfx_stream: the host-side state of a stream (carried units, offsets, verdict)."""
+    _fields_ = [
+        ("in_units", ctypes.c_uint64),
+        ("out_units", ctypes.c_uint64),
+        ("err_offset", ctypes.c_uint64),
+        ("format", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("n_carry", ctypes.c_uint32),
+        ("finished", ctypes.c_uint32),
+        ("carry", ctypes.c_uint8 * 4),
+        ("carry_need", ctypes.c_uint8),
+        ("carry_out", ctypes.c_uint8),
+        ("reserved", ctypes.c_uint16),
+    ]
+
+
+STREAM_UTF8_TO_UTF16LE = 0
+STREAM_UTF16LE_TO_UTF8 = 1
+STREAM_UTF8_TO_UTF16BE = 2
+STREAM_UTF16BE_TO_UTF8 = 3
+
+
 class Result(NamedTuple):
     status: int
     count: int
@@ -118,6 +141,8 @@ def lib() -> ctypes.CDLL:
         "utfx_validate_utf16be_async": (I, [P, P, Z, P]),
         "utfx_utf8_to_utf16be_async": (I, [P, P, Z, P, Z, P]),
         "utfx_utf16be_to_utf8_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_stream_init": (I, [ctypes.POINTER(CStream), I]),
+        "utfx_stream_transcode": (CResult, [P, ctypes.POINTER(CStream), P, Z, P, Z, I]),
         "utfx_batch_run": (I, [P, P, Z, P, Z, P, U32, U64, P]),
         "utfx_capture_begin": (I, [P]),
         "utfx_capture_end": (I, [P, ctypes.POINTER(P)]),
@@ -340,6 +365,10 @@ class Context:
         )
 
 
+    # ---- streams
+    def open_stream(self, fmt: int) -> "Stream":
+        return Stream(self, fmt)
+
     # ---- HIP graphs
     def capture_begin(self):
         st = self._lib.utfx_capture_begin(self._h)
@@ -352,6 +381,42 @@ class Context:
         if st != OK:
             raise UtfxError("capture_end: %d %s" % (st, self.last_error()))
         return Graph(self, g)
+
+
+class Stream:
+    """Input in chunks cut at any unit offset (utfx_stream_init / utfx_stream_transcode):
+    the concatenated outputs and the first error equal those of one call on the
+    concatenated chunks."""
+
+    def __init__(self, ctx: "Context", fmt: int):
+        self.ctx = ctx
+        self.state = CStream()
+        st = ctx._lib.utfx_stream_init(ctypes.byref(self.state), int(fmt))
+        if st != OK:
+            raise UtfxError("stream_init: bad format %r" % (fmt,))
+        self.in16 = fmt in (STREAM_UTF16LE_TO_UTF8, STREAM_UTF16BE_TO_UTF8)
+
+    def transcode(self, src, dst, final: bool = False) -> Result:
+        p, n = _ptr_len(src, 2 if self.in16 else 1)
+        q, cap = _ptr_len(dst, 1 if self.in16 else 2)
+        return _res(self.ctx._lib.utfx_stream_transcode(self.ctx._h, ctypes.byref(self.state), p, n, q, cap,
+                                                        1 if final else 0))
+
+    def raw(self, p, n: int, q, cap: int, final: bool = False) -> Result:
+        return _res(self.ctx._lib.utfx_stream_transcode(self.ctx._h, ctypes.byref(self.state), p, n, q, cap,
+                                                        1 if final else 0))
+
+    @property
+    def n_carry(self) -> int:
+        return int(self.state.n_carry)
+
+    @property
+    def in_units(self) -> int:
+        return int(self.state.in_units)
+
+    @property
+    def out_units(self) -> int:
+        return int(self.state.out_units)
 
 
 class Graph:

@@ -16,12 +16,15 @@
 #include "utfx_kernels.hpp"
 #include "utfx_transcode.hpp"
 #include "utfx_batch.hpp"
+#include "utfx_stream.hpp"
 
 using namespace utfx_dev;
 
 static_assert(sizeof(utfx_result) == 24, "utfx_result layout");
 static_assert(sizeof(Result) == sizeof(utfx_result), "device result layout");
 static_assert(sizeof(WsHeader) == 64, "workspace header layout");
+static_assert(sizeof(utfx_stream) == 48 && offsetof(utfx_stream, carry) == 40 && offsetof(utfx_stream, carry_need) == 44,
+              "stream state layout");
 static_assert(sizeof(utfx_item) == sizeof(BItem) && offsetof(utfx_item, dir) == offsetof(BItem, dir), "item layout");
 
 struct utfx_ctx {
@@ -33,6 +36,8 @@ struct utfx_ctx {
   uint64_t cap_tiles = 0;
   Result* d_result = nullptr;             // device result slot of synchronous calls
   Result* h_result = nullptr;             // pinned host copy
+  StreamDev* d_stream = nullptr;          // stream calls: cut description, staged character, results
+  StreamDev* h_stream = nullptr;          // pinned host copy
   uint64_t launches = 0;                  // launches since the status words were cleared
   uint32_t tile_bytes[UTFX_OP_COUNT_];
   uint32_t seg_tiles[UTFX_OP_COUNT_];
@@ -365,9 +370,168 @@ utfx_result run_sync(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* o
   return r;
 }
 
+bool encoding_error(int32_t st) { return st >= UTFX_E_STRAY_CONT && st <= UTFX_E_BAD_BYTE; }
+
+// One stream call: k_stream_edge stages and transcodes the character across the cut
+// (piece 1) and finds the unfinished one at the chunk's end, piece 2 (the rest of the
+// chunk, in place) runs as an ordinary single-buffer transcode, and one copy brings
+// everything back.  The host does offsets only; every unit is looked at on the
+// device.
+utfx_result stream_transcode(utfx_ctx* c, utfx_stream* st, const void* in, uint64_t n, void* out, uint64_t cap,
+                             bool final) {
+  if (!c) return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  c->err[0] = 0;
+  if (!st || st->format < UTFX_STREAM_UTF8_TO_UTF16LE || st->format > UTFX_STREAM_UTF16BE_TO_UTF8) {
+    set_msg(c, "null or malformed stream state");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  const bool in16 = (st->format == UTFX_STREAM_UTF16LE_TO_UTF8 || st->format == UTFX_STREAM_UTF16BE_TO_UTF8);
+  const bool be = (st->format == UTFX_STREAM_UTF8_TO_UTF16BE || st->format == UTFX_STREAM_UTF16BE_TO_UTF8);
+  if (st->status != UTFX_OK) {
+    if (!encoding_error(st->status)) {
+      set_msg(c, "malformed stream state");
+      return mkres(UTFX_E_INVALID_ARG, 0, 0);
+    }
+    return mkres(st->status, st->err_offset, 0);
+  }
+  if (st->finished) {
+    set_msg(c, "stream already finished");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  const uint32_t nc = st->n_carry;
+  if (nc > (in16 ? 1u : 3u) || (nc > 0) != (st->carry_need > 0) || st->carry_need > 3 || st->carry_out > 4) {
+    set_msg(c, "malformed stream state");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  if (c->capturing) {
+    set_msg(c, "synchronous call during graph capture");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  if (n > 0 && !in) {
+    set_msg(c, "null input with n > 0");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  if (n > UTFX_MAX_UNITS) {
+    set_msg(c, "input longer than UTFX_MAX_UNITS");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  if (in16 && (reinterpret_cast<uintptr_t>(in) & 1)) {
+    set_msg(c, "UTF-16 input not 2-byte aligned");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  if (cap > 0 && !out) {
+    set_msg(c, "null output with cap > 0");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  if (!in16 && (reinterpret_cast<uintptr_t>(out) & 1)) {
+    set_msg(c, "UTF-16 output not 2-byte aligned");
+    return mkres(UTFX_E_INVALID_ARG, 0, 0);
+  }
+  if (n == 0 && nc == 0) {
+    if (final) st->finished = 1;
+    return mkres(UTFX_OK, 0, 0);
+  }
+  const uint64_t h = nc ? (n < st->carry_need ? n : st->carry_need) : 0;
+  const bool grow = nc && !final && h < st->carry_need;  // the chunk does not finish the carried character
+  uint32_t carry = 0;
+  memcpy(&carry, st->carry, 4);
+  const uint32_t flags = (in16 ? SE_IN16 : 0u) | (be ? SE_BE : 0u) | (final ? SE_FINAL : 0u);
+  hipLaunchKernelGGL(k_stream_edge, dim3(1), dim3(64), 0, c->stream, c->d_stream, in, n, h, carry, nc, flags,
+                     grow ? 1u : 0u, out, cap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_err(c, "stream edge launch", e);
+    return mkres(UTFX_E_DEVICE, 0, 0);
+  }
+  const Kind kind = in16 ? U16U8 : U8U16;
+  const uint64_t iu = in16 ? 2 : 1, ou = in16 ? 1 : 2;
+  const bool p1 = nc > 0 && !grow, p2 = !grow && n > h;
+  const uint64_t w1 = p1 ? st->carry_out : 0;  // piece 2's output starts after piece 1's
+  const uint64_t cap2 = cap > w1 ? cap - w1 : 0;
+  if (p2) {
+    void* out2 = cap2 ? static_cast<void*>(static_cast<uint8_t*>(out) + w1 * ou) : nullptr;
+    utfx_status s = run(c, kind, static_cast<const uint8_t*>(in) + h * iu, n - h, out2, cap2, &c->d_stream->r[1], be);
+    if (s != UTFX_OK) return mkres(s, 0, 0);
+  }
+  e = hipMemcpyAsync(c->h_stream, c->d_stream, sizeof(StreamDev), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    set_err(c, "synchronise", e);
+    return mkres(UTFX_E_DEVICE, 0, 0);
+  }
+  const StreamEdge cut = c->h_stream->e;
+  Result r1{UTFX_OK, 0, 0, 0}, r2{UTFX_OK, 0, 0, 0};
+  if (p1) r1 = c->h_stream->r[0];
+  if (p2) r2 = c->h_stream->r[1];
+  if (r1.status == UTFX_E_DEVICE || r2.status == UTFX_E_DEVICE) {
+    set_msg(c, "look-back watchdog fired; workspace reinitialised");
+    init_ws(c);
+    return mkres(UTFX_E_DEVICE, 0, 0);
+  }
+  if (cut.t > n || cut.t < (grow ? n : h) || cut.n_keep != (grow ? nc + h : n - cut.t) ||
+      cut.n_keep > (in16 ? 1u : 3u) || cut.keep_need > 3 || cut.keep_out > 4 || (cut.n_keep > 0) != (cut.keep_need > 0)) {
+    set_msg(c, "stream cut out of range");
+    return mkres(UTFX_E_DEVICE, 0, 0);
+  }
+  if (p2 && cut.t < n && encoding_error(r2.status) && r2.count == cut.t - h) {
+    // the only error is the unfinished character at the end, which is carried: piece 2
+    // is chunk[h, t), whose output is complete
+    r2.status = r2.written > cap2 ? UTFX_E_OUTPUT_TOO_SMALL : UTFX_OK;
+    r2.count = r2.written;
+    if (r2.status != UTFX_OK) r2.written = 0;
+  }
+  const uint64_t base = st->in_units;  // stream offset of the chunk's first unit
+  if (encoding_error(r1.status) || encoding_error(r2.status)) {
+    utfx_result r;
+    if (encoding_error(r1.status)) {
+      r = mkres(r1.status, base - nc + r1.count, r1.written);
+    } else {
+      r = mkres(r2.status, base + h + r2.count, w1 + r2.written);
+    }
+    st->status = r.status;
+    st->err_offset = r.count;
+    st->in_units = base + n;
+    st->out_units += r.written;
+    st->n_carry = 0;
+    st->carry_need = 0;
+    st->carry_out = 0;
+    return r;
+  }
+  // piece 2 was placed after w1 output units: piece 1 must have needed exactly that many
+  if (p1 && r1.count != w1) {
+    set_msg(c, "stream state disagrees with the staged character");
+    return mkres(UTFX_E_DEVICE, 0, 0);
+  }
+  const uint64_t total = r1.count + r2.count;  // OK: units written; OUTPUT_TOO_SMALL: units needed
+  if (r1.status == UTFX_E_OUTPUT_TOO_SMALL || r2.status == UTFX_E_OUTPUT_TOO_SMALL)
+    return mkres(UTFX_E_OUTPUT_TOO_SMALL, total, 0);
+  st->in_units = base + n;
+  st->out_units += total;
+  st->n_carry = cut.n_keep;
+  memcpy(st->carry, cut.keep, 4);
+  st->carry_need = static_cast<uint8_t>(cut.keep_need);
+  st->carry_out = static_cast<uint8_t>(cut.keep_out);
+  if (final) st->finished = 1;
+  return mkres(UTFX_OK, total, total);
+}
+
 }  // namespace
 
 extern "C" {
+
+utfx_status utfx_stream_init(utfx_stream* st, int format) {
+  if (!st || format < UTFX_STREAM_UTF8_TO_UTF16LE || format > UTFX_STREAM_UTF16BE_TO_UTF8)
+    return UTFX_E_INVALID_ARG;
+  memset(st, 0, sizeof(*st));
+  st->format = format;
+  st->status = UTFX_OK;
+  return UTFX_OK;
+}
+
+utfx_result utfx_stream_transcode(utfx_ctx* c, utfx_stream* st, const void* in, size_t n, void* out, size_t cap,
+                                  int final) {
+  return stream_transcode(c, st, in, n, out, cap, final != 0);
+}
 
 utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
   if (!out) return UTFX_E_INVALID_ARG;
@@ -393,6 +557,9 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
   }
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_result), sizeof(Result));
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(Result), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_stream), sizeof(StreamDev));
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->h_stream), sizeof(StreamDev), hipHostMallocDefault);
   if (e != hipSuccess) {
     utfx_destroy(c);
     return UTFX_E_DEVICE;
@@ -412,6 +579,8 @@ void utfx_destroy(utfx_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_result) (void)hipFree(c->d_result);
   if (c->h_result) (void)hipHostFree(c->h_result);
+  if (c->d_stream) (void)hipFree(c->d_stream);
+  if (c->h_stream) (void)hipHostFree(c->h_stream);
   delete c;
 }
 

@@ -456,3 +456,12 @@ def tile_edge_cases(tile_sizes: Sequence[int], n_bytes: int, rng: np.random.Gene
             c[edge] = 0xDE00
             cases.append((c, None))
     return cases
+
+
+def stream_cuts(n_units: int, rng: np.random.Generator, max_chunk: int, min_chunk: int = 0) -> List[int]:
+    """Chunk boundaries [0, c1, ..., n] of a stream cut at arbitrary unit offsets: chunk
+    lengths uniform in [min_chunk, max_chunk] (empty chunks included when min_chunk = 0)."""
+    cuts = [0]
+    while cuts[-1] < n_units:
+        cuts.append(min(n_units, cuts[-1] + int(rng.integers(min_chunk, max_chunk + 1))))
+    return cuts

@@ -54,6 +54,22 @@ def test_result_struct_layout():
     assert utfx.CResult.count.offset == 8 and utfx.CResult.written.offset == 16
 
 
+def test_stream_state_layout_and_init(libpath):
+    """utfx_stream matches the header's layout; utfx_stream_init is host-only (it
+    launches nothing), zeroes the state and rejects unknown formats and a null state."""
+    assert ctypes.sizeof(utfx.CStream) == 48 and utfx.CStream.carry.offset == 40
+    L = utfx.lib()
+    st = utfx.CStream()
+    ctypes.memset(ctypes.byref(st), 0x77, ctypes.sizeof(st))
+    assert L.utfx_stream_init(ctypes.byref(st), utfx.STREAM_UTF16BE_TO_UTF8) == utfx.OK
+    assert (st.in_units, st.out_units, st.err_offset, st.status, st.n_carry, st.finished) == (0, 0, 0, 0, 0, 0)
+    assert st.format == utfx.STREAM_UTF16BE_TO_UTF8 and bytes(st.carry) == bytes(4)
+    assert (st.carry_need, st.carry_out, st.reserved) == (0, 0, 0)
+    assert L.utfx_stream_init(ctypes.byref(st), 4) == utfx.E_INVALID_ARG
+    assert L.utfx_stream_init(ctypes.byref(st), -1) == utfx.E_INVALID_ARG
+    assert L.utfx_stream_init(None, 0) == utfx.E_INVALID_ARG
+
+
 def test_product_path_never_touches_the_oracle():
     """The library and its binding share nothing with oracle/ and never load it."""
     pkg = os.path.dirname(utfx.__file__)

@@ -119,7 +119,7 @@ def test_all_scalar_values_against_python_codecs():
 
 
 def test_utf16be_against_python_codecs():
-    """UTF-16BE (section 2.2, bytes of each code unit in the other order): all scalar
+    """UTF-16BE (section 2, bytes of each code unit in the other order): all scalar
     values against CPython's utf-16-be codec both ways, and every string of length <= 4
     over the 12 representative words against its strict decoder's verdict and offset."""
     s = all_scalar_values_str()
