@@ -1,4 +1,4 @@
-"""Scalar CPU oracle for validating UTF-8 <-> UTF-16LE (and UTF-16BE) transcoding.
+"""Scalar CPU oracle for validating UTF-8 <-> UTF-16LE (and UTF-16BE, UTF-32LE) transcoding.
 
 TEST INFRASTRUCTURE ONLY.  The test suite, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` are the only callers.  The GPU library never
@@ -91,6 +91,9 @@ def lib() -> ctypes.CDLL:
             ("utfx_ref_validate_utf16le", [p8, sz]),
             ("utfx_ref_utf8_to_utf16le", [p8, sz, p8, sz]),
             ("utfx_ref_utf16le_to_utf8", [p8, sz, p8, sz]),
+            ("utfx_ref_validate_utf32le", [p8, sz]),
+            ("utfx_ref_utf8_to_utf32le", [p8, sz, p8, sz]),
+            ("utfx_ref_utf32le_to_utf8", [p8, sz, p8, sz]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -196,6 +199,41 @@ def utf8_to_utf16be(data, cap: Optional[int] = None):
 
 def utf16be_to_utf8(data, cap: Optional[int] = None):
     return utf16le_to_utf8(_be_words(data), cap)
+
+
+# ---- UTF-32LE (section 2: one 32-bit integer per character) ------------------------
+
+def _u32(a) -> np.ndarray:
+    if isinstance(a, (bytes, bytearray, memoryview)):
+        b = bytes(a)
+        assert len(b) % 4 == 0
+        return np.frombuffer(b, dtype="<u4").astype(np.uint32)
+    a = np.ascontiguousarray(a)
+    assert a.dtype == np.uint32, a.dtype
+    return a
+
+
+def validate_utf32le(data) -> Result:
+    a = _u32(data)
+    return _res(lib().utfx_ref_validate_utf32le(_ptr(a), a.size))
+
+
+def utf8_to_utf32le(data, cap: Optional[int] = None):
+    """Returns (Result, out) where out is a uint32 array of length cap (default n)."""
+    a = _u8(data)
+    cap = a.size if cap is None else int(cap)
+    out = np.zeros(cap, dtype=np.uint32)
+    r = _res(lib().utfx_ref_utf8_to_utf32le(_ptr(a), a.size, _ptr(out), cap))
+    return r, out
+
+
+def utf32le_to_utf8(data, cap: Optional[int] = None):
+    """Returns (Result, out) where out is a uint8 array of length cap (default 4n)."""
+    a = _u32(data)
+    cap = 4 * a.size if cap is None else int(cap)
+    out = np.zeros(cap, dtype=np.uint8)
+    r = _res(lib().utfx_ref_utf32le_to_utf8(_ptr(a), a.size, _ptr(out), cap))
+    return r, out
 
 
 def validate_utf8_fixed(buf: np.ndarray, length: int, want_arrays: bool = True):

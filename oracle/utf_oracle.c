@@ -8,6 +8,9 @@
  *   section 2.2 + Table 1  UTF-8 byte types; shortest form only; nothing above
  *                U+10FFFF; C0, C1, F5..FF never appear.
  *   Figure 1(a)  which code-point bits go into which UTF-8 byte.
+ *   section 2    UTF-32: each character is one 32-bit integer, its code point; the
+ *                code-point space ends at U+10FFFF and U+D800..DFFF are surrogates,
+ *                not characters.
  *   section 6.4  the six validation rules; on an error the characters before it are
  *                transcoded and the call stops (sections 6.4 and 7.4).
  *
@@ -88,6 +91,16 @@ static int32_t decode_utf16_at(const uint16_t *in, size_t n, size_t i, uint32_t 
   if (w >= 0xDC00 && w <= 0xDFFF) return UTFX_REF_E_SURROGATE;
   *cp = w;
   *len = 1;
+  return UTFX_REF_OK;
+}
+
+/* Section 2: a UTF-32 unit is a character if it is a code point (at most 0x10FFFF)
+ * outside the surrogate range. */
+static int32_t decode_utf32_at(const uint32_t *in, size_t i, uint32_t *cp) {
+  uint32_t u = in[i];
+  if (u >= 0xD800 && u <= 0xDFFF) return UTFX_REF_E_SURROGATE;
+  if (u > 0x10FFFF) return UTFX_REF_E_TOO_LARGE;
+  *cp = u;
   return UTFX_REF_OK;
 }
 
@@ -188,6 +201,16 @@ utfx_ref_result utfx_ref_validate_utf16le(const uint16_t *in, size_t n) {
   return mk(UTFX_REF_OK, n, n);
 }
 
+utfx_ref_result utfx_ref_validate_utf32le(const uint32_t *in, size_t n) {
+  if (n > 0 && in == 0) return mk(UTFX_REF_E_INVALID_ARG, 0, 0);
+  for (size_t i = 0; i < n; i++) {
+    uint32_t cp;
+    int32_t st = decode_utf32_at(in, i, &cp);
+    if (st != UTFX_REF_OK) return mk(st, i, i);
+  }
+  return mk(UTFX_REF_OK, n, n);
+}
+
 /* ---- validating transcode ------------------------------------------------------ */
 
 utfx_ref_result utfx_ref_utf8_to_utf16le(const uint8_t *in, size_t n, uint16_t *out, size_t cap) {
@@ -227,6 +250,41 @@ utfx_ref_result utfx_ref_utf16le_to_utf8(const uint16_t *in, size_t n, uint8_t *
       o++;
     }
     i += len;
+  }
+  if (o > cap) return mk(UTFX_REF_E_OUTPUT_TOO_SMALL, o, 0);
+  return mk(UTFX_REF_OK, o, o);
+}
+
+utfx_ref_result utfx_ref_utf8_to_utf32le(const uint8_t *in, size_t n, uint32_t *out, size_t cap) {
+  if ((n > 0 && in == 0) || (cap > 0 && out == 0)) return mk(UTFX_REF_E_INVALID_ARG, 0, 0);
+  size_t i = 0;
+  uint64_t o = 0;
+  while (i < n) {
+    uint32_t cp;
+    size_t len;
+    int32_t st = decode_utf8_at(in, n, i, &cp, &len);
+    if (st != UTFX_REF_OK) return mk(st, i, o);
+    if (o < cap) out[o] = cp;
+    o++;
+    i += len;
+  }
+  if (o > cap) return mk(UTFX_REF_E_OUTPUT_TOO_SMALL, o, 0);
+  return mk(UTFX_REF_OK, o, o);
+}
+
+utfx_ref_result utfx_ref_utf32le_to_utf8(const uint32_t *in, size_t n, uint8_t *out, size_t cap) {
+  if ((n > 0 && in == 0) || (cap > 0 && out == 0)) return mk(UTFX_REF_E_INVALID_ARG, 0, 0);
+  uint64_t o = 0;
+  for (size_t i = 0; i < n; i++) {
+    uint32_t cp;
+    int32_t st = decode_utf32_at(in, i, &cp);
+    if (st != UTFX_REF_OK) return mk(st, i, o);
+    uint8_t b[4];
+    size_t k = encode_utf8(cp, b);
+    for (size_t j = 0; j < k; j++) {
+      if (o < cap) out[o] = b[j];
+      o++;
+    }
   }
   if (o > cap) return mk(UTFX_REF_E_OUTPUT_TOO_SMALL, o, 0);
   return mk(UTFX_REF_OK, o, o);

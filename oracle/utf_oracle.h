@@ -69,6 +69,14 @@ utfx_ref_result utfx_ref_utf8_to_utf16le(const uint8_t *in, size_t n_bytes,
 utfx_ref_result utfx_ref_utf16le_to_utf8(const uint16_t *in, size_t n_words,
                                          uint8_t *out, size_t cap_bytes);
 
+/* UTF-32LE (section 2: one 32-bit unit per character): a unit in U+D800..DFFF is a
+ * SURROGATE error, one above U+10FFFF a TOO_LARGE error, at its own offset. */
+utfx_ref_result utfx_ref_validate_utf32le(const uint32_t *in, size_t n_units);
+utfx_ref_result utfx_ref_utf8_to_utf32le(const uint8_t *in, size_t n_bytes,
+                                         uint32_t *out, size_t cap_units);
+utfx_ref_result utfx_ref_utf32le_to_utf8(const uint32_t *in, size_t n_units,
+                                         uint8_t *out, size_t cap_bytes);
+
 /* Convenience loop for exhaustive tests: validates n_strings strings of len bytes
  * each, stored back to back in buf; per-string status and count go to the arrays
  * (either may be NULL).  Returns the number of valid strings. */

@@ -148,6 +148,54 @@ def test_utf16be_against_python_codecs():
             assert (got.status, got.count) == want, strs[i]
 
 
+ALPHA32 = np.array([0x0, 0x7F, 0x80, 0x7FF, 0x800, 0xD7FF, 0xD800, 0xDBFF, 0xDC00, 0xDFFF, 0xE000, 0xFFFF,
+                    0x10000, 0x10FFFF, 0x110000, 0xFFFFFFFF], dtype=np.uint32)
+
+
+def test_utf32le_against_python_codecs():
+    """UTF-32LE (section 2: one 32-bit integer per character): every scalar value against
+    CPython's utf-32-le codec both ways; every string of length <= 3 over 16 edge units
+    (both surrogate edges, U+10FFFF, the first value past it, 0xFFFFFFFF) against its
+    strict decoder's verdict and offset; UTF-8 -> UTF-32 errors at validate_utf8's
+    offsets with the valid prefix's characters written."""
+    s = all_scalar_values_str()
+    u8 = np.frombuffer(s.encode("utf-8"), dtype=np.uint8)
+    u32 = np.frombuffer(s.encode("utf-32-le"), dtype="<u4").astype(np.uint32)
+    assert u32.size == 1_112_064
+    r, out = O.utf8_to_utf32le(u8)
+    assert r == O.Result(O.OK, u32.size, u32.size) and np.array_equal(out[: r.written], u32)
+    r, out = O.utf32le_to_utf8(u32)
+    assert r == O.Result(O.OK, u8.size, u8.size) and np.array_equal(out[: r.written], u8)
+    assert O.validate_utf32le(u32) == O.Result(O.OK, u32.size, u32.size)
+    for L in range(1, 4):
+        strs = _all_strings(ALPHA32, L).astype(np.uint32)
+        for i in range(strs.shape[0]):
+            b = strs[i].astype("<u4").tobytes()
+            try:
+                b.decode("utf-32-le")
+                want = (O.OK, L)
+            except UnicodeDecodeError as e:
+                want = (O.E_SURROGATE if 0xD800 <= strs[i][e.start // 4] <= 0xDFFF else O.E_TOO_LARGE, e.start // 4)
+            got = O.validate_utf32le(strs[i])
+            assert (got.status, got.count) == want, strs[i]
+            r, out = O.utf32le_to_utf8(strs[i])
+            prefix = b[: 4 * want[1]].decode("utf-32-le").encode("utf-8")
+            if want[0] == O.OK:
+                assert r == O.Result(O.OK, len(prefix), len(prefix))
+            else:
+                assert (r.status, r.count) == want
+            assert r.written == len(prefix) and out[: r.written].tobytes() == prefix
+    rng = synth.rng_for(98, 32)
+    for _ in range(300):
+        inj = synth.inject_utf8("mixed4", 400, 1e-2, rng)
+        v = O.validate_utf8(inj.data)
+        r, out = O.utf8_to_utf32le(inj.data)
+        prefix = inj.data[: v.count].tobytes().decode("utf-8")
+        assert r.status == v.status and r.count == (v.count if v.status else len(prefix))
+        assert r.written == len(prefix)
+        assert np.array_equal(out[: r.written], np.array([ord(ch) for ch in prefix], np.uint32))
+
+
 def test_encoded_surrogates_rejected():
     """Rule 6: the 2,048 surrogate code points in 3-byte form (built by Python's
     surrogatepass handler) are each a SURROGATE error at offset 0."""
