@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--stream-chunks", default="1,16",
                     help="chunk sizes (MiB) of the stream runs over one mixed buffer (empty = skip)")
     ap.add_argument("--stream-mib", type=int, default=256, help="stream length (MiB)")
+    ap.add_argument("--utf32-mib", type=int, default=256, help="UTF-32 runs: input MiB per direction (0 = skip)")
     ap.add_argument("--no-tune-cache", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain 256 MiB device copies (counter calibration for rocprofv3 --pmc)")
@@ -235,6 +236,7 @@ def main():
     small = run_small(ctx, log, args.small_calls) if args.small_calls else None
     runs = run_structured(ctx, log, args.run_mib) if args.run_mib else None
     streamed = run_stream(ctx, log, args.stream_mib, args.stream_chunks) if args.stream_chunks else None
+    utf32 = run_utf32(ctx, log, args.utf32_mib) if args.utf32_mib else None
     batch = run_batch(args, ctx, log) if args.batch_strings else None
     serving = run_serving(args, log) if args.serve_rates else None
 
@@ -267,6 +269,7 @@ def main():
         "small_64KiB": small,
         "run_structured": runs,
         "stream": streamed,
+        "utf32": utf32,
         "batched": batch,
         "serving": serving,
     }
@@ -358,6 +361,55 @@ def run_stream(ctx, log, mib, chunk_list, reps=3):
                             "matches_one_call": ok})
         log("stream chunks of %d MiB + 1 B: %d calls, %.3f ms (%.1f GB/s, %.1f us per call), output %s" %
             (c, calls, t * 1e3, n / t / 1e9, t / calls * 1e6, "matches" if ok else "MISMATCH"))
+    return out
+
+
+def run_utf32(ctx, log, mib, reps=5):
+    """UTF-32LE: mixed-profile UTF-8 -> UTF-32 and CJK / emoji UTF-32 -> UTF-8 on
+    buffers of `mib` MiB of input, device time per call (HIP events around repeated
+    async calls) and HBM bytes (input + output) per second."""
+    import numpy as np
+    import torch
+
+    import paper_2212_05098_amd as utfx
+    from paper_2212_05098_amd import synth
+
+    n = mib << 20
+    res = utfx.result_tensor(1)
+    out = {"mib": mib, "cases": []}
+
+    def timed(f, src, dst):
+        f(src, dst, res)
+        torch.cuda.synchronize()
+        r = utfx.results_from_tensor(res)[0]
+        assert r.status == utfx.OK
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f(src, dst, res)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r.written
+
+    data = synth.config_buffer("mixed4", synth.DIR_8TO16, n, config=2)
+    src = torch.from_numpy(data).cuda()
+    dst = torch.empty(n, dtype=torch.int32, device="cuda")
+    ms, w = timed(ctx.utf8_to_utf32le_async, src, dst)
+    cases = [("mixed4", "utf8->utf32le", n, 4 * w, ms)]
+    del src, dst
+    for prof in ("cjk", "emoji"):
+        units = synth.utf32_buffer(prof, n // 4, synth.rng_for(0, 9, synth.PROFILE_IDS[prof]))
+        src = torch.from_numpy(units.view(np.int32)).cuda()
+        dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+        ms, w = timed(ctx.utf32le_to_utf8_async, src, dst)
+        cases.append((prof, "utf32le->utf8", n, w, ms))
+        del src, dst
+    torch.cuda.empty_cache()
+    for prof, d, nin, nout, ms in cases:
+        case = {"profile": prof, "dir": d, "in_bytes": nin, "out_bytes": int(nout), "ms_avg": round(ms, 4),
+                "in_GBps": round(nin / (ms * 1e6), 1), "hbm_frac": round((nin + nout) / (ms * 1e6) / HBM_PEAK_GBS, 4)}
+        out["cases"].append(case)
+        log("utf32 %-6s %-14s %8.3f ms  in %7.1f GB/s  hbm %.3f" % (prof, d, ms, case["in_GBps"], case["hbm_frac"]))
     return out
 
 

@@ -177,6 +177,27 @@ utfx_status utfx_utf8_to_utf16be_async(utfx_ctx *ctx, const uint8_t *in, size_t 
 utfx_status utfx_utf16be_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
                                        uint8_t *out, size_t cap_bytes, utfx_result *d_result);
 
+/* ---- UTF-32LE ------------------------------------------------------------------
+ * One 32-bit unit per character (section 2).  A unit in U+D800..DFFF is a
+ * UTFX_E_SURROGATE error and one above U+10FFFF a UTFX_E_TOO_LARGE error, at its own
+ * offset; UTF-8 input is validated exactly as by utfx_validate_utf8.  UTF-32 pointers
+ * must be 4-byte aligned (else UTFX_E_INVALID_ARG); lengths are in 32-bit units.
+ * Results and errors otherwise follow the UTF-16 calls: count is the offset of the
+ * first invalid unit on an error, written the output units of the valid prefix.
+ * Room for n_bytes units (UTF-8 -> UTF-32) or 4 n_units bytes (UTF-32 -> UTF-8)
+ * always suffices. */
+utfx_result utfx_validate_utf32le(utfx_ctx *ctx, const uint32_t *in, size_t n_units);
+utfx_result utfx_utf8_to_utf32le(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                 uint32_t *out, size_t cap_units);
+utfx_result utfx_utf32le_to_utf8(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
+                                 uint8_t *out, size_t cap_bytes);
+utfx_status utfx_validate_utf32le_async(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
+                                        utfx_result *d_result);
+utfx_status utfx_utf8_to_utf32le_async(utfx_ctx *ctx, const uint8_t *in, size_t n_bytes,
+                                       uint32_t *out, size_t cap_units, utfx_result *d_result);
+utfx_status utfx_utf32le_to_utf8_async(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
+                                       uint8_t *out, size_t cap_bytes, utfx_result *d_result);
+
 /* ---- streams: input in chunks cut at any unit offset -------------------------
  * A stream transcodes input that arrives in pieces.  Its result is the result of the
  * single-buffer call on the concatenation of all its chunks: the same output, split

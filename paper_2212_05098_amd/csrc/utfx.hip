@@ -17,6 +17,7 @@
 #include "utfx_transcode.hpp"
 #include "utfx_batch.hpp"
 #include "utfx_stream.hpp"
+#include "utfx_utf32.hpp"
 
 using namespace utfx_dev;
 
@@ -142,14 +143,15 @@ bool valid_tile(uint32_t t) { return t == 4096 || t == 8192; }
 
 // Common launch geometry: base rounded down to 16 bytes, misalignment in units,
 // tiles covering logical positions [-mis, n + extra).
-utfx_status prep(utfx_ctx* c, int op, const void* in, uint64_t n, uint32_t unit, uint64_t extra,
-                 void* result, Launch& L, uint32_t& wg) {
+// Launch description for a kernel of wg_ threads and seg_tiles tiles per segment.
+utfx_status prep_cfg(utfx_ctx* c, uint32_t wg_, uint32_t seg_tiles, const void* in, uint64_t n, uint32_t unit,
+                     uint64_t extra, void* result, Launch& L, uint32_t& wg) {
   const uintptr_t a = reinterpret_cast<uintptr_t>(in);
   L.base = reinterpret_cast<const uint8_t*>(a & ~static_cast<uintptr_t>(15));
   L.mis = (a & 15) / unit;
   L.n = n;
-  wg = c->tile_bytes[op] / 16;
-  L.seg = c->seg_tiles[op];
+  wg = wg_;
+  L.seg = seg_tiles;
   L.wg = wg;
   L.be = 0;
   const uint64_t per_seg = static_cast<uint64_t>(wg) * (16 / unit) * L.seg;
@@ -164,6 +166,11 @@ utfx_status prep(utfx_ctx* c, int op, const void* in, uint64_t n, uint32_t unit,
   L.out = nullptr;
   L.cap = 0;
   return UTFX_OK;
+}
+
+utfx_status prep(utfx_ctx* c, int op, const void* in, uint64_t n, uint32_t unit, uint64_t extra,
+                 void* result, Launch& L, uint32_t& wg) {
+  return prep_cfg(c, c->tile_bytes[op] / 16, c->seg_tiles[op], in, n, unit, extra, result, L, wg);
 }
 
 template <template <int> class K>
@@ -250,7 +257,10 @@ utfx_status store_result_async(utfx_ctx* c, void* d_result, int32_t st, uint64_t
   return UTFX_OK;
 }
 
-enum Kind { LEN8, LEN16, VAL8, VAL16, U8U16, U16U8 };
+enum Kind { LEN8, LEN16, VAL8, VAL16, U8U16, U16U8, VAL32, U8U32, U32U8 };
+
+// UTF-32 launches use one fixed configuration each: (threads, tiles per segment).
+constexpr uint32_t kU8U32Wg = 256, kU8U32Seg = 2, kU32U8Wg = 256, kU32U8Seg = 4, kVal32Wg = 256, kVal32Seg = 8;
 
 hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
   switch (kind) {
@@ -266,6 +276,15 @@ hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
       return hipGetLastError();
     case U8U16:
       return launch_fin_u8u16(wg, 1, L, s);
+    case VAL32:
+      hipLaunchKernelGGL(k_fin_validate32, dim3(1), dim3(64), 0, s, L);
+      return hipGetLastError();
+    case U8U32:
+      hipLaunchKernelGGL(k_fin_u8u32<kU8U32Wg>, dim3(1), dim3(kU8U32Wg), 0, s, L);
+      return hipGetLastError();
+    case U32U8:
+      hipLaunchKernelGGL(k_fin_u32u8<kU32U8Wg>, dim3(1), dim3(kU32U8Wg), 0, s, L);
+      return hipGetLastError();
     default:
       return launch_fin_u16u8(wg, 1, L, s);
   }
@@ -278,7 +297,9 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
   c->err[0] = 0;
   const bool in16 = (kind == LEN16 || kind == VAL16 || kind == U16U8);
   const bool out16 = (kind == U8U16);
-  const bool has_out = (kind == U8U16 || kind == U16U8);
+  const bool in32 = (kind == VAL32 || kind == U32U8);
+  const bool out32 = (kind == U8U32);
+  const bool has_out = (kind == U8U16 || kind == U16U8 || kind == U8U32 || kind == U32U8);
   if (!d_result) {
     set_msg(c, "null result pointer");
     return UTFX_E_INVALID_ARG;
@@ -303,12 +324,23 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
     set_msg(c, "UTF-16 output not 2-byte aligned");
     return UTFX_E_INVALID_ARG;
   }
+  if (in32 && (reinterpret_cast<uintptr_t>(in) & 3)) {
+    set_msg(c, "UTF-32 input not 4-byte aligned");
+    return UTFX_E_INVALID_ARG;
+  }
+  if (out32 && (reinterpret_cast<uintptr_t>(out) & 3)) {
+    set_msg(c, "UTF-32 output not 4-byte aligned");
+    return UTFX_E_INVALID_ARG;
+  }
   if (n == 0) return store_result_async(c, d_result, UTFX_OK, 0, 0);
 
   int op = 0;
-  uint32_t unit = in16 ? 2 : 1;
+  uint32_t unit = in32 ? 4 : (in16 ? 2 : 1);
   uint64_t extra = 0;
   switch (kind) {
+    case VAL32:
+    case U8U32:
+    case U32U8: break;
     case LEN8: op = UTFX_OP_LENGTH_UTF8; break;
     case LEN16: op = UTFX_OP_LENGTH_UTF16; break;
     case VAL8: op = UTFX_OP_VALIDATE_UTF8; extra = 1; break;
@@ -318,7 +350,11 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
   }
   Launch L;
   uint32_t wg = 0;
-  utfx_status s = prep(c, op, in, n, unit, extra, d_result, L, wg);
+  utfx_status s;
+  if (kind == VAL32) s = prep_cfg(c, kVal32Wg, kVal32Seg, in, n, unit, 0, d_result, L, wg);
+  else if (kind == U8U32) s = prep_cfg(c, kU8U32Wg, kU8U32Seg, in, n, unit, 1, d_result, L, wg);
+  else if (kind == U32U8) s = prep_cfg(c, kU32U8Wg, kU32U8Seg, in, n, unit, 0, d_result, L, wg);
+  else s = prep(c, op, in, n, unit, extra, d_result, L, wg);
   if (s != UTFX_OK) return s;
   L.out = out;
   L.cap = cap;
@@ -335,6 +371,18 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
     case VAL16: e = launch_val16(wg, L.ntiles, L, c->stream); break;
     case U8U16: e = launch_u8u16(wg, L.ntiles, L, c->stream); break;
     case U16U8: e = launch_u16u8(wg, L.ntiles, L, c->stream); break;
+    case VAL32:
+      hipLaunchKernelGGL(k_validate32<kVal32Wg>, dim3((uint32_t)L.ntiles), dim3(kVal32Wg), 0, c->stream, L);
+      e = hipGetLastError();
+      break;
+    case U8U32:
+      hipLaunchKernelGGL((k_u8_to_u32<kU8U32Wg, kU8U32Seg>), dim3((uint32_t)L.ntiles), dim3(kU8U32Wg), 0, c->stream, L);
+      e = hipGetLastError();
+      break;
+    case U32U8:
+      hipLaunchKernelGGL((k_u32_to_u8<kU32U8Wg, kU32U8Seg>), dim3((uint32_t)L.ntiles), dim3(kU32U8Wg), 0, c->stream, L);
+      e = hipGetLastError();
+      break;
   }
   if (e == hipSuccess) e = launch_fin(kind, wg, L, c->stream);
   if (e != hipSuccess) {
@@ -518,6 +566,27 @@ utfx_result stream_transcode(utfx_ctx* c, utfx_stream* st, const void* in, uint6
 }  // namespace
 
 extern "C" {
+
+utfx_result utfx_validate_utf32le(utfx_ctx* c, const uint32_t* in, size_t n) {
+  return run_sync(c, VAL32, in, n, nullptr, 0);
+}
+utfx_result utfx_utf8_to_utf32le(utfx_ctx* c, const uint8_t* in, size_t n, uint32_t* out, size_t cap) {
+  return run_sync(c, U8U32, in, n, out, cap);
+}
+utfx_result utfx_utf32le_to_utf8(utfx_ctx* c, const uint32_t* in, size_t n, uint8_t* out, size_t cap) {
+  return run_sync(c, U32U8, in, n, out, cap);
+}
+utfx_status utfx_validate_utf32le_async(utfx_ctx* c, const uint32_t* in, size_t n, utfx_result* d_result) {
+  return run(c, VAL32, in, n, nullptr, 0, d_result);
+}
+utfx_status utfx_utf8_to_utf32le_async(utfx_ctx* c, const uint8_t* in, size_t n, uint32_t* out, size_t cap,
+                                       utfx_result* d_result) {
+  return run(c, U8U32, in, n, out, cap, d_result);
+}
+utfx_status utfx_utf32le_to_utf8_async(utfx_ctx* c, const uint32_t* in, size_t n, uint8_t* out, size_t cap,
+                                       utfx_result* d_result) {
+  return run(c, U32U8, in, n, out, cap, d_result);
+}
 
 utfx_status utfx_stream_init(utfx_stream* st, int format) {
   if (!st || format < UTFX_STREAM_UTF8_TO_UTF16LE || format > UTFX_STREAM_UTF16BE_TO_UTF8)

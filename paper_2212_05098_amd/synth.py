@@ -465,3 +465,21 @@ def stream_cuts(n_units: int, rng: np.random.Generator, max_chunk: int, min_chun
     while cuts[-1] < n_units:
         cuts.append(min(n_units, cuts[-1] + int(rng.integers(min_chunk, max_chunk + 1))))
     return cuts
+
+
+def utf32_buffer(profile: str, n_units: int, rng: np.random.Generator) -> np.ndarray:
+    """n_units i.i.d. code points of the profile as a UTF-32 buffer (uint32)."""
+    return draw_codepoints(profile, n_units, rng)
+
+
+def inject_utf32(units: np.ndarray, rate: float, rng: np.random.Generator) -> Tuple[np.ndarray, List[int]]:
+    """A copy of a UTF-32 buffer with units replaced at the given rate (at least one) by
+    values that are not characters: surrogates, the first value past U+10FFFF, random
+    larger values.  Returns (buffer, sorted positions)."""
+    out = np.array(units, dtype=np.uint32, copy=True)
+    k = max(1, int(rng.binomial(out.size, rate)))
+    pos = np.unique(rng.integers(0, out.size, size=k))
+    bad = np.concatenate([rng.integers(0xD800, 0xE000, size=pos.size), np.full(pos.size, 0x110000),
+                          rng.integers(0x110000, 1 << 32, size=pos.size)]).astype(np.uint32)
+    out[pos] = rng.choice(bad, size=pos.size)
+    return out, pos.tolist()

@@ -134,3 +134,53 @@ def check_u16be_to_u8(ctx, words_be, cap=None, in_shift=0, out_shift=0, guard=64
     assert tuple(ctx.validate_utf16be(src)) == tuple(O.validate_utf16be(words_be))
     assert tuple(ctx.utf8_length_from_utf16be(src)) == tuple(O.utf8_length_from_utf16be(words_be))
     return r
+
+
+def dev_u32(u, pad_front_units=0, pad_back=0):
+    """Upload UTF-32 units as an int32 tensor view (4-byte aligned, shifted by
+    pad_front_units units)."""
+    import torch
+
+    u = np.ascontiguousarray(u, dtype=np.uint32)
+    back = torch.zeros(pad_front_units + u.size + pad_back + 4, dtype=torch.int32, device="cuda")
+    if u.size:
+        back[pad_front_units:pad_front_units + u.size] = torch.from_numpy(u.view(np.int32).copy()).cuda()
+    return back[pad_front_units:pad_front_units + u.size], back
+
+
+def check_u8_to_u32(ctx, data, cap=None, in_shift=0, out_shift=0, guard=32):
+    import torch
+
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    cap = data.size if cap is None else cap
+    src, _ = dev_u8(data, pad_front=in_shift)
+    fill = 0x5A5A5A5A
+    out_back = torch.full((out_shift + cap + guard,), fill, dtype=torch.int32, device="cuda")
+    dst = out_back[out_shift:out_shift + cap]
+    r = ctx.utf8_to_utf32le(src, dst)
+    want, ref = O.utf8_to_utf32le(data, cap=cap)
+    assert tuple(r) == tuple(want), (r, want)
+    got = out_back.cpu().numpy().view(np.uint32)
+    w = min(r.written, cap)
+    assert np.array_equal(got[out_shift:out_shift + w], ref[:w])
+    assert np.all(got[:out_shift] == fill) and np.all(got[out_shift + cap:] == fill)
+    return r
+
+
+def check_u32_to_u8(ctx, units, cap=None, in_shift=0, out_shift=0, guard=64):
+    import torch
+
+    units = np.ascontiguousarray(units, dtype=np.uint32)
+    cap = 4 * units.size if cap is None else cap
+    src, _ = dev_u32(units, pad_front_units=in_shift)
+    out_back = torch.full((out_shift + cap + guard,), 0xA5, dtype=torch.uint8, device="cuda")
+    dst = out_back[out_shift:out_shift + cap]
+    r = ctx.utf32le_to_utf8(src, dst)
+    want, ref = O.utf32le_to_utf8(units, cap=cap)
+    assert tuple(r) == tuple(want), (r, want)
+    got = host_u8(out_back)
+    w = min(r.written, cap)
+    assert np.array_equal(got[out_shift:out_shift + w], ref[:w])
+    assert np.all(got[:out_shift] == 0xA5) and np.all(got[out_shift + cap:] == 0xA5)
+    assert tuple(ctx.validate_utf32le(src)) == tuple(O.validate_utf32le(units))
+    return r

@@ -1,0 +1,184 @@
+"""UTF-32LE through the C ABI against the oracle (pinned to CPython's utf-32-le codec):
+UTF-8 -> UTF-32 (validation of section 6.4, code points of Figure 1(a)) and UTF-32 ->
+UTF-8 (section 2's range and surrogate rules), element by element, at ragged sizes
+that span many segments, with injected errors, every UTF-8 error kind at every chunk
+offset, the class-edge alphabets, misaligned pointers, small outputs, the async forms
+and one 256 MiB buffer per direction."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2212_05098_amd as utfx
+from paper_2212_05098_amd import synth
+from gpu_helpers import check_u32_to_u8, check_u8_to_u32, dev_u8, dev_u32, note
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (1, 2, 3, 5, 15, 16, 17, 63, 64, 65, 1000, 4095, 4096, 4097, 8191, 8193, 16_385, 40_000, 300_007)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    c = utfx.Context()
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("prof", synth.SCRIPT_PROFILES + ("mixed4",))
+def test_profiles_ragged_sizes(ctx, prof):
+    rng = synth.rng_for(80, synth.PROFILE_IDS[prof])
+    for n in SIZES:
+        note("utf32 %s n=%d" % (prof, n))
+        data = synth.utf8_buffer(prof, n, rng)
+        check_u8_to_u32(ctx, data)
+        check_u32_to_u8(ctx, synth.utf32_buffer(prof, n, rng))
+
+
+def test_round_trip(ctx):
+    import torch
+
+    rng = synth.rng_for(81)
+    data = synth.utf8_buffer("mixed4", 2_000_003, rng)
+    src, _ = dev_u8(data)
+    mid = torch.empty(data.size, dtype=torch.int32, device="cuda")
+    r = ctx.utf8_to_utf32le(src, mid)
+    assert r.status == utfx.OK
+    back = torch.empty(4 * r.written, dtype=torch.uint8, device="cuda")
+    r2 = ctx.utf32le_to_utf8(mid[: r.written], back)
+    assert r2 == (utfx.OK, data.size, data.size)
+    assert np.array_equal(back[: data.size].cpu().numpy(), data)
+
+
+@pytest.mark.parametrize("prof", ["cjk", "mixed4", "emoji"])
+@pytest.mark.parametrize("rate", [1e-4, 3e-2])
+def test_injected_errors(ctx, prof, rate):
+    rng = synth.rng_for(82, synth.PROFILE_IDS[prof], int(rate * 1e6))
+    for trial in range(3):
+        inj = synth.inject_utf8(prof, 200_000, rate, rng)
+        note("utf32 inject utf8 %s rate=%g trial=%d" % (prof, rate, trial))
+        r = check_u8_to_u32(ctx, inj.data)
+        assert r.status != utfx.OK and r.count == inj.positions[0]
+        units, pos = synth.inject_utf32(synth.utf32_buffer(prof, 100_000, rng), rate, rng)
+        note("utf32 inject utf32 %s rate=%g trial=%d" % (prof, rate, trial))
+        r = check_u32_to_u8(ctx, units)
+        assert r.status in (utfx.E_SURROGATE, utfx.E_TOO_LARGE) and r.count == pos[0]
+
+
+@pytest.mark.parametrize("kind", synth.UTF8_KINDS)
+def test_each_utf8_error_kind_at_every_chunk_offset(ctx, kind):
+    rng = synth.rng_for(83, synth.UTF8_KINDS.index(kind))
+    base = synth.utf8_buffer("mixed4", 4000, rng).tobytes()
+    for off in range(0, 81):
+        item = synth.utf8_error_item(kind, rng)
+        prefix = base[:off].decode("utf-8", errors="ignore").encode("utf-8")
+        prefix += b"a" * (off - len(prefix))
+        data = np.frombuffer(prefix + item + b"z" + base[off:], dtype=np.uint8)
+        note("utf32 kind %s off=%d" % (kind, off))
+        assert check_u8_to_u32(ctx, data).count == off
+
+
+def test_class_alphabets(ctx):
+    from test_oracle_pins import ALPHA8, ALPHA32, _all_strings
+
+    for L in (1, 2, 3):
+        strs = _all_strings(ALPHA32, L).astype(np.uint32)
+        note("utf32 alphabet L=%d (%d strings)" % (L, strs.shape[0]))
+        for s in strs:
+            check_u32_to_u8(ctx, s, guard=8)
+    for L in (1, 2):
+        strs = _all_strings(ALPHA8, L).astype(np.uint8)
+        note("utf8->utf32 alphabet L=%d" % L)
+        for s in strs:
+            check_u8_to_u32(ctx, s, guard=8)
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2, 3, 5, 7, 13])
+def test_misaligned_pointers(ctx, shift):
+    rng = synth.rng_for(84, shift)
+    data = synth.utf8_buffer("mixed4", 20_011, rng)
+    units = synth.utf32_buffer("emoji", 10_007, rng)
+    note("utf32 misaligned shift=%d" % shift)
+    check_u8_to_u32(ctx, data, in_shift=shift, out_shift=shift % 4)
+    check_u32_to_u8(ctx, units, in_shift=shift % 4, out_shift=shift)
+
+
+def test_output_capacity(ctx):
+    rng = synth.rng_for(85)
+    data = synth.utf8_buffer("mixed4", 50_000, rng)
+    need = O.utf8_to_utf32le(data)[0].count
+    for cap in (0, 1, 3, 4, 5, need // 2, need - 1, need):
+        note("utf32 cap u8 %d" % cap)
+        r = check_u8_to_u32(ctx, data, cap=cap, out_shift=1)
+        assert r.status == (utfx.OK if cap >= need else utfx.E_OUTPUT_TOO_SMALL)
+    units = synth.utf32_buffer("cjk", 20_000, rng)
+    need = O.utf32le_to_utf8(units)[0].count
+    for cap in (0, 1, 15, 16, 17, need - 1, need):
+        note("utf32 cap u32 %d" % cap)
+        r = check_u32_to_u8(ctx, units, cap=cap, out_shift=3)
+        assert r.status == (utfx.OK if cap >= need else utfx.E_OUTPUT_TOO_SMALL)
+    inj = synth.inject_utf8("cjk", 50_000, 1e-4, rng)
+    check_u8_to_u32(ctx, inj.data, cap=10)
+
+
+def test_empty_and_arguments(ctx):
+    import torch
+
+    e8 = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    e32 = torch.zeros(0, dtype=torch.int32, device="cuda")
+    o32 = torch.zeros(4, dtype=torch.int32, device="cuda")
+    o8 = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    assert ctx.utf8_to_utf32le(e8, o32) == (utfx.OK, 0, 0)
+    assert ctx.utf32le_to_utf8(e32, o8) == (utfx.OK, 0, 0)
+    assert ctx.validate_utf32le(e32) == (utfx.OK, 0, 0)
+    b = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    for off in (1, 2, 3):
+        assert ctx.raw("utfx_validate_utf32le", b.data_ptr() + off, 4).status == utfx.E_INVALID_ARG
+        assert ctx.raw("utfx_utf32le_to_utf8", b.data_ptr() + off, 4, b.data_ptr(), 16).status == utfx.E_INVALID_ARG
+        assert ctx.raw("utfx_utf8_to_utf32le", b.data_ptr(), 4, b.data_ptr() + off, 4).status == utfx.E_INVALID_ARG
+    assert ctx.raw("utfx_utf32le_to_utf8", None, 4, b.data_ptr(), 16).status == utfx.E_INVALID_ARG
+
+
+def test_async_forms(ctx):
+    import torch
+
+    rng = synth.rng_for(86)
+    data = synth.utf8_buffer("mixed4", 70_001, rng)
+    units, pos = synth.inject_utf32(synth.utf32_buffer("emoji", 30_001, rng), 1e-4, rng)
+    s8, _ = dev_u8(data)
+    s32, _ = dev_u32(units)
+    o32 = torch.empty(data.size, dtype=torch.int32, device="cuda")
+    o8 = torch.empty(4 * units.size, dtype=torch.uint8, device="cuda")
+    res = utfx.result_tensor(3)
+    assert ctx.utf8_to_utf32le_async(s8, o32, res[0:24]) == utfx.OK
+    assert ctx.utf32le_to_utf8_async(s32, o8, res[24:48]) == utfx.OK
+    assert ctx.validate_utf32le_async(s32, res[48:72]) == utfx.OK
+    torch.cuda.synchronize()
+    got = utfx.results_from_tensor(res)
+    w32, r32 = O.utf8_to_utf32le(data)
+    w8, r8 = O.utf32le_to_utf8(units)
+    assert tuple(got[0]) == tuple(w32)
+    assert np.array_equal(o32.cpu().numpy().view(np.uint32)[: w32.written], r32[: w32.written])
+    assert tuple(got[1]) == tuple(w8) and w8.count == pos[0]
+    assert np.array_equal(o8.cpu().numpy()[: w8.written], r8[: w8.written])
+    assert tuple(got[2]) == tuple(O.validate_utf32le(units))
+
+
+def test_full_size_each_direction(ctx):
+    """256 MiB per direction: mixed UTF-8 to UTF-32, and 64 Mi CJK units to UTF-8."""
+    import torch
+
+    full = 256 << 20
+    data = synth.config_buffer("mixed4", synth.DIR_8TO16, full, config=2)
+    note("utf32 full size utf8->utf32")
+    r = check_u8_to_u32(ctx, data)
+    assert r.status == utfx.OK
+    torch.cuda.empty_cache()
+    rng = synth.rng_for(87)
+    units = synth.utf32_buffer("cjk", full // 4, rng)
+    note("utf32 full size utf32->utf8")
+    r = check_u32_to_u8(ctx, units)
+    assert r.status == utfx.OK
+    torch.cuda.empty_cache()
