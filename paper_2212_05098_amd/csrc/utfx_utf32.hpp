@@ -43,10 +43,14 @@ __device__ __forceinline__ uint32_t spill8_chars(uint32_t xp) {
   return ((xp >> 24) >= 0xC0u) + (((xp >> 16) & 0xFFu) >= 0xE0u) + (((xp >> 8) & 0xFFu) >= 0xF0u);
 }
 
-// One 16-byte chunk: validate it (process8 without decoding) and scatter the code
-// point of every character that ends in it into the stage from slot PAD + off - spill
-// on.  Returns the slot after the chunk's last code point (LIM for a chunk whose slots
-// would leave the stage, which then writes to the dump slot).
+// One 16-byte chunk: validate and decode it with process8 (the UTF-16 words of section
+// 6.2 at each emit position), then scatter the code point of every character that ends
+// in it into the stage from slot PAD + off - spill on.  A BMP character's word is its
+// code point; a 4-byte character is emitted once, at its low surrogate, as 0x10000 +
+// (high - 0xD800) * 1024 + (low - 0xDC00), the high surrogate being the word one
+// position back (for position 0, in the previous chunk, its code point comes straight
+// from the four bytes, Figure 1(a)).  Returns the slot after the chunk's last code point
+// (LIM for a chunk whose slots would leave the stage, which then writes to the dump slot).
 template <uint32_t PAD, uint32_t LIM, uint32_t DUMP>
 __device__ __forceinline__ uint32_t chunk_u8_to_u32(const uint32_t x[4], uint32_t xp, bool full, uint64_t q0,
                                                     uint64_t lo, uint64_t hi, uint32_t off, uint32_t* stage,
@@ -61,34 +65,28 @@ __device__ __forceinline__ uint32_t chunk_u8_to_u32(const uint32_t x[4], uint32_
     range_masks(q0, lo, hi + 1, inD);
   }
   const int cls = classify8(ch);
-  process8_any<false>(cls, full, ch, inE, inD, E, cnt, det, W);
+  process8_any<true>(cls, full, ch, inE, inD, E, cnt, det, W);
   const uint32_t idx = PAD + off - spill8_chars(xp);
   *first = idx;
   const bool fits = idx + 16 <= LIM;
   uint32_t* pw = stage + (fits ? idx : DUMP);
   uint32_t* const dump = stage + DUMP;
-  const uint32_t win[5] = {xp, x[0], x[1], x[2], x[3]};
+  // position 0 as the end of a 4-byte character whose first three bytes are in xp
+  const uint32_t cp0 = ((xp >> 8) & 0x07u) << 18 | ((xp >> 16) & 0x3Fu) << 12 | ((xp >> 24) & 0x3Fu) << 6 |
+                       (x[0] & 0x3Fu);
+  uint32_t prev = 0;  // the word one position back
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
-    // bytes p, p-1, p-2, p-3 of the chunk (negative positions from xp)
-    const uint32_t b0 = (win[(p + 4) >> 2] >> (8 * ((p + 4) & 3))) & 0xFFu;
-    const uint32_t b1 = (win[(p + 3) >> 2] >> (8 * ((p + 3) & 3))) & 0xFFu;
-    const uint32_t b2 = (win[(p + 2) >> 2] >> (8 * ((p + 2) & 3))) & 0xFFu;
-    const uint32_t b3 = (win[(p + 1) >> 2] >> (8 * ((p + 1) & 3))) & 0xFFu;
-    const bool c0 = (b0 & 0xC0u) == 0x80u, c1 = (b1 & 0xC0u) == 0x80u, c2 = (b2 & 0xC0u) == 0x80u;
-    const bool end1 = b0 < 0x80u;
-    const bool end2 = c0 && b1 >= 0xC0u && b1 < 0xE0u;
-    const bool end3 = c0 && c1 && b2 >= 0xE0u && b2 < 0xF0u;
-    const bool end4 = c0 && c1 && c2 && b3 >= 0xF0u;
-    const uint32_t t0 = b0 & 0x3Fu, t1 = b1 & 0x3Fu, t2 = b2 & 0x3Fu;
-    uint32_t cp = ((b3 & 0x07u) << 18) | (t2 << 12) | (t1 << 6) | t0;
-    cp = end3 ? (((b2 & 0x0Fu) << 12) | (t1 << 6) | t0) : cp;
-    cp = end2 ? (((b1 & 0x1Fu) << 6) | t0) : cp;
-    cp = end1 ? b0 : cp;
-    uint32_t bit = (end1 || end2 || end3 || end4) ? 1u : 0u;
-    if (!full) bit &= (inE[p >> 2] >> (8 * (p & 3) + 7)) & 1u;
+    const uint32_t pair = W[p >> 1];
+    const uint32_t w = (p & 1) ? (pair >> 16) : (pair & 0xFFFFu);
+    const uint32_t e = (E[p >> 2] >> (8 * (p & 3) + 7)) & 1u;
+    const bool hi_half = (w & 0xFC00u) == 0xD800u, lo_half = (w & 0xFC00u) == 0xDC00u;
+    const uint32_t cp4 = (p == 0) ? cp0 : 0x10000u + ((prev - 0xD800u) << 10) + (w - 0xDC00u);
+    const uint32_t cp = lo_half ? cp4 : w;
+    const uint32_t bit = (e && !hi_half) ? 1u : 0u;
     *(bit ? pw : dump) = cp;
     pw += bit;
+    prev = w;
   }
   *det_out = det;
   return fits ? (uint32_t)(pw - stage) : LIM;
