@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
             ("utfx_ref_validate_utf32le", [p8, sz]),
             ("utfx_ref_utf8_to_utf32le", [p8, sz, p8, sz]),
             ("utfx_ref_utf32le_to_utf8", [p8, sz, p8, sz]),
+            ("utfx_ref_utf16le_to_utf32le", [p8, sz, p8, sz]),
+            ("utfx_ref_utf32le_to_utf16le", [p8, sz, p8, sz]),
         ]:
             fn = getattr(L, name)
             fn.argtypes = args
@@ -233,6 +235,24 @@ def utf32le_to_utf8(data, cap: Optional[int] = None):
     cap = 4 * a.size if cap is None else int(cap)
     out = np.zeros(cap, dtype=np.uint8)
     r = _res(lib().utfx_ref_utf32le_to_utf8(_ptr(a), a.size, _ptr(out), cap))
+    return r, out
+
+
+def utf16le_to_utf32le(data, cap: Optional[int] = None):
+    """Returns (Result, out) where out is a uint32 array of length cap (default n)."""
+    a = _u16(data)
+    cap = a.size if cap is None else int(cap)
+    out = np.zeros(cap, dtype=np.uint32)
+    r = _res(lib().utfx_ref_utf16le_to_utf32le(_ptr(a), a.size, _ptr(out), cap))
+    return r, out
+
+
+def utf32le_to_utf16le(data, cap: Optional[int] = None):
+    """Returns (Result, out) where out is a uint16 array of length cap (default 2n)."""
+    a = _u32(data)
+    cap = 2 * a.size if cap is None else int(cap)
+    out = np.zeros(cap, dtype=np.uint16)
+    r = _res(lib().utfx_ref_utf32le_to_utf16le(_ptr(a), a.size, _ptr(out), cap))
     return r, out
 
 

@@ -290,6 +290,41 @@ utfx_ref_result utfx_ref_utf32le_to_utf8(const uint32_t *in, size_t n, uint8_t *
   return mk(UTFX_REF_OK, o, o);
 }
 
+utfx_ref_result utfx_ref_utf16le_to_utf32le(const uint16_t *in, size_t n, uint32_t *out, size_t cap) {
+  if ((n > 0 && in == 0) || (cap > 0 && out == 0)) return mk(UTFX_REF_E_INVALID_ARG, 0, 0);
+  size_t i = 0;
+  uint64_t o = 0;
+  while (i < n) {
+    uint32_t cp;
+    size_t len;
+    int32_t st = decode_utf16_at(in, n, i, &cp, &len);
+    if (st != UTFX_REF_OK) return mk(st, i, o);
+    if (o < cap) out[o] = cp;
+    o++;
+    i += len;
+  }
+  if (o > cap) return mk(UTFX_REF_E_OUTPUT_TOO_SMALL, o, 0);
+  return mk(UTFX_REF_OK, o, o);
+}
+
+utfx_ref_result utfx_ref_utf32le_to_utf16le(const uint32_t *in, size_t n, uint16_t *out, size_t cap) {
+  if ((n > 0 && in == 0) || (cap > 0 && out == 0)) return mk(UTFX_REF_E_INVALID_ARG, 0, 0);
+  uint64_t o = 0;
+  for (size_t i = 0; i < n; i++) {
+    uint32_t cp;
+    int32_t st = decode_utf32_at(in, i, &cp);
+    if (st != UTFX_REF_OK) return mk(st, i, o);
+    uint16_t w[2];
+    size_t k = encode_utf16(cp, w);
+    for (size_t j = 0; j < k; j++) {
+      if (o < cap) out[o] = w[j];
+      o++;
+    }
+  }
+  if (o > cap) return mk(UTFX_REF_E_OUTPUT_TOO_SMALL, o, 0);
+  return mk(UTFX_REF_OK, o, o);
+}
+
 /* ---- loops for exhaustive tests ------------------------------------------------ */
 
 uint64_t utfx_ref_validate_utf8_fixed(const uint8_t *buf, size_t n_strings, size_t len,

@@ -76,6 +76,10 @@ utfx_ref_result utfx_ref_utf8_to_utf32le(const uint8_t *in, size_t n_bytes,
                                          uint32_t *out, size_t cap_units);
 utfx_ref_result utfx_ref_utf32le_to_utf8(const uint32_t *in, size_t n_units,
                                          uint8_t *out, size_t cap_bytes);
+utfx_ref_result utfx_ref_utf16le_to_utf32le(const uint16_t *in, size_t n_words,
+                                            uint32_t *out, size_t cap_units);
+utfx_ref_result utfx_ref_utf32le_to_utf16le(const uint32_t *in, size_t n_units,
+                                            uint16_t *out, size_t cap_words);
 
 /* Convenience loop for exhaustive tests: validates n_strings strings of len bytes
  * each, stored back to back in buf; per-string status and count go to the arrays

@@ -196,6 +196,53 @@ def test_utf32le_against_python_codecs():
         assert np.array_equal(out[: r.written], np.array([ord(ch) for ch in prefix], np.uint32))
 
 
+def test_utf16_utf32_against_python_codecs():
+    """UTF-16LE <-> UTF-32LE: every scalar value both ways against CPython's codecs;
+    every UTF-16 string of length <= 5 over the 12 edge words and every UTF-32 string of
+    length <= 3 over the 16 edge units against the strict decoders' verdict and offset,
+    with the valid prefix transcoded."""
+    s = all_scalar_values_str()
+    u16 = np.frombuffer(s.encode("utf-16-le"), dtype="<u2").astype(np.uint16)
+    u32 = np.frombuffer(s.encode("utf-32-le"), dtype="<u4").astype(np.uint32)
+    r, out = O.utf16le_to_utf32le(u16)
+    assert r == O.Result(O.OK, u32.size, u32.size) and np.array_equal(out[: r.written], u32)
+    r, out = O.utf32le_to_utf16le(u32)
+    assert r == O.Result(O.OK, u16.size, u16.size) and np.array_equal(out[: r.written], u16)
+    for L in range(1, 6):
+        strs = _all_strings(ALPHA16, L).astype(np.uint16)
+        for i in range(strs.shape[0]):
+            b = strs[i].astype("<u2").tobytes()
+            try:
+                b.decode("utf-16-le")
+                good = L
+            except UnicodeDecodeError as e:
+                good = e.start // 2
+            pre = np.frombuffer(b[: 2 * good].decode("utf-16-le").encode("utf-32-le"), "<u4")
+            r, out = O.utf16le_to_utf32le(strs[i])
+            if good == L:
+                assert r == O.Result(O.OK, pre.size, pre.size)
+            else:
+                assert (r.status, r.count) == (O.E_SURROGATE, good)
+            assert r.written == pre.size and np.array_equal(out[: r.written], pre)
+    for L in range(1, 4):
+        strs = _all_strings(ALPHA32, L).astype(np.uint32)
+        for i in range(strs.shape[0]):
+            b = strs[i].astype("<u4").tobytes()
+            try:
+                b.decode("utf-32-le")
+                good = L
+            except UnicodeDecodeError as e:
+                good = e.start // 4
+            pre = np.frombuffer(b[: 4 * good].decode("utf-32-le").encode("utf-16-le"), "<u2")
+            r, out = O.utf32le_to_utf16le(strs[i])
+            if good == L:
+                assert r == O.Result(O.OK, pre.size, pre.size)
+            else:
+                bad = strs[i][good]
+                assert (r.status, r.count) == (O.E_SURROGATE if 0xD800 <= bad <= 0xDFFF else O.E_TOO_LARGE, good)
+            assert r.written == pre.size and np.array_equal(out[: r.written], pre)
+
+
 def test_encoded_surrogates_rejected():
     """Rule 6: the 2,048 surrogate code points in 3-byte form (built by Python's
     surrogatepass handler) are each a SURROGATE error at offset 0."""
