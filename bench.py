@@ -365,8 +365,8 @@ def run_stream(ctx, log, mib, chunk_list, reps=3):
 
 
 def run_utf32(ctx, log, mib, reps=5):
-    """UTF-32LE: mixed-profile UTF-8 -> UTF-32 and CJK / emoji UTF-32 -> UTF-8 on
-    buffers of `mib` MiB of input, device time per call (HIP events around repeated
+    """UTF-32LE: mixed-profile UTF-8 -> UTF-32, and CJK / emoji UTF-32 -> UTF-8,
+    UTF-32 -> UTF-16LE and UTF-16LE -> UTF-32 on buffers of `mib` MiB of input, device time per call (HIP events around repeated
     async calls) and HBM bytes (input + output) per second."""
     import numpy as np
     import torch
@@ -403,6 +403,15 @@ def run_utf32(ctx, log, mib, reps=5):
         dst = torch.empty(n, dtype=torch.uint8, device="cuda")
         ms, w = timed(ctx.utf32le_to_utf8_async, src, dst)
         cases.append((prof, "utf32le->utf8", n, w, ms))
+        dst = torch.empty(n // 2, dtype=torch.int16, device="cuda")
+        ms, w = timed(ctx.utf32le_to_utf16le_async, src, dst)
+        cases.append((prof, "utf32le->utf16le", n, 2 * w, ms))
+        del src, dst
+        words = synth.config_buffer(prof, synth.DIR_16TO8, n, config=2)
+        src = torch.from_numpy(words.view(np.int16)).cuda()
+        dst = torch.empty(n // 2, dtype=torch.int32, device="cuda")
+        ms, w = timed(ctx.utf16le_to_utf32le_async, src, dst)
+        cases.append((prof, "utf16le->utf32le", n, 4 * w, ms))
         del src, dst
     torch.cuda.empty_cache()
     for prof, d, nin, nout, ms in cases:

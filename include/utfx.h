@@ -197,6 +197,19 @@ utfx_status utfx_utf8_to_utf32le_async(utfx_ctx *ctx, const uint8_t *in, size_t 
                                        uint32_t *out, size_t cap_units, utfx_result *d_result);
 utfx_status utfx_utf32le_to_utf8_async(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
                                        uint8_t *out, size_t cap_bytes, utfx_result *d_result);
+/* UTF-16LE <-> UTF-32LE: UTF-16 input is validated exactly as by utfx_validate_utf16le
+ * (an unpaired surrogate is UTFX_E_SURROGATE at its offset) and a pair becomes one
+ * code point (section 2.1); UTF-32 input as above, a code point above U+FFFF becoming
+ * a surrogate pair.  Room for n_words units (UTF-16 -> UTF-32) or 2 n_units words
+ * (UTF-32 -> UTF-16) always suffices. */
+utfx_result utfx_utf16le_to_utf32le(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                    uint32_t *out, size_t cap_units);
+utfx_result utfx_utf32le_to_utf16le(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
+                                    uint16_t *out, size_t cap_words);
+utfx_status utfx_utf16le_to_utf32le_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                          uint32_t *out, size_t cap_units, utfx_result *d_result);
+utfx_status utfx_utf32le_to_utf16le_async(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
+                                          uint16_t *out, size_t cap_words, utfx_result *d_result);
 
 /* ---- streams: input in chunks cut at any unit offset -------------------------
  * A stream transcodes input that arrives in pieces.  Its result is the result of the

@@ -257,10 +257,11 @@ utfx_status store_result_async(utfx_ctx* c, void* d_result, int32_t st, uint64_t
   return UTFX_OK;
 }
 
-enum Kind { LEN8, LEN16, VAL8, VAL16, U8U16, U16U8, VAL32, U8U32, U32U8 };
+enum Kind { LEN8, LEN16, VAL8, VAL16, U8U16, U16U8, VAL32, U8U32, U32U8, U16U32, U32U16 };
 
 // UTF-32 launches use one fixed configuration each: (threads, tiles per segment).
 constexpr uint32_t kU8U32Wg = 256, kU8U32Seg = 2, kU32U8Wg = 256, kU32U8Seg = 4, kVal32Wg = 256, kVal32Seg = 8;
+constexpr uint32_t kU16U32Wg = 256, kU16U32Seg = 2, kU32U16Wg = 256, kU32U16Seg = 4;
 
 hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
   switch (kind) {
@@ -283,7 +284,13 @@ hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
       hipLaunchKernelGGL(k_fin_u8u32<kU8U32Wg>, dim3(1), dim3(kU8U32Wg), 0, s, L);
       return hipGetLastError();
     case U32U8:
-      hipLaunchKernelGGL(k_fin_u32u8<kU32U8Wg>, dim3(1), dim3(kU32U8Wg), 0, s, L);
+      hipLaunchKernelGGL((k_fin_u32to<kU32U8Wg, false>), dim3(1), dim3(kU32U8Wg), 0, s, L);
+      return hipGetLastError();
+    case U32U16:
+      hipLaunchKernelGGL((k_fin_u32to<kU32U16Wg, true>), dim3(1), dim3(kU32U16Wg), 0, s, L);
+      return hipGetLastError();
+    case U16U32:
+      hipLaunchKernelGGL(k_fin_u16u32<kU16U32Wg>, dim3(1), dim3(kU16U32Wg), 0, s, L);
       return hipGetLastError();
     default:
       return launch_fin_u16u8(wg, 1, L, s);
@@ -295,11 +302,12 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
                 bool be = false) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
-  const bool in16 = (kind == LEN16 || kind == VAL16 || kind == U16U8);
-  const bool out16 = (kind == U8U16);
-  const bool in32 = (kind == VAL32 || kind == U32U8);
-  const bool out32 = (kind == U8U32);
-  const bool has_out = (kind == U8U16 || kind == U16U8 || kind == U8U32 || kind == U32U8);
+  const bool in16 = (kind == LEN16 || kind == VAL16 || kind == U16U8 || kind == U16U32);
+  const bool out16 = (kind == U8U16 || kind == U32U16);
+  const bool in32 = (kind == VAL32 || kind == U32U8 || kind == U32U16);
+  const bool out32 = (kind == U8U32 || kind == U16U32);
+  const bool has_out = (kind == U8U16 || kind == U16U8 || kind == U8U32 || kind == U32U8 || kind == U16U32 ||
+                        kind == U32U16);
   if (!d_result) {
     set_msg(c, "null result pointer");
     return UTFX_E_INVALID_ARG;
@@ -340,7 +348,9 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
   switch (kind) {
     case VAL32:
     case U8U32:
-    case U32U8: break;
+    case U32U8:
+    case U16U32:
+    case U32U16: break;
     case LEN8: op = UTFX_OP_LENGTH_UTF8; break;
     case LEN16: op = UTFX_OP_LENGTH_UTF16; break;
     case VAL8: op = UTFX_OP_VALIDATE_UTF8; extra = 1; break;
@@ -354,6 +364,8 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
   if (kind == VAL32) s = prep_cfg(c, kVal32Wg, kVal32Seg, in, n, unit, 0, d_result, L, wg);
   else if (kind == U8U32) s = prep_cfg(c, kU8U32Wg, kU8U32Seg, in, n, unit, 1, d_result, L, wg);
   else if (kind == U32U8) s = prep_cfg(c, kU32U8Wg, kU32U8Seg, in, n, unit, 0, d_result, L, wg);
+  else if (kind == U16U32) s = prep_cfg(c, kU16U32Wg, kU16U32Seg, in, n, unit, 1, d_result, L, wg);
+  else if (kind == U32U16) s = prep_cfg(c, kU32U16Wg, kU32U16Seg, in, n, unit, 0, d_result, L, wg);
   else s = prep(c, op, in, n, unit, extra, d_result, L, wg);
   if (s != UTFX_OK) return s;
   L.out = out;
@@ -380,7 +392,18 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
       e = hipGetLastError();
       break;
     case U32U8:
-      hipLaunchKernelGGL((k_u32_to_u8<kU32U8Wg, kU32U8Seg>), dim3((uint32_t)L.ntiles), dim3(kU32U8Wg), 0, c->stream, L);
+      hipLaunchKernelGGL((k_u32_to<kU32U8Wg, kU32U8Seg, uint8_t>), dim3((uint32_t)L.ntiles), dim3(kU32U8Wg), 0,
+                         c->stream, L);
+      e = hipGetLastError();
+      break;
+    case U32U16:
+      hipLaunchKernelGGL((k_u32_to<kU32U16Wg, kU32U16Seg, uint16_t>), dim3((uint32_t)L.ntiles), dim3(kU32U16Wg), 0,
+                         c->stream, L);
+      e = hipGetLastError();
+      break;
+    case U16U32:
+      hipLaunchKernelGGL((k_u16_to_u32<kU16U32Wg, kU16U32Seg>), dim3((uint32_t)L.ntiles), dim3(kU16U32Wg), 0,
+                         c->stream, L);
       e = hipGetLastError();
       break;
   }
@@ -586,6 +609,21 @@ utfx_status utfx_utf8_to_utf32le_async(utfx_ctx* c, const uint8_t* in, size_t n,
 utfx_status utfx_utf32le_to_utf8_async(utfx_ctx* c, const uint32_t* in, size_t n, uint8_t* out, size_t cap,
                                        utfx_result* d_result) {
   return run(c, U32U8, in, n, out, cap, d_result);
+}
+
+utfx_result utfx_utf16le_to_utf32le(utfx_ctx* c, const uint16_t* in, size_t n, uint32_t* out, size_t cap) {
+  return run_sync(c, U16U32, in, n, out, cap);
+}
+utfx_result utfx_utf32le_to_utf16le(utfx_ctx* c, const uint32_t* in, size_t n, uint16_t* out, size_t cap) {
+  return run_sync(c, U32U16, in, n, out, cap);
+}
+utfx_status utfx_utf16le_to_utf32le_async(utfx_ctx* c, const uint16_t* in, size_t n, uint32_t* out, size_t cap,
+                                          utfx_result* d_result) {
+  return run(c, U16U32, in, n, out, cap, d_result);
+}
+utfx_status utfx_utf32le_to_utf16le_async(utfx_ctx* c, const uint32_t* in, size_t n, uint16_t* out, size_t cap,
+                                          utfx_result* d_result) {
+  return run(c, U32U16, in, n, out, cap, d_result);
 }
 
 utfx_status utfx_stream_init(utfx_stream* st, int format) {

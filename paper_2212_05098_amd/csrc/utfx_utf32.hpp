@@ -8,9 +8,11 @@
 //   payload bits of its 1-4 bytes (Figure 1(a)); a chunk's count is its number of
 //   non-continuation bytes, so characters that start in the 3 bytes before a chunk and
 //   end inside it are emitted by that chunk (spill8_chars).
-//   UTF-32 -> UTF-8: each unit is a character by itself; a unit in U+D800..DFFF or above
-//   U+10FFFF is an error at its own offset (section 2), and the others are encoded by
-//   Figure 1(a).
+//   UTF-32 -> UTF-8 / UTF-16: each unit is a character by itself; a unit in U+D800..DFFF
+//   or above U+10FFFF is an error at its own offset (section 2), and the others are
+//   encoded by Figure 1(a) or as one word / a surrogate pair (section 2.1).
+//   UTF-16 -> UTF-32: a pair is emitted once, at its low surrogate; pairing is checked
+//   as in UTF-16 -> UTF-8 (section 7.4).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -240,34 +242,42 @@ __device__ __forceinline__ uint32_t len32(uint32_t u) {
   return u < 0x80u ? 1u : (u < 0x800u ? 2u : (u < 0x10000u ? 3u : 4u));
 }
 
-// Bytes of the in-range units of a chunk, and the first invalid in-range unit (4 = none).
+// UTF-16 words of a unit (section 2.1): two above U+FFFF, whether valid or not.
+__device__ __forceinline__ uint32_t len32w(uint32_t u) { return u > 0xFFFFu ? 2u : 1u; }
+
+// Output units (UTF-8 bytes, or UTF-16 words with OUT16) of the in-range units of a
+// chunk, and the first invalid in-range unit (4 = none).
+template <bool OUT16 = false>
 __device__ __forceinline__ uint32_t count32(const uint32_t x[4], uint64_t q0, uint64_t lo, uint64_t hi, bool full,
                                            uint32_t* first_bad) {
   uint32_t acc = 0, fb = 4;
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
     const bool in = full || (q0 + i >= lo && q0 + i < hi);
-    acc += in ? len32(x[i]) : 0u;
+    acc += in ? (OUT16 ? len32w(x[i]) : len32(x[i])) : 0u;
     if (in && bad32(x[i])) fb = (uint32_t)i;
   }
   *first_bad = fb;
   return acc;
 }
 
-template <int WG, int S>
-struct Seg32to8Smem {
+template <int WG, int S, typename U>
+struct Seg32OutSmem {
   static constexpr int NW = WG / 64;
   static constexpr uint32_t PAD = 16;
-  static constexpr uint32_t SEGO = 16u * WG * S;  // bound on a segment's output bytes
-  uint8_t stage[PAD + SEGO + 32];
+  static constexpr uint32_t SEGO = (16u / sizeof(U)) * WG * S;  // bound on a segment's output units
+  U stage[PAD + SEGO + 32];
   uint32_t wtot[NW * (S / 2)];
   unsigned long long seg_base;
   unsigned long long werr;
 };
 
-template <int WG, int S>
-__global__ void __launch_bounds__(WG) k_u32_to_u8(Launch L) {
-  typedef Seg32to8Smem<WG, S> M;
+// UTF-32 -> UTF-8 (U = uint8_t, Figure 1(a)) or UTF-16 (U = uint16_t, section 2.1; the
+// words byte-swapped for UTF-16BE when L.be).
+template <int WG, int S, typename U>
+__global__ void __launch_bounds__(WG) k_u32_to(Launch L) {
+  constexpr bool OUT16 = sizeof(U) == 2;
+  typedef Seg32OutSmem<WG, S, U> M;
   __shared__ __attribute__((aligned(16))) M sm;
   constexpr uint32_t T = 4u * WG;  // units per tile
   constexpr uint32_t SEGU = T * S;
@@ -285,25 +295,33 @@ __global__ void __launch_bounds__(WG) k_u32_to_u8(Launch L) {
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const uint64_t q0 = q00 + (uint64_t)k * T;
-    c[k] = count32(x[k], q0, lo, hi, segfull || (q0 >= lo && q0 + 4 <= hi), &fb[k]);
+    c[k] = count32<OUT16>(x[k], q0, lo, hi, segfull || (q0 >= lo && q0 + 4 <= hi), &fb[k]);
   }
   if (threadIdx.x == 0) sm.werr = NO_ERR;
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, sm.wtot);  // contains a barrier
   if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
 
-  // ---- encode into the stage (Figure 1(a)); the first invalid unit of a chunk is exact
+  // ---- encode into the stage; the first invalid unit of a chunk is exact
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const uint64_t q0 = q00 + (uint64_t)k * T;
-    uint8_t* p = sm.stage + PAD + off[k];
+    U* p = sm.stage + PAD + off[k];
     const bool full = segfull || (q0 >= lo && q0 + 4 <= hi);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t u = x[k][i];
       const bool in = full || (q0 + i >= lo && q0 + i < hi);
-      const uint32_t n = in ? len32(u) : 0u;
-      if (n == 1) {
+      const uint32_t n = in ? (OUT16 ? len32w(u) : len32(u)) : 0u;
+      if (OUT16) {
+        if (n == 1) {
+          p[0] = (U)u;
+        } else if (n == 2) {
+          const uint32_t v = u - 0x10000u;
+          p[0] = (U)(0xD800u + ((v >> 10) & 0x3FFu));
+          p[1] = (U)(0xDC00u + (v & 0x3FFu));
+        }
+      } else if (n == 1) {
         p[0] = (uint8_t)u;
       } else if (n == 2) {
         p[0] = (uint8_t)(0xC0u | (u >> 6));
@@ -331,14 +349,14 @@ __global__ void __launch_bounds__(WG) k_u32_to_u8(Launch L) {
   }
   __syncthreads();
   if (threadIdx.x == 0) report_err(L.err, sm.werr);
-  store_span<uint8_t>(sm.stage, PAD, seg_total, reinterpret_cast<uint8_t*>(L.out), sm.seg_base, L.cap, threadIdx.x,
-                      WG);
+  store_span<U>(sm.stage, PAD, seg_total, reinterpret_cast<U*>(L.out), sm.seg_base, L.cap, threadIdx.x, WG,
+                L.be != 0);
 }
 
-// Result of a UTF-32 -> UTF-8 launch: the kind of the first invalid unit and the bytes
-// of the units before it, or the total against cap.
-template <int WG>
-__global__ void __launch_bounds__(WG) k_fin_u32u8(Launch L) {
+// Result of a UTF-32 -> UTF-8 (UTF-16 with OUT16) launch: the kind of the first invalid
+// unit and the output units of the units before it, or the total against cap.
+template <int WG, bool OUT16>
+__global__ void __launch_bounds__(WG) k_fin_u32to(Launch L) {
   __shared__ unsigned long long lds[WG / 64 + 2];
   constexpr uint64_t T = 4ull * WG;
   const uint64_t err = ld_agent(L.err);
@@ -352,7 +370,7 @@ __global__ void __launch_bounds__(WG) k_fin_u32u8(Launch L) {
       const uint64_t q0 = q0b + 4ull * threadIdx.x;
       uint32_t x[4], fb;
       load32(L, q0, x);
-      acc += count32(x, q0, L.mis, qoff, false, &fb);
+      acc += count32<OUT16>(x, q0, L.mis, qoff, false, &fb);
     }
     const uint64_t s = block_sum_u64<WG>(acc, lds);
     written = (seg ? tile_inclusive(L.status, seg - 1) : 0) + s;
@@ -369,6 +387,159 @@ __global__ void __launch_bounds__(WG) k_fin_u32u8(Launch L) {
     } else {
       write_result(L.result, ST_OK, tot, tot);
     }
+    reset_ws(L.ws);
+  }
+}
+
+// ================================================================ UTF-16LE -> UTF-32LE
+
+// Characters starting in an 8-word chunk: its in-range words that are not low
+// surrogates.
+__device__ __forceinline__ uint32_t count16_chars(const uint32_t x[4], uint64_t q0, uint64_t lo, uint64_t hi,
+                                                  bool full) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t w = (x[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+    const bool in = full || (q0 + j >= lo && q0 + j < hi);
+    acc += (in && !is_lo(w)) ? 1u : 0u;
+  }
+  return acc;
+}
+
+template <int WG, int S>
+struct Seg16to32Smem {
+  static constexpr int NW = WG / 64;
+  static constexpr uint32_t SEGW = 8u * WG * S;
+  static constexpr uint32_t PAD = 16;
+  static constexpr uint32_t LIM = PAD + SEGW;
+  static constexpr uint32_t DUMP = LIM + 8;
+  static constexpr uint32_t SSZ = DUMP + 20;
+  uint32_t stage[SSZ];
+  uint32_t wtot[NW * (S / 2)];
+  uint32_t halo[S * NW];
+  unsigned long long seg_base;
+  unsigned long long werr;
+  uint32_t bounds[2];
+};
+
+// UTF-16 (L.be: big-endian words) -> UTF-32: validation by the surrogate sequencing
+// check of section 7.4 (analyze16 / locate16); a BMP word is its code point and a pair
+// is emitted once, at its low surrogate, as 0x10000 + (high - 0xD800) * 1024 +
+// (low - 0xDC00) (section 2.1).  A pair whose high surrogate ends the previous chunk is
+// emitted by this chunk.
+template <int WG, int S>
+__global__ void __launch_bounds__(WG) k_u16_to_u32(Launch L) {
+  typedef Seg16to32Smem<WG, S> M;
+  __shared__ __attribute__((aligned(16))) M sm;
+  constexpr int NW = M::NW;
+  constexpr uint32_t TW = 8u * WG;
+  constexpr uint32_t SEGW = M::SEGW;
+  constexpr uint32_t PAD = M::PAD, LIM = M::LIM, DUMP = M::DUMP;
+  const uint64_t seg = blockIdx.x;
+  uint32_t x[S][4];
+  load_seg16<WG, S>(L, seg, x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t epoch = cur_epoch(L.ws);
+  const uint64_t s0 = seg * SEGW;
+  const uint64_t q00 = s0 + 8ull * threadIdx.x;
+  const uint64_t lo = L.mis, hi = L.mis + L.n;
+  const bool segfull = s0 >= lo && s0 + SEGW <= hi;
+
+  const uint32_t wp_seg = (threadIdx.x == 0) ? (load16_prev(L, s0) << 16) : 0u;
+  uint32_t c[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const uint64_t q0 = q00 + (uint64_t)k * TW;
+    c[k] = count16_chars(x[k], q0, lo, hi, segfull || (q0 >= lo && q0 + 8 <= hi));
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) sm.halo[k * NW + wid] = x[k][3];
+  }
+  if (threadIdx.x == 0) sm.werr = NO_ERR;
+  uint32_t off[S];
+  const uint32_t seg_total = segment_offsets<WG, S>(c, off, sm.wtot);  // contains a barrier
+  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const uint64_t q0 = q00 + (uint64_t)k * TW;
+    const uint32_t hl = (wid > 0) ? sm.halo[k * NW + wid - 1] : (k > 0 ? sm.halo[(k - 1) * NW + NW - 1] : wp_seg);
+    const uint32_t wp = wave_shr1(x[k][3], hl) >> 16;  // the word before the chunk
+    const bool full = segfull || (q0 >= lo && q0 + 8 <= hi);
+    uint32_t len[8], cnt;
+    bool det;
+    if (full) analyze16<true>(x[k], wp, q0, lo, hi, len, cnt, det);
+    else analyze16<false>(x[k], wp, q0, lo, hi, len, cnt, det);
+    const uint32_t idx = PAD + off[k] - (is_hi(wp) ? 1u : 0u);
+    const bool fits = idx + 8 <= LIM;
+    uint32_t* pw = sm.stage + (fits ? idx : DUMP);
+    uint32_t* const dump = sm.stage + DUMP;
+    uint32_t prev = wp;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t w = (x[k][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+      const bool in = full || (q0 + j >= lo && q0 + j < hi);
+      const uint32_t cp = is_lo(w) ? 0x10000u + ((prev - 0xD800u) << 10) + (w - 0xDC00u) : w;
+      const uint32_t bit = (in && !is_hi(w)) ? 1u : 0u;
+      *(bit ? pw : dump) = cp;
+      pw += bit;
+      prev = w;
+    }
+    if (k == 0 && threadIdx.x == 0) sm.bounds[0] = idx;
+    if (k == S - 1 && threadIdx.x == WG - 1) sm.bounds[1] = fits ? (uint32_t)(pw - sm.stage) : LIM;
+    if (det) {
+      const int64_t p0 = (int64_t)q0 - (int64_t)L.mis;
+      if (before(p0 - 1, sm.werr)) {
+        const uint16_t* in16 = reinterpret_cast<const uint16_t*>(L.base) + L.mis;
+        const uint64_t e = locate16(in16, L.n, p0 - 1, p0 + 8, L.be != 0);
+        if (e != NO_ERR) atomicMin(&sm.werr, (unsigned long long)e);
+      }
+    }
+  }
+  if (wid == 0) {
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    if (lane == 0) sm.seg_base = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) report_err(L.err, sm.werr);
+  const uint32_t st0 = sm.bounds[0];
+  uint32_t st1 = sm.bounds[1];
+  st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
+  const int64_t g = (int64_t)sm.seg_base + (int64_t)st0 - (int64_t)PAD;
+  store_span<uint32_t>(sm.stage, st0, st1 - st0, reinterpret_cast<uint32_t*>(L.out), (uint64_t)g, L.cap,
+                       threadIdx.x, WG);
+}
+
+// Result of a UTF-16 -> UTF-32 launch: the characters of the valid prefix (words that
+// are not low surrogates before the error), or the total against cap.
+template <int WG>
+__global__ void __launch_bounds__(WG) k_fin_u16u32(Launch L) {
+  __shared__ unsigned long long lds[WG / 64 + 2];
+  constexpr uint64_t TW = 8ull * WG;
+  const uint64_t err = ld_agent(L.err);
+  const bool fault = ld_fault(L.ws) != 0;
+  uint64_t written = 0;
+  if (!fault && err != NO_ERR) {
+    const uint64_t qoff = err + L.mis;
+    const uint64_t seg = qoff / L.seg_units;
+    uint32_t acc = 0;
+    for (uint64_t q0b = seg * L.seg_units; q0b < qoff; q0b += TW) {
+      const uint64_t q0 = q0b + 8ull * threadIdx.x;
+      uint32_t x[4];
+      load16(L, q0, x);
+      acc += count16_chars(x, q0, L.mis, qoff, false);
+    }
+    const uint64_t s = block_sum_u64<WG>(acc, lds);
+    written = (seg ? tile_inclusive(L.status, seg - 1) : 0) + s;
+  }
+  if (threadIdx.x == 0) {
+    const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
+    if (fault) write_result(L.result, ST_DEVICE, 0, 0);
+    else if (err != NO_ERR) write_result(L.result, ST_SURROGATE, err, written);
+    else if (tot > L.cap) write_result(L.result, ST_OUTPUT_TOO_SMALL, tot, 0);
+    else write_result(L.result, ST_OK, tot, tot);
     reset_ws(L.ws);
   }
 }

@@ -1,16 +1,18 @@
 """UTF-32LE through the C ABI against the oracle (pinned to CPython's utf-32-le codec):
-UTF-8 -> UTF-32 (validation of section 6.4, code points of Figure 1(a)) and UTF-32 ->
-UTF-8 (section 2's range and surrogate rules), element by element, at ragged sizes
-that span many segments, with injected errors, every UTF-8 error kind at every chunk
-offset, the class-edge alphabets, misaligned pointers, small outputs, the async forms
-and one 256 MiB buffer per direction."""
+UTF-8 -> UTF-32 (validation of section 6.4, code points of Figure 1(a)), UTF-32 ->
+UTF-8 (section 2's range and surrogate rules) and UTF-16LE <-> UTF-32LE (section 2.1),
+element by element, at ragged sizes that span many segments, with injected errors,
+every UTF-8 error kind and every unpaired surrogate at every chunk offset, the
+class-edge alphabets, misaligned pointers, small outputs, the async forms and one 256
+MiB buffer per direction."""
 import numpy as np
 import pytest
 
 import oracle as O
 import paper_2212_05098_amd as utfx
 from paper_2212_05098_amd import synth
-from gpu_helpers import check_u32_to_u8, check_u8_to_u32, dev_u8, dev_u32, note
+from gpu_helpers import (check_u16_to_u32, check_u32_to_u16, check_u32_to_u8, check_u8_to_u32, dev_u8, dev_u16,
+                         dev_u32, note)
 
 pytestmark = pytest.mark.gpu
 
@@ -181,4 +183,111 @@ def test_full_size_each_direction(ctx):
     note("utf32 full size utf32->utf8")
     r = check_u32_to_u8(ctx, units)
     assert r.status == utfx.OK
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- UTF-16LE <-> UTF-32LE
+
+@pytest.mark.parametrize("prof", synth.SCRIPT_PROFILES + ("mixed4",))
+def test_utf16_utf32_ragged_sizes(ctx, prof):
+    rng = synth.rng_for(90, synth.PROFILE_IDS[prof])
+    for n in SIZES:
+        note("utf16<->utf32 %s n=%d" % (prof, n))
+        check_u16_to_u32(ctx, synth.utf16_buffer(prof, n, rng))
+        check_u32_to_u16(ctx, synth.utf32_buffer(prof, n, rng))
+
+
+@pytest.mark.parametrize("rate", [1e-4, 3e-2])
+def test_utf16_utf32_injected_errors(ctx, rate):
+    rng = synth.rng_for(91, int(rate * 1e6))
+    for prof in ("emoji", "mixed4"):
+        inj = synth.inject_utf16(prof, 200_000, rate, rng)
+        note("utf16->utf32 inject %s rate=%g" % (prof, rate))
+        r = check_u16_to_u32(ctx, inj.data)
+        assert r.status == utfx.E_SURROGATE and r.count == inj.positions[0]
+        units, pos = synth.inject_utf32(synth.utf32_buffer(prof, 100_000, rng), rate, rng)
+        note("utf32->utf16 inject %s rate=%g" % (prof, rate))
+        r = check_u32_to_u16(ctx, units)
+        assert r.status in (utfx.E_SURROGATE, utfx.E_TOO_LARGE) and r.count == pos[0]
+
+
+def test_utf16_surrogate_error_at_every_chunk_offset(ctx):
+    rng = synth.rng_for(92)
+    base = synth.utf16_buffer("emoji", 3000, rng)
+    for kind in synth.UTF16_KINDS:
+        for off in range(0, 40):
+            w = base.copy()
+            if off > 0:
+                w[off - 1] = 0x41
+            if off > 1 and 0xD800 <= w[off - 2] < 0xDC00:
+                w[off - 2] = 0x40
+            w[off] = synth.utf16_error_item(kind, rng)[0]
+            w[off + 1] = 0x42
+            if 0xDC00 <= w[off + 2] < 0xE000:
+                w[off + 2] = 0x43
+            note("utf16->utf32 %s off=%d" % (kind, off))
+            assert check_u16_to_u32(ctx, w).count == off
+
+
+def test_utf16_utf32_alphabets(ctx):
+    from test_oracle_pins import ALPHA16, ALPHA32, _all_strings
+
+    for L in (1, 2, 3):
+        note("utf16->utf32 alphabet L=%d" % L)
+        for s in _all_strings(ALPHA16, L).astype(np.uint16):
+            check_u16_to_u32(ctx, s, guard=8)
+        note("utf32->utf16 alphabet L=%d" % L)
+        for s in _all_strings(ALPHA32, L).astype(np.uint32):
+            check_u32_to_u16(ctx, s, guard=8)
+
+
+@pytest.mark.parametrize("shift", [0, 1, 3, 6])
+def test_utf16_utf32_misaligned_and_capacity(ctx, shift):
+    rng = synth.rng_for(93, shift)
+    words = synth.utf16_buffer("emoji", 10_007, rng)
+    units = synth.utf32_buffer("mixed4", 10_007, rng)
+    note("utf16<->utf32 shift=%d" % shift)
+    check_u16_to_u32(ctx, words, in_shift=shift, out_shift=shift % 4)
+    check_u32_to_u16(ctx, units, in_shift=shift % 4, out_shift=shift)
+    need = O.utf16le_to_utf32le(words)[0].count
+    for cap in (0, 1, need - 1, need):
+        r = check_u16_to_u32(ctx, words, cap=cap, out_shift=shift % 4)
+        assert r.status == (utfx.OK if cap >= need else utfx.E_OUTPUT_TOO_SMALL)
+    need = O.utf32le_to_utf16le(units)[0].count
+    for cap in (0, 1, need - 1, need):
+        r = check_u32_to_u16(ctx, units, cap=cap, out_shift=shift)
+        assert r.status == (utfx.OK if cap >= need else utfx.E_OUTPUT_TOO_SMALL)
+
+
+def test_utf16_utf32_async_and_round_trip(ctx):
+    import torch
+
+    rng = synth.rng_for(94)
+    words = synth.utf16_buffer("mixed4", 1_000_003, rng)
+    s16, _ = dev_u16(words)
+    o32 = torch.empty(words.size, dtype=torch.int32, device="cuda")
+    back = torch.empty(2 * words.size, dtype=torch.int16, device="cuda")
+    res = utfx.result_tensor(2)
+    assert ctx.utf16le_to_utf32le_async(s16, o32, res[0:24]) == utfx.OK
+    torch.cuda.synchronize()
+    r = utfx.results_from_tensor(res)[0]
+    assert tuple(r) == tuple(O.utf16le_to_utf32le(words)[0])
+    assert ctx.utf32le_to_utf16le_async(o32[: r.written], back, res[24:48]) == utfx.OK
+    torch.cuda.synchronize()
+    r2 = utfx.results_from_tensor(res)[1]
+    assert tuple(r2) == (utfx.OK, words.size, words.size)
+    assert np.array_equal(back[: words.size].cpu().numpy().view(np.uint16), words)
+
+
+def test_utf16_utf32_full_size(ctx):
+    import torch
+
+    full = 256 << 20
+    words = synth.config_buffer("emoji", synth.DIR_16TO8, full, config=2)
+    note("utf16->utf32 full size")
+    assert check_u16_to_u32(ctx, words).status == utfx.OK
+    torch.cuda.empty_cache()
+    units = synth.utf32_buffer("mixed4", full // 4, synth.rng_for(95))
+    note("utf32->utf16 full size")
+    assert check_u32_to_u16(ctx, units).status == utfx.OK
     torch.cuda.empty_cache()
