@@ -259,9 +259,10 @@ utfx_status store_result_async(utfx_ctx* c, void* d_result, int32_t st, uint64_t
 
 enum Kind { LEN8, LEN16, VAL8, VAL16, U8U16, U16U8, VAL32, U8U32, U32U8, U16U32, U32U16 };
 
-// UTF-32 launches use one fixed configuration each: (threads, tiles per segment).
+// UTF-32 launches use one fixed configuration each: (threads, tiles per segment), the
+// fastest of 2, 4 and 8 tiles measured on 256 MiB inputs.
 constexpr uint32_t kU8U32Wg = 256, kU8U32Seg = 2, kU32U8Wg = 256, kU32U8Seg = 4, kVal32Wg = 256, kVal32Seg = 8;
-constexpr uint32_t kU16U32Wg = 256, kU16U32Seg = 2, kU32U16Wg = 256, kU32U16Seg = 4;
+constexpr uint32_t kU16U32Wg = 256, kU16U32Seg = 4, kU32U16Wg = 256, kU32U16Seg = 8;
 
 hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
   switch (kind) {

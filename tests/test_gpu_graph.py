@@ -149,3 +149,59 @@ def test_capture_refuses_growth(ctx):
         assert all(r.status == utfx.OK and r.count == 1000 for r in utfx.results_from_tensor(res))
     finally:
         fresh.close()
+
+
+def test_graph_other_formats_replays(ctx):
+    """UTF-8 -> UTF-32, UTF-32 -> UTF-16LE and UTF-16BE -> UTF-8 recorded in one graph
+    and replayed with new contents (every other replay with an error), eager work and
+    synchronisations in between; every replay against the oracle."""
+    import torch
+
+    n = 150_000
+    s8 = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    o32 = torch.zeros(n, dtype=torch.int32, device="cuda")
+    s32 = torch.zeros(n // 4, dtype=torch.int32, device="cuda")
+    o16 = torch.zeros(n // 2, dtype=torch.int16, device="cuda")
+    sbe = torch.zeros(n // 2, dtype=torch.int16, device="cuda")
+    o8 = torch.zeros(3 * (n // 2), dtype=torch.uint8, device="cuda")
+    res = utfx.result_tensor(3)
+
+    def record():
+        assert ctx.utf8_to_utf32le_async(s8, o32, res[0:24]) == utfx.OK
+        assert ctx.utf32le_to_utf16le_async(s32, o16, res[24:48]) == utfx.OK
+        assert ctx.utf16be_to_utf8_async(sbe, o8, res[48:72]) == utfx.OK
+
+    record()  # eager calls size the workspaces
+    torch.cuda.synchronize()
+    ctx.capture_begin()
+    try:
+        record()
+    finally:
+        g = ctx.capture_end()
+    for rep, prof in enumerate(("cjk", "emoji", "mixed4", "latin")):
+        rng = synth.rng_for(22, rep)
+        d8 = synth.utf8_buffer(prof, n, rng)
+        u32 = synth.utf32_buffer(prof, n // 4, rng)
+        wbe = synth.utf16_buffer(prof, n // 2, rng).byteswap()
+        if rep % 2:
+            d8[n // 3] = 0xC0
+            u32[n // 7] = 0x110000
+            wbe[n // 5] = 0x00DC  # a lone low surrogate, big-endian
+        s8.copy_(torch.from_numpy(d8))
+        s32.copy_(torch.from_numpy(u32.view(np.int32)))
+        sbe.copy_(torch.from_numpy(wbe.view(np.int16)))
+        torch.cuda.synchronize()
+        note("graph other formats replay %d" % rep)
+        g.launch()
+        torch.cuda.synchronize()
+        got = utfx.results_from_tensor(res)
+        for r, (want, ref), out in ((got[0], O.utf8_to_utf32le(d8), o32), (got[1], O.utf32le_to_utf16le(u32), o16),
+                                    (got[2], O.utf16be_to_utf8(wbe), o8)):
+            assert tuple(r) == tuple(want), (rep, r, want)
+            host = out.cpu().numpy()
+            host = host.view(np.uint32) if host.dtype == np.int32 else (
+                host.view(np.uint16) if host.dtype == np.int16 else host)
+            assert np.array_equal(host[: want.written], ref[: want.written]), rep
+        # eager work between replays
+        assert ctx.validate_utf32le(s32).status == (utfx.OK if rep % 2 == 0 else utfx.E_TOO_LARGE)
+    g.close()
