@@ -1,5 +1,6 @@
 /*
- * utfx.h -- validating UTF-8 <-> UTF-16LE transcoding on AMD Instinct MI355X (gfx950).
+ * utfx.h -- validating UTF-8 <-> UTF-16LE transcoding on AMD Instinct MI355X (gfx950),
+ * with UTF-16BE and UTF-32LE forms, batched calls, graphs, a server and streams.
  *
  * The operations are those of Clausecker & Lemire, "Transcoding Unicode Characters
  * with AVX-512 Instructions": validating transcoding that, on the first encoding
@@ -18,8 +19,9 @@
  * Two contexts may run concurrently on different streams.
  *
  * Alignment: UTF-8 input and output may start at any byte address.  UTF-16 pointers
- * must be 2-byte aligned (else UTFX_E_INVALID_ARG).  Lengths are in code units: bytes
- * for UTF-8, 16-bit words for UTF-16.
+ * must be 2-byte aligned and UTF-32 pointers 4-byte aligned (else UTFX_E_INVALID_ARG).
+ * Lengths are in code units: bytes for UTF-8, 16-bit words for UTF-16, 32-bit units for
+ * UTF-32.
  *
  * Result (every call): see utfx_result.  Precedence: argument error, then the
  * earliest encoding error, then UTFX_E_OUTPUT_TOO_SMALL, then UTFX_OK.  n = 0 is OK
