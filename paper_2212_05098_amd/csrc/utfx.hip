@@ -36,9 +36,11 @@ struct utfx_ctx {
   unsigned long long* status = nullptr;   // device status words
   uint64_t cap_tiles = 0;
   Result* d_result = nullptr;             // device result slot of synchronous calls
-  Result* h_result = nullptr;             // pinned host copy
-  StreamDev* d_stream = nullptr;          // stream calls: cut description, staged character, results
-  StreamDev* h_stream = nullptr;          // pinned host copy
+  Result* h_result = nullptr;             // pinned host slot the finalisation kernels write directly
+  Result* h_result_dev = nullptr;         // the same memory as the device addresses it (null: copy instead)
+  StreamDev* d_stream = nullptr;          // stream calls: staged character and its output
+  StreamRec* h_stream = nullptr;          // stream calls: results and cut, written by the kernels (pinned)
+  StreamRec* h_stream_dev = nullptr;      // the same memory as the device addresses it
   uint64_t launches = 0;                  // launches since the status words were cleared
   uint32_t tile_bytes[UTFX_OP_COUNT_];
   uint32_t seg_tiles[UTFX_OP_COUNT_];
@@ -425,9 +427,14 @@ utfx_result run_sync(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* o
     set_msg(c, "synchronous call during graph capture");
     return mkres(UTFX_E_INVALID_ARG, 0, 0);
   }
-  utfx_status s = run(c, kind, in, n, out, cap, c->d_result, be);
+  // the finalisation kernel writes the result straight into pinned host memory when the
+  // device can address it (saves a copy per call), else into a device slot copied back
+  utfx_status s = run(c, kind, in, n, out, cap, c->h_result_dev ? static_cast<void*>(c->h_result_dev) : c->d_result,
+                      be);
   if (s != UTFX_OK) return mkres(s, 0, 0);
-  hipError_t e = hipMemcpyAsync(c->h_result, c->d_result, sizeof(Result), hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipSuccess;
+  if (!c->h_result_dev)
+    e = hipMemcpyAsync(c->h_result, c->d_result, sizeof(Result), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     set_err(c, "synchronise", e);
@@ -508,8 +515,8 @@ utfx_result stream_transcode(utfx_ctx* c, utfx_stream* st, const void* in, uint6
   uint32_t carry = 0;
   memcpy(&carry, st->carry, 4);
   const uint32_t flags = (in16 ? SE_IN16 : 0u) | (be ? SE_BE : 0u) | (final ? SE_FINAL : 0u);
-  hipLaunchKernelGGL(k_stream_edge, dim3(1), dim3(64), 0, c->stream, c->d_stream, in, n, h, carry, nc, flags,
-                     grow ? 1u : 0u, out, cap);
+  hipLaunchKernelGGL(k_stream_edge, dim3(1), dim3(64), 0, c->stream, c->d_stream, c->h_stream_dev, in, n, h, carry,
+                     nc, flags, grow ? 1u : 0u, out, cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_err(c, "stream edge launch", e);
@@ -522,11 +529,10 @@ utfx_result stream_transcode(utfx_ctx* c, utfx_stream* st, const void* in, uint6
   const uint64_t cap2 = cap > w1 ? cap - w1 : 0;
   if (p2) {
     void* out2 = cap2 ? static_cast<void*>(static_cast<uint8_t*>(out) + w1 * ou) : nullptr;
-    utfx_status s = run(c, kind, static_cast<const uint8_t*>(in) + h * iu, n - h, out2, cap2, &c->d_stream->r[1], be);
+    utfx_status s = run(c, kind, static_cast<const uint8_t*>(in) + h * iu, n - h, out2, cap2, &c->h_stream_dev->r[1], be);
     if (s != UTFX_OK) return mkres(s, 0, 0);
   }
-  e = hipMemcpyAsync(c->h_stream, c->d_stream, sizeof(StreamDev), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     set_err(c, "synchronise", e);
     return mkres(UTFX_E_DEVICE, 0, 0);
@@ -665,9 +671,12 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
   }
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_result), sizeof(Result));
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(Result), hipHostMallocDefault);
+  if (e == hipSuccess && hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_result_dev), c->h_result, 0) != hipSuccess)
+    c->h_result_dev = nullptr;
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_stream), sizeof(StreamDev));
   if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&c->h_stream), sizeof(StreamDev), hipHostMallocDefault);
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->h_stream), sizeof(StreamRec), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_stream_dev), c->h_stream, 0);
   if (e != hipSuccess) {
     utfx_destroy(c);
     return UTFX_E_DEVICE;

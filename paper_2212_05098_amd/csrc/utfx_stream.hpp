@@ -40,11 +40,18 @@ struct StreamEdge {
   uint8_t keep[8];    // the carried units as they are in memory
 };
 
+// Device memory of a stream call: piece 1 staged, transcoded and copied out from here.
 struct StreamDev {
-  Result r[2];        // results of piece 1 and piece 2
-  StreamEdge e;
+  Result r1;          // piece 1's result before the caller's capacity is applied
   uint8_t stage[16];  // piece 1 (UTF-16 staged little-endian)
   uint8_t out1[16];   // piece 1's output before it is copied out (UTF-16 little-endian)
+};
+
+// What the host reads after the call's one synchronisation; pinned host memory that the
+// kernels write through its device address.
+struct StreamRec {
+  Result r[2];        // results of piece 1 and piece 2
+  StreamEdge e;
 };
 
 enum : uint32_t { SE_IN16 = 1u, SE_BE = 2u, SE_FINAL = 4u };
@@ -59,10 +66,10 @@ __device__ __forceinline__ uint32_t se_len_of_lead(uint32_t b) { return b >= 0xF
 // unfinished character at the chunk's end (not before h).  With grow != 0 the chunk
 // does not finish the carried character (h = n) and is carried along with it instead.
 // Then the wave transcodes piece 1 into out1 and lane 0 copies it to out[0, cap) and
-// writes its result to r[0].
-__global__ void __launch_bounds__(64) k_stream_edge(StreamDev* d, const void* in_v, uint64_t n, uint64_t h,
-                                                    uint32_t carry, uint32_t nc, uint32_t flags, uint32_t grow,
-                                                    void* out, uint64_t cap) {
+// writes its result to rec->r[0]; the cut goes to rec->e.
+__global__ void __launch_bounds__(64) k_stream_edge(StreamDev* d, StreamRec* rec, const void* in_v, uint64_t n,
+                                                    uint64_t h, uint32_t carry, uint32_t nc, uint32_t flags,
+                                                    uint32_t grow, void* out, uint64_t cap) {
   __shared__ __attribute__((aligned(16))) uint8_t wstage[WSTAGE];
   const uint32_t lane = threadIdx.x;
   const bool fin = (flags & SE_FINAL) != 0;
@@ -145,7 +152,7 @@ __global__ void __launch_bounds__(64) k_stream_edge(StreamDev* d, const void* in
     uint32_t* ek = reinterpret_cast<uint32_t*>(e.keep);
     ek[0] = keep[0];
     ek[1] = keep[1];
-    d->e = e;
+    rec->e = e;
     uint32_t* ds = reinterpret_cast<uint32_t*>(d->stage);
     ds[0] = stage[0];
     ds[1] = stage[1];
@@ -159,14 +166,14 @@ __global__ void __launch_bounds__(64) k_stream_edge(StreamDev* d, const void* in
   const uint64_t n1 = nc + h;
   if (!in16)
     wave_u8_to_u16(d->stage, n1, reinterpret_cast<uint16_t*>(d->out1), sizeof(d->out1) / 2,
-                   reinterpret_cast<uint16_t*>(wstage), &d->r[0], alo, ahi);
+                   reinterpret_cast<uint16_t*>(wstage), &d->r1, alo, ahi);
   else
-    wave_u16_to_u8(reinterpret_cast<const uint16_t*>(d->stage), n1, d->out1, sizeof(d->out1), wstage, &d->r[0],
+    wave_u16_to_u8(reinterpret_cast<const uint16_t*>(d->stage), n1, d->out1, sizeof(d->out1), wstage, &d->r1,
                    alo, ahi);
   __threadfence();
   __syncthreads();
   if (lane != 0) return;
-  Result r = d->r[0];
+  Result r = d->r1;
   uint64_t w = r.status == ST_OUTPUT_TOO_SMALL ? 0 : r.written;
   if (r.status == ST_OK && r.count > cap) {
     r.status = ST_OUTPUT_TOO_SMALL;
@@ -182,7 +189,7 @@ __global__ void __launch_bounds__(64) k_stream_edge(StreamDev* d, const void* in
     uint8_t* o8 = static_cast<uint8_t*>(out);
     for (uint64_t i = 0; i < w; ++i) o8[i] = d->out1[i];
   }
-  write_result(&d->r[0], r.status, r.count, r.written);
+  write_result(&rec->r[0], r.status, r.count, r.written);
 }
 
 }  // namespace utfx_dev
