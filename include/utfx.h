@@ -212,6 +212,15 @@ utfx_status utfx_utf16le_to_utf32le_async(utfx_ctx *ctx, const uint16_t *in, siz
                                           uint32_t *out, size_t cap_units, utfx_result *d_result);
 utfx_status utfx_utf32le_to_utf16le_async(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
                                           uint16_t *out, size_t cap_words, utfx_result *d_result);
+/* The same with UTF-16BE words (section 2: the byte order within each 16-bit unit). */
+utfx_result utfx_utf16be_to_utf32le(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                    uint32_t *out, size_t cap_units);
+utfx_result utfx_utf32le_to_utf16be(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
+                                    uint16_t *out, size_t cap_words);
+utfx_status utfx_utf16be_to_utf32le_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
+                                          uint32_t *out, size_t cap_units, utfx_result *d_result);
+utfx_status utfx_utf32le_to_utf16be_async(utfx_ctx *ctx, const uint32_t *in, size_t n_units,
+                                          uint16_t *out, size_t cap_words, utfx_result *d_result);
 
 /* ---- streams: input in chunks cut at any unit offset -------------------------
  * A stream transcodes input that arrives in pieces.  Its result is the result of the

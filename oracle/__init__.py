@@ -256,6 +256,16 @@ def utf32le_to_utf16le(data, cap: Optional[int] = None):
     return r, out
 
 
+def utf16be_to_utf32le(data, cap: Optional[int] = None):
+    return utf16le_to_utf32le(_be_words(data), cap)
+
+
+def utf32le_to_utf16be(data, cap: Optional[int] = None):
+    """Returns (Result, out): out holds the UTF-16BE bytes as a uint16 array."""
+    r, out = utf32le_to_utf16le(data, cap)
+    return r, out.byteswap()
+
+
 def validate_utf8_fixed(buf: np.ndarray, length: int, want_arrays: bool = True):
     """Validate back-to-back strings of `length` bytes.  Returns (n_valid, status, count)."""
     a = _u8(buf)

@@ -151,6 +151,10 @@ def lib() -> ctypes.CDLL:
         "utfx_utf32le_to_utf16le": (CResult, [P, P, Z, P, Z]),
         "utfx_utf16le_to_utf32le_async": (I, [P, P, Z, P, Z, P]),
         "utfx_utf32le_to_utf16le_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_utf16be_to_utf32le": (CResult, [P, P, Z, P, Z]),
+        "utfx_utf32le_to_utf16be": (CResult, [P, P, Z, P, Z]),
+        "utfx_utf16be_to_utf32le_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_utf32le_to_utf16be_async": (I, [P, P, Z, P, Z, P]),
         "utfx_stream_init": (I, [ctypes.POINTER(CStream), I]),
         "utfx_stream_transcode": (CResult, [P, ctypes.POINTER(CStream), P, Z, P, Z, I]),
         "utfx_batch_run": (I, [P, P, Z, P, Z, P, U32, U64, P]),
@@ -423,6 +427,26 @@ class Context:
         p, n = _ptr_len(src, 4)
         q, cap = _ptr_len(dst, 2)
         return int(self._lib.utfx_utf32le_to_utf16le_async(self._h, p, n, q, cap, d_result.data_ptr()))
+
+    def utf16be_to_utf32le(self, src, dst) -> Result:
+        p, n = _ptr_len(src, 2)
+        q, cap = _ptr_len(dst, 4)
+        return _res(self._lib.utfx_utf16be_to_utf32le(self._h, p, n, q, cap))
+
+    def utf32le_to_utf16be(self, src, dst) -> Result:
+        p, n = _ptr_len(src, 4)
+        q, cap = _ptr_len(dst, 2)
+        return _res(self._lib.utfx_utf32le_to_utf16be(self._h, p, n, q, cap))
+
+    def utf16be_to_utf32le_async(self, src, dst, d_result) -> int:
+        p, n = _ptr_len(src, 2)
+        q, cap = _ptr_len(dst, 4)
+        return int(self._lib.utfx_utf16be_to_utf32le_async(self._h, p, n, q, cap, d_result.data_ptr()))
+
+    def utf32le_to_utf16be_async(self, src, dst, d_result) -> int:
+        p, n = _ptr_len(src, 4)
+        q, cap = _ptr_len(dst, 2)
+        return int(self._lib.utfx_utf32le_to_utf16be_async(self._h, p, n, q, cap, d_result.data_ptr()))
 
     # ---- streams
     def open_stream(self, fmt: int) -> "Stream":

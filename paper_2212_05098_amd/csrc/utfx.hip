@@ -633,6 +633,21 @@ utfx_status utfx_utf32le_to_utf16le_async(utfx_ctx* c, const uint32_t* in, size_
   return run(c, U32U16, in, n, out, cap, d_result);
 }
 
+utfx_result utfx_utf16be_to_utf32le(utfx_ctx* c, const uint16_t* in, size_t n, uint32_t* out, size_t cap) {
+  return run_sync(c, U16U32, in, n, out, cap, true);
+}
+utfx_result utfx_utf32le_to_utf16be(utfx_ctx* c, const uint32_t* in, size_t n, uint16_t* out, size_t cap) {
+  return run_sync(c, U32U16, in, n, out, cap, true);
+}
+utfx_status utfx_utf16be_to_utf32le_async(utfx_ctx* c, const uint16_t* in, size_t n, uint32_t* out, size_t cap,
+                                          utfx_result* d_result) {
+  return run(c, U16U32, in, n, out, cap, d_result, true);
+}
+utfx_status utfx_utf32le_to_utf16be_async(utfx_ctx* c, const uint32_t* in, size_t n, uint16_t* out, size_t cap,
+                                          utfx_result* d_result) {
+  return run(c, U32U16, in, n, out, cap, d_result, true);
+}
+
 utfx_status utfx_stream_init(utfx_stream* st, int format) {
   if (!st || format < UTFX_STREAM_UTF8_TO_UTF16LE || format > UTFX_STREAM_UTF16BE_TO_UTF8)
     return UTFX_E_INVALID_ARG;

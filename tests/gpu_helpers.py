@@ -186,7 +186,8 @@ def check_u32_to_u8(ctx, units, cap=None, in_shift=0, out_shift=0, guard=64):
     return r
 
 
-def check_u16_to_u32(ctx, words, cap=None, in_shift=0, out_shift=0, guard=32):
+def check_u16_to_u32(ctx, words, cap=None, in_shift=0, out_shift=0, guard=32, be=False):
+    """be: `words` is a UTF-16BE buffer (the uint16 array holding its bytes)."""
     import torch
 
     words = np.ascontiguousarray(words, dtype=np.uint16)
@@ -194,8 +195,9 @@ def check_u16_to_u32(ctx, words, cap=None, in_shift=0, out_shift=0, guard=32):
     src, _ = dev_u16(words, pad_front_words=in_shift)
     fill = 0x5A5A5A5A
     out_back = torch.full((out_shift + cap + guard,), fill, dtype=torch.int32, device="cuda")
-    r = ctx.utf16le_to_utf32le(src, out_back[out_shift:out_shift + cap])
-    want, ref = O.utf16le_to_utf32le(words, cap=cap)
+    fn = ctx.utf16be_to_utf32le if be else ctx.utf16le_to_utf32le
+    r = fn(src, out_back[out_shift:out_shift + cap])
+    want, ref = (O.utf16be_to_utf32le if be else O.utf16le_to_utf32le)(words, cap=cap)
     assert tuple(r) == tuple(want), (r, want)
     got = out_back.cpu().numpy().view(np.uint32)
     w = min(r.written, cap)
@@ -204,15 +206,17 @@ def check_u16_to_u32(ctx, words, cap=None, in_shift=0, out_shift=0, guard=32):
     return r
 
 
-def check_u32_to_u16(ctx, units, cap=None, in_shift=0, out_shift=0, guard=32):
+def check_u32_to_u16(ctx, units, cap=None, in_shift=0, out_shift=0, guard=32, be=False):
+    """be: the output is UTF-16BE (compared as the bytes in memory)."""
     import torch
 
     units = np.ascontiguousarray(units, dtype=np.uint32)
     cap = 2 * units.size if cap is None else cap
     src, _ = dev_u32(units, pad_front_units=in_shift)
     out_back = torch.full((out_shift + cap + guard,), 0x5A5A, dtype=torch.int16, device="cuda")
-    r = ctx.utf32le_to_utf16le(src, out_back[out_shift:out_shift + cap])
-    want, ref = O.utf32le_to_utf16le(units, cap=cap)
+    fn = ctx.utf32le_to_utf16be if be else ctx.utf32le_to_utf16le
+    r = fn(src, out_back[out_shift:out_shift + cap])
+    want, ref = (O.utf32le_to_utf16be if be else O.utf32le_to_utf16le)(units, cap=cap)
     assert tuple(r) == tuple(want), (r, want)
     got = host_u16(out_back)
     w = min(r.written, cap)

@@ -291,3 +291,26 @@ def test_utf16_utf32_full_size(ctx):
     note("utf32->utf16 full size")
     assert check_u32_to_u16(ctx, units).status == utfx.OK
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prof", ["emoji", "mixed4", "cjk"])
+def test_utf16be_utf32(ctx, prof):
+    """UTF-16BE <-> UTF-32LE: ragged sizes, injected unpaired surrogates (dense enough for
+    the rescan), misaligned pointers and small outputs, big-endian words on the UTF-16
+    side."""
+    rng = synth.rng_for(96, synth.PROFILE_IDS[prof])
+    for n in (1, 2, 17, 4097, 8193, 300_007):
+        note("utf16be<->utf32 %s n=%d" % (prof, n))
+        check_u16_to_u32(ctx, synth.utf16_buffer(prof, n, rng).byteswap(), be=True)
+        check_u32_to_u16(ctx, synth.utf32_buffer(prof, n, rng), be=True)
+    for rate in (1e-4, 3e-2):
+        inj = synth.inject_utf16(prof, 100_000, rate, rng)
+        note("utf16be->utf32 inject %s rate=%g" % (prof, rate))
+        r = check_u16_to_u32(ctx, inj.data.byteswap(), be=True)
+        assert r.status == utfx.E_SURROGATE and r.count == inj.positions[0]
+    words = synth.utf16_buffer(prof, 10_007, rng).byteswap()
+    units = synth.utf32_buffer(prof, 10_007, rng)
+    check_u16_to_u32(ctx, words, in_shift=3, out_shift=1, be=True)
+    check_u32_to_u16(ctx, units, in_shift=1, out_shift=3, be=True)
+    need = O.utf32le_to_utf16be(units)[0].count
+    assert check_u32_to_u16(ctx, units, cap=need - 1, be=True).status == utfx.E_OUTPUT_TOO_SMALL

@@ -208,6 +208,11 @@ def test_utf16_utf32_against_python_codecs():
     assert r == O.Result(O.OK, u32.size, u32.size) and np.array_equal(out[: r.written], u32)
     r, out = O.utf32le_to_utf16le(u32)
     assert r == O.Result(O.OK, u16.size, u16.size) and np.array_equal(out[: r.written], u16)
+    be = s.encode("utf-16-be")
+    r, out = O.utf32le_to_utf16be(u32)
+    assert r == O.Result(O.OK, u16.size, u16.size) and out[: r.written].tobytes() == be
+    r, out = O.utf16be_to_utf32le(np.frombuffer(be, dtype=np.uint16))
+    assert r == O.Result(O.OK, u32.size, u32.size) and np.array_equal(out[: r.written], u32)
     for L in range(1, 6):
         strs = _all_strings(ALPHA16, L).astype(np.uint16)
         for i in range(strs.shape[0]):
