@@ -1,0 +1,61 @@
+"""Host logic of the rocprofv3 summaries (CPU): the kernel-trace table and its per-input
+split, the traffic calibration against a copy kernel, and that a traffic summary taken
+from other kernel sources is not used."""
+import csv
+import os
+
+from paper_2212_05098_amd import profsum
+
+
+def _write(path, fields, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_stats_table_and_split(tmp_path):
+    rows, t = [], 0
+    for i in range(8):  # k_u8_to_u16 on inputs a, b alternating: 100 and 300 ns
+        d = 100 if i % 2 == 0 else 300
+        rows.append({"Kernel_Name": "void utfx_dev::k_u8_to_u16<512, 4>(Launch)", "Start_Timestamp": t,
+                     "End_Timestamp": t + d})
+        t += 1000
+    rows.append({"Kernel_Name": "k_other", "Start_Timestamp": t, "End_Timestamp": t + 400})
+    _write(str(tmp_path / "s" / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    text = profsum.stats_text(str(tmp_path / "s"), "cmd", cycle=["a", "b"])
+    lines = [l for l in text.splitlines() if not l.startswith("#")]
+    main = [l for l in lines if l.startswith("void k_u8_to_u16<512, 4>(Launch) ") and "[" not in l][0].split()
+    assert main[-5:] == ["8", "0.20", "0.10", "0.30", "80.00"]  # 1600 of 2000 ns
+    a = [l for l in lines if "[a]" in l][0].split()
+    b = [l for l in lines if "[b]" in l][0].split()
+    assert a[-5:-1] == ["4", "0.10", "0.10", "0.10"] and b[-5:-1] == ["4", "0.30", "0.30", "0.30"]
+    assert "# kernel sources: %s" % profsum.source_hash() in text
+
+
+def test_traffic_calibration_and_staleness(tmp_path):
+    fields = ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    copy = profsum.COPY_KERNEL
+    fetch = [{"Kernel_Name": copy, "Grid_Size": 1 << 20, "Counter_Name": "FETCH_SIZE", "Counter_Value": 131072.0},
+             {"Kernel_Name": copy, "Grid_Size": 64, "Counter_Name": "FETCH_SIZE", "Counter_Value": 1.0},
+             {"Kernel_Name": "k_u8_to_u16<512, 4>", "Grid_Size": 8192, "Counter_Name": "FETCH_SIZE",
+              "Counter_Value": 65536.0}]
+    write = [{"Kernel_Name": copy, "Grid_Size": 1 << 20, "Counter_Name": "WRITE_SIZE", "Counter_Value": 262144.0},
+             {"Kernel_Name": "k_u8_to_u16<512, 4>", "Grid_Size": 8192, "Counter_Name": "WRITE_SIZE",
+              "Counter_Value": 1024.0}]
+    _write(str(tmp_path / "f" / "run_counter_collection.csv"), fields, fetch)
+    _write(str(tmp_path / "w" / "run_counter_collection.csv"), fields, write)
+    text = profsum.traffic_text(str(tmp_path / "f"), str(tmp_path / "w"), "k_u8_to_u16", "case x", 256 << 20,
+                                "cf", "cw")
+    kv = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith("#"))
+    # a 256 MiB copy reads 131072 KiB (factor 2) and writes 262144 KiB (factor 1)
+    assert kv["fetch_factor"] == "2.0000" and kv["write_factor"] == "1.0000"
+    assert int(kv["read_bytes_per_launch"]) == 65536 * 1024 * 2 and int(kv["write_bytes_per_launch"]) == 1024 * 1024
+    p = tmp_path / "t.txt"
+    p.write_text(text)
+    assert profsum.read_traffic(str(p), "k_u8_to_u16", "case x") == 65536 * 2048 + 1024 * 1024
+    assert profsum.read_traffic(str(p), "k_u16_to_u8", "case x") is None
+    p.write_text(text.replace("kernel_sources: %s" % profsum.source_hash(), "kernel_sources: 0000000000000000"))
+    assert profsum.read_traffic(str(p), "k_u8_to_u16", "case x") is None
