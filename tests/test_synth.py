@@ -35,3 +35,25 @@ def test_config_buffers_exact_and_valid():
         w = synth.config_buffer(prof, synth.DIR_16TO8, 1 << 16, config=9)
         assert w.size == 1 << 15
         w.astype("<u2").tobytes().decode("utf-16-le")
+
+
+def test_stream_cuts_cover_the_buffer():
+    rng = synth.rng_for(5, 1)
+    for n, mx, mn in ((0, 3, 0), (1, 1, 0), (1000, 7, 0), (1000, 50, 1), (10 ** 6, 200_000, 1 << 10)):
+        cuts = synth.stream_cuts(n, rng, mx, min_chunk=mn)
+        assert cuts[0] == 0 and cuts[-1] == n
+        steps = np.diff(cuts)
+        assert np.all(steps >= 0) and np.all(steps <= mx)
+        assert np.all(steps[:-1] >= mn)
+
+
+def test_utf32_buffers_and_injection():
+    rng = synth.rng_for(5, 2)
+    for prof in synth.SCRIPT_PROFILES + ("mixed4",):
+        u = synth.utf32_buffer(prof, 5000, rng)
+        assert u.dtype == np.uint32 and u.size == 5000
+        u.astype("<u4").tobytes().decode("utf-32-le")  # every unit a scalar value
+        bad, pos = synth.inject_utf32(u, 1e-2, rng)
+        assert pos == sorted(pos) and len(pos) >= 1
+        assert np.array_equal(np.delete(bad, pos), np.delete(u, pos))
+        assert all((0xD800 <= bad[p] <= 0xDFFF) or bad[p] > 0x10FFFF for p in pos)
