@@ -32,12 +32,17 @@ COPY_KERNEL = "copyBuffer"
 
 
 def source_hash() -> str:
+    """Hash of what decides the profiled kernels: their sources, the compiler flags and
+    the tuning cache that picks their launch shapes."""
+    from . import build as B
+
     h = hashlib.sha256()
-    for rel in SOURCES:
+    for rel in SOURCES + ("tune_cache.json",):
         p = os.path.join(HERE, rel)
         if os.path.exists(p):
             with open(p, "rb") as f:
                 h.update(rel.encode() + b"\0" + f.read())
+    h.update(b"flags\0" + " ".join(B.HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
