@@ -38,8 +38,8 @@ def _dev(data, in16):
     import torch
 
     if in16:
-        return torch.from_numpy(np.ascontiguousarray(data, dtype=np.uint16).view(np.int16)).cuda()
-    return torch.from_numpy(np.ascontiguousarray(data, dtype=np.uint8)).cuda()
+        return torch.from_numpy(np.array(data, dtype=np.uint16).view(np.int16)).cuda()
+    return torch.from_numpy(np.array(data, dtype=np.uint8)).cuda()
 
 
 def run_stream(ctx, fmt, data, cuts, check_prefixes=True):
