@@ -99,3 +99,27 @@ def test_tune_cache_round_trip(tmp_path):
     tune.save(cache, p)
     assert tune.load(p) == cache
     assert tune.load(str(tmp_path / "missing.json")) is None
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/utfx.h compiles as strict C99 and its structs have the sizes and offsets
+    the library and the binding assume."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(B.LIB), "..", "include")
+    src = tmp_path / "h.c"
+    src.write_text(
+        '#include <stddef.h>\n#include "utfx.h"\n'
+        "int main(void) {\n"
+        "  return !(sizeof(utfx_result) == 24 && offsetof(utfx_result, count) == 8 &&\n"
+        "           sizeof(utfx_stream) == 48 && offsetof(utfx_stream, carry) == 40 &&\n"
+        "           offsetof(utfx_stream, carry_need) == 44 && sizeof(utfx_item) == 40);\n"
+        "}\n")
+    exe = tmp_path / "h"
+    subprocess.check_call([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc, str(src), "-o",
+                           str(exe)])
+    assert subprocess.run([str(exe)]).returncode == 0
