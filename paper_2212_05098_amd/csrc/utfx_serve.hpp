@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "utfx.h"
+#include "utfx_serve_policy.hpp"
 
 namespace utfx_srv {
 
@@ -77,8 +78,6 @@ inline uint64_t now_ns() {
   clock_gettime(CLOCK_MONOTONIC, &ts);
   return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
-
-inline uint64_t al16(uint64_t x) { return (x + 15) & ~15ull; }
 
 }  // namespace utfx_srv
 
@@ -152,42 +151,27 @@ inline uint64_t out_bytes(const Req& r) { return r.out_cap * (r.dir ? 1 : 2); }
 // with UTFX_E_INVALID_ARG on the next progress call).
 inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bulk, utfx_status* st) {
   const utfx_server_config& c = S->cfg;
-  // staged data grows from the start of each arena, direct data from its end
-  uint64_t in_lo = 0, out_lo = 0, in_hi = c.arena_in_bytes, out_hi = c.arena_out_bytes, units = 0;
+  StepPacker pk(PackLimits{c.arena_in_bytes, c.arena_out_bytes, c.max_items, kDirectMin});
+  uint64_t units = 0;
   s.reqs.clear();
   s.direct_out.clear();
   s.direct_in_off.clear();
   s.direct_out_off.clear();
   std::vector<uint32_t> direct_in_idx;
-  while (!q.empty() && s.reqs.size() < c.max_items) {
+  while (!q.empty()) {
     const Req& r = q.front();
-    if (r.dir > 1 || in_bytes(r) > c.arena_in_bytes || out_bytes(r) > c.arena_out_bytes) {
+    const ReqShape sh{in_bytes(r), out_bytes(r), r.dir, in_bytes(r) >= kDirectMin && is_pinned(r.data),
+                      out_bytes(r) >= kDirectMin && is_pinned(r.out)};
+    Placement pl;
+    const PackVerdict v = pk.place(sh, &pl);
+    if (v == PACK_REJECT) {
       S->rejected.push_back(r.tag);
       q.pop_front();
       continue;
     }
-    const bool din = in_bytes(r) >= kDirectMin && is_pinned(r.data);
-    const bool dout = out_bytes(r) >= kDirectMin && is_pinned(r.out);
-    uint64_t io, oo, nlo = in_lo, nhi = in_hi, olo = out_lo, ohi = out_hi;
-    if (din) {
-      if (in_bytes(r) > nhi) break;
-      io = nhi = (nhi - in_bytes(r)) & ~15ull;
-    } else {
-      io = al16(nlo);
-      nlo = io + in_bytes(r);
-    }
-    if (dout) {
-      if (out_bytes(r) > ohi) break;
-      oo = ohi = (ohi - out_bytes(r)) & ~15ull;
-    } else {
-      oo = al16(olo);
-      olo = oo + out_bytes(r);
-    }
-    if (nlo > nhi || olo > ohi) break;  // no room left in this step
-    in_lo = nlo;
-    in_hi = nhi;
-    out_lo = olo;
-    out_hi = ohi;
+    if (v == PACK_FULL) break;  // no room left in this step
+    const uint64_t io = pl.in_off, oo = pl.out_off;
+    const bool din = pl.direct_in, dout = pl.direct_out;
     if (din) direct_in_idx.push_back((uint32_t)s.reqs.size());
     else if (in_bytes(r)) memcpy(s.h_in + io, r.data, in_bytes(r));
     utfx_item& it = s.h_items[s.reqs.size()];
@@ -205,6 +189,7 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
   const uint32_t n = (uint32_t)s.reqs.size();
   if (!n) return 0;
   hipError_t e = hipMemcpyAsync(s.d_items, s.h_items, n * sizeof(utfx_item), hipMemcpyHostToDevice, s.stream);
+  const uint64_t in_lo = pk.staged_in_bytes(), out_lo = pk.staged_out_bytes();
   if (e == hipSuccess && in_lo) e = hipMemcpyAsync(s.d_in, s.h_in, in_lo, hipMemcpyHostToDevice, s.stream);
   for (uint32_t k : direct_in_idx) {
     if (e != hipSuccess) break;
@@ -336,10 +321,11 @@ utfx_status utfx_server_progress(utfx_server* S, utfx_completion* done, uint32_t
   for (auto& s : S->slots) bulk_busy |= s.busy && s.bulk;
   for (auto& s : S->slots) {
     if (s.busy) continue;
-    if (!S->pending_bulk.empty() && (!bulk_busy || S->pending.empty())) {
+    const int which = pick_queue(!S->pending_bulk.empty(), !S->pending.empty(), bulk_busy);
+    if (which == 1) {
       launch_step(S, s, S->pending_bulk, true, &st);
       bulk_busy = true;
-    } else if (!S->pending.empty()) {
+    } else if (which == 0) {
       launch_step(S, s, S->pending, false, &st);
     } else {
       continue;
