@@ -215,6 +215,27 @@ def utf16_error_item(kind: str, rng: np.random.Generator) -> List[int]:
     raise ValueError(kind)
 
 
+def _utf8_units(cps: np.ndarray) -> np.ndarray:
+    """Bytes per character of the drawn code points (their UTF-8 lengths), used only to
+    decide which characters lie inside the buffer."""
+    c = cps.astype(np.int64)
+    return 1 + (c >= 0x80) + (c >= 0x800) + (c >= 0x10000)
+
+
+def _error_slots(units: np.ndarray, n_units: int, n_err: int, rng: np.random.Generator) -> np.ndarray:
+    """Indices of the characters an injection replaces: n_err drawn uniformly without
+    replacement among the characters that end inside the buffer with room to spare for
+    the items (at most 4 units each), ascending."""
+    if n_err == 0:
+        return np.zeros(0, np.int64)
+    ends = np.cumsum(units)
+    room = n_units - 4 * n_err
+    m = int(np.searchsorted(ends, room, side="right")) if room > 0 else 0
+    if m == 0:
+        m = 1  # a buffer too short for the room: the first character, trimmed later
+    return np.sort(rng.choice(m, size=min(n_err, m), replace=False))
+
+
 @dataclass
 class Injected:
     data: np.ndarray          # uint8 (UTF-8) or uint16 (UTF-16) input
@@ -231,7 +252,7 @@ def inject_utf8(profile: str, n_bytes: int, rate: float, rng: np.random.Generato
     k = int(n_bytes / bpc * 1.05) + 64
     cps = draw_codepoints(profile, k, rng)
     n_err = max(1, int(round(rate * n_bytes))) if rate > 0 else 0
-    at = np.sort(rng.choice(k, size=min(n_err, k), replace=False)) if n_err else np.zeros(0, np.int64)
+    at = _error_slots(_utf8_units(cps), n_bytes, n_err, rng)
     parts: List[bytes] = []
     pos: List[int] = []
     knd: List[str] = []
@@ -271,7 +292,7 @@ def inject_utf16(profile: str, n_words: int, rate: float, rng: np.random.Generat
     k = int(2 * n_words / bpc * 1.05) + 64
     cps = draw_codepoints(profile, k, rng)
     n_err = max(1, int(round(rate * n_words))) if rate > 0 else 0
-    at = np.sort(rng.choice(k, size=min(n_err, k), replace=False)) if n_err else np.zeros(0, np.int64)
+    at = _error_slots(1 + (cps >= 0x10000).astype(np.int64), n_words, n_err, rng)
     parts: List[np.ndarray] = []
     pos: List[int] = []
     knd: List[str] = []

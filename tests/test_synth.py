@@ -57,3 +57,49 @@ def test_utf32_buffers_and_injection():
         assert pos == sorted(pos) and len(pos) >= 1
         assert np.array_equal(np.delete(bad, pos), np.delete(u, pos))
         assert all((0xD800 <= bad[p] <= 0xDFFF) or bad[p] > 0x10FFFF for p in pos)
+
+
+def test_batch_injection_lands_in_every_flagged_string():
+    """Every string the batch generator flags carries its error at the recorded offset,
+    short strings included (log-normal lengths, median 256 B: a quarter are under
+    90 B), and the number of erroring strings is binomial(n, err_frac)."""
+    import oracle as O
+
+    n, frac = 20000, 0.05
+    b = synth.make_batch(n, seed_key=(0, 4, 99), median=256, sigma=2.0, hi=64 << 10, err_frac=frac)
+    flagged = np.nonzero(b.err_pos >= 0)[0]
+    mean, sd = n * frac, (n * frac * (1 - frac)) ** 0.5
+    assert abs(flagged.size - mean) < 4 * sd, flagged.size
+    for i in flagged:
+        a, L = int(b.in_off[i]), int(b.in_len[i])
+        if b.direction[i] == 0:
+            r = O.validate_utf8(b.arena[a:a + L])
+        else:
+            r = O.validate_utf16le(b.arena[a:a + 2 * L].view(np.uint16))
+        assert r.status != O.OK and r.count == b.err_pos[i], (i, L, r, b.err_pos[i])
+    # unflagged strings are valid
+    for i in np.nonzero(b.err_pos < 0)[0][:2000]:
+        a, L = int(b.in_off[i]), int(b.in_len[i])
+        if b.direction[i] == 0:
+            assert O.validate_utf8(b.arena[a:a + L]).status == O.OK
+        else:
+            assert O.validate_utf16le(b.arena[a:a + 2 * L].view(np.uint16)).status == O.OK
+
+
+@pytest.mark.parametrize("direction", [synth.DIR_8TO16, synth.DIR_16TO8])
+def test_single_injection_in_short_buffers(direction):
+    """One injected error per buffer of 8..300 units always lands inside it."""
+    import oracle as O
+
+    rng = synth.rng_for(6, direction)
+    for L in list(range(8, 64)) + [100, 255, 256, 300]:
+        for prof in synth.SCRIPT_PROFILES:
+            if direction == synth.DIR_8TO16:
+                inj = synth.inject_utf8(prof, L, 1.0 / L, rng)
+                assert inj.data.size == L
+                r = O.validate_utf8(inj.data)
+            else:
+                inj = synth.inject_utf16(prof, L, 1.0 / L, rng)
+                assert inj.data.size == L
+                r = O.validate_utf16le(inj.data)
+            assert inj.positions.size == 1 and r.status != O.OK and r.count == inj.positions[0], (L, prof, r)
