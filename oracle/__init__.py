@@ -63,15 +63,30 @@ class Result(NamedTuple):
     written: int
 
 
-def build(force: bool = False) -> str:
-    """Compile utf_oracle.c into liboracle_utf.so next to it (gcc, -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC]
-        )
-        os.replace(tmp, _LIB)
-    return _LIB
+_TIMING_SRC = os.path.join(_HERE, "oracle_timing.c")
+_HDR = os.path.join(_HERE, "utf_oracle.h")
+
+
+def build(force: bool = False, sanitize: bool = False, lib_path: Optional[str] = None) -> str:
+    """Compile utf_oracle.c (strict C99) and the timing harness oracle_timing.c into
+    liboracle_utf.so next to them (gcc, -O2).  sanitize builds a separate copy with
+    AddressSanitizer and UndefinedBehaviorSanitizer (host code only) at lib_path."""
+    out = lib_path or _LIB
+    srcs = (_SRC, _TIMING_SRC, _HDR)
+    if force or sanitize or not os.path.exists(out) or any(os.path.getmtime(out) < os.path.getmtime(s) for s in srcs):
+        tmp = out + ".tmp%d" % os.getpid()
+        san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=all"] if sanitize else []
+        objs = []
+        for src, std in ((_SRC, "-std=c99"), (_TIMING_SRC, "-std=gnu99")):
+            obj = tmp + "." + os.path.basename(src) + ".o"
+            subprocess.check_call(["gcc", "-O2", std, "-Wall", "-Wextra", "-fPIC", "-pthread"] + san +
+                                  ["-c", "-o", obj, src])
+            objs.append(obj)
+        subprocess.check_call(["gcc", "-shared", "-pthread"] + san + ["-o", tmp] + objs)
+        for o in objs:
+            os.remove(o)
+        os.replace(tmp, out)
+    return out
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -104,6 +119,13 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.argtypes = [p8, sz, sz, p8, p8]
             fn.restype = ctypes.c_uint64
+        L.utfx_ref_batch.argtypes = [p8, sz, p8, sz, p8, sz, p8]
+        L.utfx_ref_batch.restype = ctypes.c_uint64
+        ci = ctypes.c_int
+        L.utfx_ref_time_buffer.argtypes = [ci, p8, sz, p8, sz, ci, ci, p8, p8, p8, p8, p8]
+        L.utfx_ref_time_buffer.restype = ci
+        L.utfx_ref_time_batch.argtypes = [p8, sz, p8, sz, p8, sz, p8, ci, ci, p8, p8, p8]
+        L.utfx_ref_time_batch.restype = ci
         _lib = L
     return _lib
 
@@ -287,6 +309,96 @@ def validate_utf16le_fixed(buf: np.ndarray, length: int, want_arrays: bool = Tru
         _ptr(a), n, length, _ptr(st) if want_arrays else None, _ptr(ct) if want_arrays else None
     )
     return int(nv), st, ct
+
+
+# ---- batches: each item is the single-string call on its bytes --------------------
+
+ITEM_DTYPE = np.dtype([("in_off", "<u8"), ("in_len", "<u8"), ("out_off", "<u8"), ("out_cap", "<u8"),
+                       ("dir", "<u4"), ("pad", "<u4")])
+RESULT_DTYPE = np.dtype([("status", "<i4"), ("reserved", "<u4"), ("count", "<u8"), ("written", "<u8")])
+
+
+def items_array(in_off, in_len, out_off, out_cap, dirs) -> np.ndarray:
+    """A structured array of batch items (the oracle's own copy of the layout)."""
+    n = len(in_off)
+    it = np.zeros(n, dtype=ITEM_DTYPE)
+    it["in_off"], it["in_len"], it["out_off"], it["out_cap"], it["dir"] = in_off, in_len, out_off, out_cap, dirs
+    return it
+
+
+def batch(in_arena: np.ndarray, items: np.ndarray, out_bytes: int):
+    """Runs every item (dir 0: UTF-8 -> UTF-16LE, 1: UTF-16LE -> UTF-8) on its bytes.
+    Returns (results, out_arena, n_ok): a RESULT_DTYPE array, the uint8 output arena of
+    out_bytes bytes (zero outside what the items stored) and the number of OK items."""
+    a = _u8(in_arena)
+    items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+    res = np.zeros(items.size, dtype=RESULT_DTYPE)
+    out = np.zeros(int(out_bytes), dtype=np.uint8)
+    ok = lib().utfx_ref_batch(_ptr(a), a.size, _ptr(out), out.size, _ptr(items), items.size, _ptr(res))
+    return res, out, int(ok)
+
+
+# ---- timing harness of the CPU baseline (oracle_timing.c) --------------------------
+
+TIME_U8_TO_U16, TIME_U16_TO_U8, TIME_VALIDATE_U8, TIME_VALIDATE_U16 = 0, 1, 2, 3
+
+
+class Timing(NamedTuple):
+    seconds: float            # fastest repetition
+    threads: int
+    result: Result            # combined over the pieces
+    out: Optional[np.ndarray]  # transcodes: the pieces' outputs joined in order
+
+
+def time_buffer(op: int, data, threads: int = 1, reps: int = 3) -> Timing:
+    """Fastest of `reps` runs (after one warm-up run) of one oracle operation over the
+    buffer on `threads` pinned threads (0 = every CPU of the affinity mask), the input
+    cut at character boundaries; steady clock inside C."""
+    in16 = op in (TIME_U16_TO_U8, TIME_VALIDATE_U16)
+    a = _u16(data) if in16 else _u8(data)
+    n = a.size
+    if op == TIME_U8_TO_U16:
+        out = np.zeros(max(n, 1), dtype=np.uint16)
+    elif op == TIME_U16_TO_U8:
+        out = np.zeros(max(3 * n, 1), dtype=np.uint8)
+    else:
+        out = None
+    ns = ctypes.c_uint64()
+    r = _CResult()
+    used = ctypes.c_int()
+    lo = np.zeros(256, dtype=np.uint64)
+    wr = np.zeros(256, dtype=np.uint64)
+    rc = lib().utfx_ref_time_buffer(op, _ptr(a), n, None if out is None else out.ctypes.data,
+                                    0 if out is None else (n if op == TIME_U8_TO_U16 else 3 * n), threads, reps,
+                                    ctypes.byref(ns), ctypes.byref(r), ctypes.byref(used), lo.ctypes.data,
+                                    wr.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad timing arguments")
+    joined = None
+    if out is not None:
+        scale = 1 if op == TIME_U8_TO_U16 else 3
+        # pieces after the first erroring one are not part of the result
+        joined = np.concatenate([out[scale * int(lo[k]):scale * int(lo[k]) + int(wr[k])]
+                                 for k in range(used.value)])[: r.written] if n else out[:0]
+    return Timing(ns.value * 1e-9, used.value, _res(r), joined)
+
+
+def time_batch(in_arena: np.ndarray, items: np.ndarray, out_bytes: int, threads: int = 1, reps: int = 3):
+    """Fastest of `reps` runs (after a warm-up) of the batched reference over the items,
+    split into runs of consecutive items of about equal bytes over `threads` pinned
+    threads.  Returns (seconds, threads_used, results, n_ok)."""
+    a = _u8(in_arena)
+    items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+    res = np.zeros(items.size, dtype=RESULT_DTYPE)
+    out = np.zeros(int(out_bytes), dtype=np.uint8)
+    ns = ctypes.c_uint64()
+    used = ctypes.c_int()
+    ok = ctypes.c_uint64()
+    rc = lib().utfx_ref_time_batch(_ptr(a), a.size, _ptr(out), out.size, _ptr(items), items.size, _ptr(res),
+                                   threads, reps, ctypes.byref(ns), ctypes.byref(used), ctypes.byref(ok))
+    if rc != 0:
+        raise ValueError("bad timing arguments")
+    return ns.value * 1e-9, used.value, res, int(ok.value)
 
 
 # Exposed for the header-consistency test only.

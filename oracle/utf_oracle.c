@@ -350,3 +350,30 @@ uint64_t utfx_ref_validate_utf16le_fixed(const uint16_t *buf, size_t n_strings, 
   }
   return valid;
 }
+
+/* ---- batched reference: every item is the single-string call on its bytes ------- */
+
+uint64_t utfx_ref_batch(const uint8_t *in_arena, size_t in_bytes, uint8_t *out_arena, size_t out_bytes,
+                        const utfx_ref_item *items, size_t n_items, utfx_ref_result *results) {
+  uint64_t ok = 0;
+  for (size_t i = 0; i < n_items; i++) {
+    const utfx_ref_item it = items[i];
+    const uint64_t in_unit = it.dir == 1 ? 2 : 1, out_unit = it.dir == 1 ? 1 : 2;
+    int bad = it.dir > 1;
+    if (!bad) bad = it.in_off > in_bytes || it.in_len > (in_bytes - it.in_off) / in_unit;
+    if (!bad) bad = it.out_off > out_bytes || it.out_cap > (out_bytes - it.out_off) / out_unit;
+    if (!bad) bad = (it.dir == 1 && (it.in_off & 1)) || (it.dir == 0 && (it.out_off & 1));
+    if (bad) {
+      results[i] = mk(UTFX_REF_E_INVALID_ARG, 0, 0);
+      continue;
+    }
+    if (it.dir == 0)
+      results[i] = utfx_ref_utf8_to_utf16le(in_arena + it.in_off, it.in_len,
+                                            (uint16_t *)(void *)(out_arena + it.out_off), it.out_cap);
+    else
+      results[i] = utfx_ref_utf16le_to_utf8((const uint16_t *)(const void *)(in_arena + it.in_off), it.in_len,
+                                            out_arena + it.out_off, it.out_cap);
+    if (results[i].status == UTFX_REF_OK) ok++;
+  }
+  return ok;
+}

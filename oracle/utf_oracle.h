@@ -89,6 +89,25 @@ uint64_t utfx_ref_validate_utf8_fixed(const uint8_t *buf, size_t n_strings, size
 uint64_t utfx_ref_validate_utf16le_fixed(const uint16_t *buf, size_t n_strings, size_t len,
                                          int32_t *status, uint64_t *count);
 
+/* Batched reference (the invariant a batched call must meet: each string gets the
+ * result of the single-string call on its bytes).  One item per string, with byte
+ * offsets into the arenas, the input length in input units, the output room in output
+ * units and the direction: 0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8.  An item whose
+ * direction is above 1, whose UTF-16 side starts at an odd offset, or whose input or
+ * output slot is not inside its arena gets UTFX_REF_E_INVALID_ARG.  Otherwise results[i]
+ * is the single-string transcode of the item and its output is stored at out_off.
+ * Returns the number of items with status OK. */
+typedef struct {
+  uint64_t in_off;
+  uint64_t in_len;
+  uint64_t out_off;
+  uint64_t out_cap;
+  uint32_t dir;
+  uint32_t pad;
+} utfx_ref_item;
+uint64_t utfx_ref_batch(const uint8_t *in_arena, size_t in_bytes, uint8_t *out_arena, size_t out_bytes,
+                        const utfx_ref_item *items, size_t n_items, utfx_ref_result *results);
+
 #ifdef __cplusplus
 }
 #endif

@@ -513,3 +513,112 @@ def test_reading_surrogate_join_constant():
     cps = np.frombuffer(pairs.encode("utf-32-le"), dtype="<u4")
     assert np.array_equal(joined.astype(np.uint32), cps)
     assert (-(0xD7C0 << 10) - 0xDC00) % (1 << 32) == 0xFCA02400
+
+
+# ------------------------------------------------------------------ length query on invalid input
+
+def test_length_query_closed_forms_on_single_units():
+    """Reading c9 on every single unit, valid or not.  Over the 256 bytes, Table 1
+    gives 128 ASCII bytes (one word each), 64 continuation bytes (none), 32 bytes
+    C0..DF and 16 bytes E0..EF (one word each: their characters stay in the BMP) and
+    16 bytes F0..FF (two words: a 4-byte character is a surrogate pair, section 6.2):
+    128 + 32 + 16 + 2 * 16 = 208.  Over the 65,536 words: 128 below U+0080 (1 byte),
+    1,920 below U+0800 (2), 2,048 surrogates (2 each: a pair is 4 bytes, section 7.3)
+    and the other 61,440 (3): 192,384."""
+    b = np.arange(256, dtype=np.uint8)
+    assert O.utf16_length_from_utf8(b) == O.Result(O.OK, 208, 208)
+    w = np.arange(65536, dtype=np.uint16)
+    assert O.utf8_length_from_utf16le(w) == O.Result(O.OK, 192384, 192384)
+    # per unit: a lead byte counts the UTF-16 length of its characters (from CPython's
+    # encoder, on the smallest valid character with that lead), a continuation byte 0
+    for v in range(256):
+        got = O.utf16_length_from_utf8(bytes([v])).count
+        if 0x80 <= v <= 0xBF:
+            assert got == 0, v
+            continue
+        ch = None
+        for tail in ([], [0x80], [0x80, 0x80], [0x80, 0x80, 0x80], [0xA0, 0x80], [0x90, 0x80, 0x80]):
+            try:
+                ch = bytes([v] + tail).decode("utf-8")
+                break
+            except UnicodeDecodeError:
+                continue
+        if ch is not None and len(ch) == 1:
+            assert got == len(ch.encode("utf-16-le")) // 2, v
+        else:  # never valid: C0, C1 count as 2-byte leads, F5..FF as 4-byte leads
+            assert v in (0xC0, 0xC1) or v >= 0xF5, v
+            assert got == (1 if v < 0xF0 else 2), v
+    for v in (0x41, 0x7FF, 0x800, 0xD7FF, 0xD800, 0xDBFF, 0xDC00, 0xDFFF, 0xE000, 0xFFFF):
+        got = O.utf8_length_from_utf16le(np.array([v], dtype=np.uint16)).count
+        if 0xD800 <= v <= 0xDFFF:
+            assert got == 2  # half of a 4-byte character
+        else:
+            assert got == len(chr(v).encode("utf-8")), hex(v)
+
+
+# ------------------------------------------------------------------ batched reference, timing harness
+
+def test_batch_reference_is_the_single_call_per_item():
+    rng = synth.rng_for(31, 1)
+    b = synth.make_batch(400, seed_key=(31, 2), median=200, sigma=1.5, hi=20000, err_frac=0.2)
+    need = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
+    caps = need.copy()
+    caps[::7] //= 2  # some outputs too small
+    unit = np.where(b.direction == 0, 2, 1).astype(np.uint64)
+    out_off = np.concatenate([[0], np.cumsum(caps * unit + 8)[:-1]]).astype(np.uint64)
+    out_off += out_off % 2
+    dirs = b.direction.copy()
+    dirs[5] = 2  # bad direction
+    in_off = b.in_off.copy()
+    odd = int(np.nonzero(b.direction == 1)[0][0])
+    in_off[odd] += 1  # UTF-16 input at an odd offset
+    out_bytes = int(out_off[-1] + caps[-1] * unit[-1] + 8)
+    items = O.items_array(in_off, b.in_len, out_off, caps, dirs)
+    res, out, n_ok = O.batch(b.arena, items, out_bytes)
+    assert n_ok == int(np.sum(res["status"] == O.OK))
+    for i in range(len(items)):
+        if i in (5, odd):
+            assert res["status"][i] == O.E_INVALID_ARG
+            continue
+        a, L, o, cap = int(in_off[i]), int(b.in_len[i]), int(out_off[i]), int(caps[i])
+        if dirs[i] == 0:
+            want, ref = O.utf8_to_utf16le(b.arena[a:a + L], cap=cap)
+            got = out[o:o + 2 * min(want.written, cap)].view(np.uint16)
+        else:
+            want, ref = O.utf16le_to_utf8(b.arena[a:a + 2 * L].view(np.uint16), cap=cap)
+            got = out[o:o + min(want.written, cap)]
+        assert (int(res["status"][i]), int(res["count"][i]), int(res["written"][i])) == tuple(want)
+        assert np.array_equal(got, ref[:min(want.written, cap)])
+    # slots past the arena are refused
+    bad = O.items_array([0], [len(b.arena) + 1], [0], [4], [0])
+    r, _, _ = O.batch(b.arena, bad, 64)
+    assert r["status"][0] == O.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 7, 16])
+def test_timing_harness_split_matches_one_thread(threads):
+    """The CPU baseline's multi-thread split (cuts at character boundaries, results
+    combined by the first erroring piece) reproduces the single-call result and output,
+    on valid text, on error-dense text and on unpaired surrogates at the cuts."""
+    rng = synth.rng_for(32, threads)
+    cases8 = [synth.utf8_buffer("mixed4", 100_003, rng),
+              synth.inject_utf8("cjk", 50_000, 1e-3, rng).data,
+              rng.choice(np.array(ALPHA8, dtype=np.uint8), size=3001)]
+    for d in cases8:
+        for op in (O.TIME_U8_TO_U16, O.TIME_VALIDATE_U8):
+            t = O.time_buffer(op, d, threads=threads, reps=1)
+            if op == O.TIME_U8_TO_U16:
+                want, ref = O.utf8_to_utf16le(d)
+                assert t.result == want, (t.result, want)
+                assert np.array_equal(t.out, ref[:want.written])
+            else:
+                assert t.result == O.validate_utf8(d)
+    cases16 = [synth.utf16_buffer("emoji", 60_001, rng),
+               synth.inject_utf16("emoji", 40_000, 1e-3, rng).data,
+               rng.choice(np.array(ALPHA16, dtype=np.uint16), size=2001)]
+    for w in cases16:
+        t = O.time_buffer(O.TIME_U16_TO_U8, w, threads=threads, reps=1)
+        want, ref = O.utf16le_to_utf8(w)
+        assert t.result == want, (t.result, want)
+        assert np.array_equal(t.out, ref[:want.written])
+        assert O.time_buffer(O.TIME_VALIDATE_U16, w, threads=threads, reps=1).result == O.validate_utf16le(w)
