@@ -92,6 +92,14 @@ void utfx_destroy(utfx_ctx *ctx);
 const char *utfx_last_error(const utfx_ctx *ctx);
 /* Rebinds the context to another stream (work already queued stays where it is). */
 utfx_status utfx_set_stream(utfx_ctx *ctx, void *hip_stream);
+/* Kernel timing.  While set, every single-buffer call on the context records
+ * start_event (a hipEvent_t) on its stream immediately before its main kernel and
+ * stop_event immediately after it (hipExtLaunchKernel), so that hipEventElapsedTime
+ * gives that kernel's own duration, without the finalisation kernel and the gaps
+ * between launches.  NULL, NULL switches it off; nothing is recorded while capturing
+ * a graph.  UTFX_E_INVALID_ARG if only one of the two is NULL.  The events stay owned
+ * by the caller and must outlive their use. */
+utfx_status utfx_set_kernel_events(utfx_ctx *ctx, void *start_event, void *stop_event);
 
 /* Tunables of one operation, picked by the autotuner.  op is a utfx_op.
  * tile_bytes: input bytes one workgroup handles per step (4096 or 8192: 16 bytes per
@@ -325,7 +333,11 @@ utfx_status utfx_batch_run(utfx_ctx *ctx, const uint8_t *in_arena, size_t in_byt
  * while capturing (UTFX_E_INVALID_ARG): synchronous calls, and calls whose workspace
  * would have to grow -- make each call once eagerly first.  Launch a graph on any
  * stream; replays of graphs made on one context must not overlap in time.  One graph
- * per capture; utfx_graph_destroy frees it (the context must outlive its graphs). */
+ * per capture; utfx_graph_destroy frees it (the context must outlive its graphs).
+ * A graph holds the addresses of the context's workspace: once an eager call on the
+ * context has grown (reallocated) the workspace, utfx_graph_launch refuses that graph
+ * with UTFX_E_INVALID_ARG instead of replaying kernels on freed memory; capture it
+ * again. */
 typedef struct utfx_graph utfx_graph;
 utfx_status utfx_capture_begin(utfx_ctx *ctx);
 utfx_status utfx_capture_end(utfx_ctx *ctx, utfx_graph **graph);
@@ -348,7 +360,9 @@ void utfx_graph_destroy(utfx_graph *graph);
  * payload or output buffer is pinned host memory skip the staging copy: that data
  * moves by DMA straight between the buffer and the device (a direct output is copied
  * whole, so out[written:out_cap] then holds unspecified values).  A request larger than an arena
- * completes with UTFX_E_INVALID_ARG.  Payloads and outputs must stay valid until the
+ * completes with UTFX_E_INVALID_ARG; the requests of a step that could not be launched
+ * (a failed copy or batched call) complete with UTFX_E_DEVICE and
+ * utfx_server_last_error() holds the reason.  Payloads and outputs must stay valid until the
  * request completes.  Single-threaded: one thread drives a server. */
 typedef struct utfx_server utfx_server;
 typedef struct {

@@ -119,6 +119,7 @@ def lib() -> ctypes.CDLL:
         "utfx_destroy": (None, [P]),
         "utfx_last_error": (ctypes.c_char_p, [P]),
         "utfx_set_stream": (I, [P, P]),
+        "utfx_set_kernel_events": (I, [P, P, P]),
         "utfx_set_tuning": (I, [P, I, U32, U32, U32]),
         "utfx_get_tuning": (I, [P, I, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32)]),
         "utfx_utf16_length_from_utf8": (CResult, [P, P, Z]),
@@ -236,6 +237,19 @@ class Context:
 
     def last_error(self) -> str:
         return (self._lib.utfx_last_error(self._h) or b"").decode()
+
+    def set_kernel_events(self, start=None, stop=None):
+        """Record two torch.cuda.Event objects (enable_timing=True) around the main
+        kernel of every following single-buffer call; None, None switches it off.
+        start.elapsed_time(stop) is then that kernel's own duration in ms."""
+        for e in (start, stop):
+            if e is not None and not e.cuda_event:
+                e.record()  # torch creates its events lazily, on the first record
+        a = ctypes.c_void_p(start.cuda_event) if start is not None else None
+        b = ctypes.c_void_p(stop.cuda_event) if stop is not None else None
+        st = self._lib.utfx_set_kernel_events(self._h, a, b)
+        if st != OK:
+            raise UtfxError("utfx_set_kernel_events: status %d" % st)
 
     def set_tuning(self, op: int, tile_bytes: int, tiles_per_segment: int = 8, wgs_per_cu=None):
         """wgs_per_cu None keeps the current value."""

@@ -6,6 +6,7 @@
 // context's stream and, for the synchronous entry points, copies the 24-byte result
 // back.  Kernels reset the workspace counters themselves (the last workgroup of every
 // launch does it), so no call issues a memset and launches can be graph-captured.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -52,6 +53,11 @@ struct utfx_ctx {
   hipStream_t cap_stream = nullptr;
   uint64_t cap_launches = 0;              // single-buffer launches recorded so far
   uint64_t cap_batches = 0;               // batched calls recorded so far
+  // generation of the workspace memory: bumped whenever the single-buffer or the
+  // batch workspace is reallocated, so that a graph holding the old addresses is refused
+  uint64_t ws_gen = 0;
+  hipEvent_t kev_start = nullptr;         // kernel timing events (utfx_set_kernel_events)
+  hipEvent_t kev_stop = nullptr;
   char err[256];
 };
 
@@ -61,6 +67,7 @@ struct utfx_graph {
   hipGraphExec_t exec = nullptr;
   uint64_t launches = 0;                  // single-buffer launches per replay
   uint64_t batches = 0;                   // batched calls per replay
+  uint64_t ws_gen = 0;                    // workspace generation the kernels' addresses belong to
 };
 
 namespace {
@@ -113,6 +120,7 @@ utfx_status alloc_ws(utfx_ctx* c, uint64_t tiles) {
   c->ws = reinterpret_cast<WsHeader*>(p);
   c->status = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(p) + sizeof(WsHeader));
   c->cap_tiles = tiles;
+  c->ws_gen++;
   return init_ws(c);
 }
 
@@ -181,11 +189,19 @@ struct Launcher;
 #define UTFX_DEFINE_LAUNCH(NAME, KERNEL)                                                         \
   hipError_t NAME(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {                 \
     switch (wg) {                                                                               \
-      case 256: hipLaunchKernelGGL(KERNEL<256>, dim3((uint32_t)grid), dim3(256), 0, s, L); break; \
-      default: hipLaunchKernelGGL(KERNEL<512>, dim3((uint32_t)grid), dim3(512), 0, s, L); break; \
+      case 256: UTFX_KLAUNCH(KERNEL<256>, dim3((uint32_t)grid), 256, s, L); break; \
+      default: UTFX_KLAUNCH(KERNEL<512>, dim3((uint32_t)grid), 512, s, L); break; \
     }                                                                                           \
     return hipGetLastError();                                                                   \
   }
+
+// Events recorded around the main kernel of the call being launched (hipExtLaunchKernel
+// records them on the stream immediately before and after that kernel); null when the
+// context has none or is capturing.  Set by run() for the duration of one launch.
+thread_local hipEvent_t t_kev_start = nullptr, t_kev_stop = nullptr;
+
+#define UTFX_KLAUNCH(K, GRID, WG, S, L) \
+  hipExtLaunchKernelGGL(K, GRID, dim3(WG), 0, S, t_kev_start, t_kev_stop, 0, L)
 
 UTFX_DEFINE_LAUNCH(launch_len8, k_len8)
 UTFX_DEFINE_LAUNCH(launch_len16, k_len16)
@@ -195,7 +211,7 @@ UTFX_DEFINE_LAUNCH(launch_val16, k_validate16)
 // Transcode kernels are instantiated per (workgroup size, tiles per segment); a whole
 // segment's output is staged in LDS (up to 96 KiB of the 160 KiB a gfx950 workgroup
 // may use).
-#define UTFX_LAUNCH_WS(K, WG, S) hipLaunchKernelGGL((K<WG, S>), g, dim3(WG), 0, s, L)
+#define UTFX_LAUNCH_WS(K, WG, S) UTFX_KLAUNCH((K<WG, S>), g, WG, s, L)
 
 hipError_t launch_u8u16(uint32_t wg, uint64_t grid, const Launch& L, hipStream_t s) {
   const dim3 g((uint32_t)grid);
@@ -233,8 +249,16 @@ bool transcode_config_ok(int op, uint32_t tile_bytes, uint32_t seg) {
   return true;
 }
 
-UTFX_DEFINE_LAUNCH(launch_fin_u8u16, k_fin_u8u16)
-UTFX_DEFINE_LAUNCH(launch_fin_u16u8, k_fin_u16u8)
+hipError_t launch_fin_u8u16(uint32_t wg, const Launch& L, hipStream_t s) {
+  if (wg == 256) hipLaunchKernelGGL(k_fin_u8u16<256>, dim3(1), dim3(256), 0, s, L);
+  else hipLaunchKernelGGL(k_fin_u8u16<512>, dim3(1), dim3(512), 0, s, L);
+  return hipGetLastError();
+}
+hipError_t launch_fin_u16u8(uint32_t wg, const Launch& L, hipStream_t s) {
+  if (wg == 256) hipLaunchKernelGGL(k_fin_u16u8<256>, dim3(1), dim3(256), 0, s, L);
+  else hipLaunchKernelGGL(k_fin_u16u8<512>, dim3(1), dim3(512), 0, s, L);
+  return hipGetLastError();
+}
 
 // One-workgroup finalisation that follows every main launch on the same stream.
 hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s);
@@ -279,7 +303,7 @@ hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
       hipLaunchKernelGGL(k_fin_validate16, dim3(1), dim3(64), 0, s, L);
       return hipGetLastError();
     case U8U16:
-      return launch_fin_u8u16(wg, 1, L, s);
+      return launch_fin_u8u16(wg, L, s);
     case VAL32:
       hipLaunchKernelGGL(k_fin_validate32, dim3(1), dim3(64), 0, s, L);
       return hipGetLastError();
@@ -296,7 +320,7 @@ hipError_t launch_fin(int kind, uint32_t wg, const Launch& L, hipStream_t s) {
       hipLaunchKernelGGL(k_fin_u16u32<kU16U32Wg>, dim3(1), dim3(kU16U32Wg), 0, s, L);
       return hipGetLastError();
     default:
-      return launch_fin_u16u8(wg, 1, L, s);
+      return launch_fin_u16u8(wg, L, s);
   }
 }
 
@@ -379,6 +403,10 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
     return UTFX_E_INVALID_ARG;
   }
   hipError_t e = hipSuccess;
+  if (!c->capturing) {
+    t_kev_start = c->kev_start;
+    t_kev_stop = c->kev_stop;
+  }
   switch (kind) {
     case LEN8: e = launch_len8(wg, L.ntiles, L, c->stream); break;
     case LEN16: e = launch_len16(wg, L.ntiles, L, c->stream); break;
@@ -387,29 +415,28 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
     case U8U16: e = launch_u8u16(wg, L.ntiles, L, c->stream); break;
     case U16U8: e = launch_u16u8(wg, L.ntiles, L, c->stream); break;
     case VAL32:
-      hipLaunchKernelGGL(k_validate32<kVal32Wg>, dim3((uint32_t)L.ntiles), dim3(kVal32Wg), 0, c->stream, L);
+      UTFX_KLAUNCH(k_validate32<kVal32Wg>, dim3((uint32_t)L.ntiles), kVal32Wg, c->stream, L);
       e = hipGetLastError();
       break;
     case U8U32:
-      hipLaunchKernelGGL((k_u8_to_u32<kU8U32Wg, kU8U32Seg>), dim3((uint32_t)L.ntiles), dim3(kU8U32Wg), 0, c->stream, L);
+      UTFX_KLAUNCH((k_u8_to_u32<kU8U32Wg, kU8U32Seg>), dim3((uint32_t)L.ntiles), kU8U32Wg, c->stream, L);
       e = hipGetLastError();
       break;
     case U32U8:
-      hipLaunchKernelGGL((k_u32_to<kU32U8Wg, kU32U8Seg, uint8_t>), dim3((uint32_t)L.ntiles), dim3(kU32U8Wg), 0,
-                         c->stream, L);
+      UTFX_KLAUNCH((k_u32_to<kU32U8Wg, kU32U8Seg, uint8_t>), dim3((uint32_t)L.ntiles), kU32U8Wg, c->stream, L);
       e = hipGetLastError();
       break;
     case U32U16:
-      hipLaunchKernelGGL((k_u32_to<kU32U16Wg, kU32U16Seg, uint16_t>), dim3((uint32_t)L.ntiles), dim3(kU32U16Wg), 0,
-                         c->stream, L);
+      UTFX_KLAUNCH((k_u32_to<kU32U16Wg, kU32U16Seg, uint16_t>), dim3((uint32_t)L.ntiles), kU32U16Wg, c->stream,
+                   L);
       e = hipGetLastError();
       break;
     case U16U32:
-      hipLaunchKernelGGL((k_u16_to_u32<kU16U32Wg, kU16U32Seg>), dim3((uint32_t)L.ntiles), dim3(kU16U32Wg), 0,
-                         c->stream, L);
+      UTFX_KLAUNCH((k_u16_to_u32<kU16U32Wg, kU16U32Seg>), dim3((uint32_t)L.ntiles), kU16U32Wg, c->stream, L);
       e = hipGetLastError();
       break;
   }
+  t_kev_start = t_kev_stop = nullptr;
   if (e == hipSuccess) e = launch_fin(kind, wg, L, c->stream);
   if (e != hipSuccess) {
     set_err(c, "kernel launch", e);
@@ -718,6 +745,13 @@ void utfx_destroy(utfx_ctx* c) {
 
 const char* utfx_last_error(const utfx_ctx* c) { return c ? c->err : "null context"; }
 
+utfx_status utfx_set_kernel_events(utfx_ctx* c, void* start_event, void* stop_event) {
+  if (!c || (!start_event) != (!stop_event)) return UTFX_E_INVALID_ARG;
+  c->kev_start = reinterpret_cast<hipEvent_t>(start_event);
+  c->kev_stop = reinterpret_cast<hipEvent_t>(stop_event);
+  return UTFX_OK;
+}
+
 utfx_status utfx_set_stream(utfx_ctx* c, void* hip_stream) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -817,9 +851,11 @@ utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes
                            utfx_result* d_results) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
+  const void* mem = c->batch.mem;
   utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, in_arena,
                              in_bytes, out_arena, out_bytes, d_items, n_items, total_in_units, d_results, c->err,
                              sizeof(c->err));
+  if (c->batch.mem != mem) c->ws_gen++;
   if (st == UTFX_OK && c->capturing) c->cap_batches++;
   return st;
 }
@@ -874,6 +910,7 @@ utfx_status utfx_capture_end(utfx_ctx* c, utfx_graph** out) {
   g->exec = exec;
   g->launches = c->cap_launches;
   g->batches = c->cap_batches;
+  g->ws_gen = c->ws_gen;
   *out = g;
   return UTFX_OK;
 }
@@ -881,6 +918,11 @@ utfx_status utfx_capture_end(utfx_ctx* c, utfx_graph** out) {
 utfx_status utfx_graph_launch(utfx_graph* g, void* hip_stream) {
   if (!g || g->ctx->capturing) return UTFX_E_INVALID_ARG;
   utfx_ctx* c = g->ctx;
+  if (g->ws_gen != c->ws_gen) {
+    // the graph's kernels hold the addresses of a workspace that has since been freed
+    set_msg(c, "the context's workspace grew after this graph was captured; capture it again");
+    return UTFX_E_INVALID_ARG;
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   // replays advance the workspace epochs like eager calls; clear the status words
   // before the epoch space could wrap

@@ -487,9 +487,13 @@ __device__ __forceinline__ uint32_t ld_fault(WsHeader* ws) {
 }
 
 // Finalisation epilogue (one thread): make the workspace ready for the next launch.
+// The fault flag is cleared too: a watchdog trip is reported by the launch it happened
+// in, and the next launch carries a new epoch, so no status word of the failed launch
+// is ever read again.
 __device__ __forceinline__ void reset_ws(WsHeader* ws) {
   st_agent(&ws->err, NO_ERR);
   st_agent(&ws->acc, 0);
+  __hip_atomic_store(&ws->fault, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t ep = __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(&ws->epoch, (ep + 1) & EPOCH_MASK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

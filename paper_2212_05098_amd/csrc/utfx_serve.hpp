@@ -86,6 +86,7 @@ struct utfx_server {
   std::deque<utfx_srv::Req> pending;       // small requests, arrival order
   std::deque<utfx_srv::Req> pending_bulk;  // bulk requests, arrival order
   std::deque<uint64_t> rejected;  // tags of requests no slot can ever hold
+  utfx_srv::FailedRequests failed;  // tags of requests whose step could not be launched
   std::vector<utfx_srv::Slot> slots;
   uint64_t steps = 0;
   uint64_t items_total = 0;
@@ -148,8 +149,9 @@ inline uint64_t out_bytes(const Req& r) { return r.out_cap * (r.dir ? 1 : 2); }
 
 // Packs every request of queue q that fits into slot s and launches the step.  Returns
 // the number of requests taken.  A request no slot can hold is rejected (it completes
-// with UTFX_E_INVALID_ARG on the next progress call).
-inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bulk, utfx_status* st) {
+// with UTFX_E_INVALID_ARG on the next progress call).  If the step cannot be launched,
+// its requests complete with UTFX_E_DEVICE and the slot stays free.
+inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bulk) {
   const utfx_server_config& c = S->cfg;
   StepPacker pk(PackLimits{c.arena_in_bytes, c.arena_out_bytes, c.max_items, kDirectMin});
   uint64_t units = 0;
@@ -211,7 +213,12 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
   if (e == hipSuccess && bs == UTFX_OK) e = hipEventRecord(s.done, s.stream);
   if (e != hipSuccess || bs != UTFX_OK) {
     snprintf(S->err, sizeof(S->err), "step launch: %s / status %d", hipGetErrorString(e), (int)bs);
-    *st = UTFX_E_DEVICE;
+    // copies already queued may still read the slot's staging buffers: let them end
+    // before the slot takes another step
+    (void)hipStreamSynchronize(s.stream);
+    for (const Req& r : s.reqs) S->failed.add(r.tag);
+    s.reqs.clear();
+    return n;
   }
   s.busy = true;
   s.bulk = bulk;
@@ -304,7 +311,7 @@ utfx_status utfx_server_progress(utfx_server* S, utfx_completion* done, uint32_t
     s.busy = false;
     s.reqs.clear();
   }
-  // requests no slot can hold
+  // requests no slot can hold, and requests of steps that could not be launched
   while (!S->rejected.empty() && *n_done < max_done) {
     utfx_completion& c = done[(*n_done)++];
     c.tag = S->rejected.front();
@@ -313,6 +320,14 @@ utfx_status utfx_server_progress(utfx_server* S, utfx_completion* done, uint32_t
     c.result.count = 0;
     c.result.written = 0;
     S->rejected.pop_front();
+  }
+  while (!S->failed.empty() && *n_done < max_done) {
+    utfx_completion& c = done[(*n_done)++];
+    c.tag = S->failed.pop();
+    c.result.status = UTFX_E_DEVICE;
+    c.result.reserved = 0;
+    c.result.count = 0;
+    c.result.written = 0;
   }
   // then launch steps on free slots while requests wait: a bulk step when none is in
   // flight, small steps otherwise, and more bulk steps only while no small request
@@ -323,14 +338,11 @@ utfx_status utfx_server_progress(utfx_server* S, utfx_completion* done, uint32_t
     if (s.busy) continue;
     const int which = pick_queue(!S->pending_bulk.empty(), !S->pending.empty(), bulk_busy);
     if (which == 1) {
-      launch_step(S, s, S->pending_bulk, true, &st);
-      bulk_busy = true;
+      launch_step(S, s, S->pending_bulk, true);
+      bulk_busy = s.busy;
     } else if (which == 0) {
-      launch_step(S, s, S->pending, false, &st);
-    } else {
-      continue;
+      launch_step(S, s, S->pending, false);
     }
-    if (st != UTFX_OK) return st;
   }
   return st;
 }

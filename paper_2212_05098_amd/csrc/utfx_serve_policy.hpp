@@ -6,6 +6,8 @@
 
 #include <stdint.h>
 
+#include <deque>
+
 namespace utfx_srv {
 
 // What the policy needs to know of a request.
@@ -83,6 +85,21 @@ struct StepPacker {
 
   uint64_t staged_in_bytes() const { return in_lo; }    // bytes of the input mirror to copy
   uint64_t staged_out_bytes() const { return out_lo; }  // bytes of the output mirror to copy back
+};
+
+// Requests of steps that could not be launched (a copy or the batched call failed to
+// queue).  The slot is free again at once; each of its requests completes exactly once,
+// with a device error, on a later progress call (never with the results of an earlier
+// step left in the slot's buffers).
+struct FailedRequests {
+  std::deque<uint64_t> tags;
+  void add(uint64_t tag) { tags.push_back(tag); }
+  bool empty() const { return tags.empty(); }
+  uint64_t pop() {
+    const uint64_t t = tags.front();
+    tags.pop_front();
+    return t;
+  }
 };
 
 // Which queue a free slot serves: 1 = bulk, 0 = small, -1 = none.  A bulk step is

@@ -373,6 +373,7 @@ __global__ void __launch_bounds__(WG) k_fin_u8u16(Launch L) {
   const bool fault = ld_fault(L.ws) != 0;
   uint64_t written = 0;
   if (!fault && err != NO_ERR) written = prefix_words8<WG>(L, err, L.seg_units, lds);
+  __syncthreads();  // every wave has read err and fault before thread 0 resets them
   if (threadIdx.x == 0) {
     const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
     if (fault) write_result(L.result, ST_DEVICE, 0, 0);
@@ -688,6 +689,7 @@ __global__ void __launch_bounds__(WG) k_fin_u16u8(Launch L) {
   const bool fault = ld_fault(L.ws) != 0;
   uint64_t written = 0;
   if (!fault && err != NO_ERR) written = prefix_bytes16<WG>(L, err, L.seg_units, lds);
+  __syncthreads();  // every wave has read err and fault before thread 0 resets them
   if (threadIdx.x == 0) {
     const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
     if (fault) write_result(L.result, ST_DEVICE, 0, 0);

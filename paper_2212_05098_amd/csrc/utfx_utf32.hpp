@@ -208,6 +208,7 @@ __global__ void __launch_bounds__(WG) k_fin_u8u32(Launch L) {
     const uint64_t s = block_sum_u64<WG>(acc, lds);
     written = (seg ? tile_inclusive(L.status, seg - 1) : 0) + s;
   }
+  __syncthreads();  // every wave has read err and fault before thread 0 resets them
   if (threadIdx.x == 0) {
     const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
     if (fault) write_result(L.result, ST_DEVICE, 0, 0);
@@ -375,6 +376,7 @@ __global__ void __launch_bounds__(WG) k_fin_u32to(Launch L) {
     const uint64_t s = block_sum_u64<WG>(acc, lds);
     written = (seg ? tile_inclusive(L.status, seg - 1) : 0) + s;
   }
+  __syncthreads();  // every wave has read err and fault before thread 0 resets them
   if (threadIdx.x == 0) {
     const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
     if (fault) {
@@ -534,6 +536,7 @@ __global__ void __launch_bounds__(WG) k_fin_u16u32(Launch L) {
     const uint64_t s = block_sum_u64<WG>(acc, lds);
     written = (seg ? tile_inclusive(L.status, seg - 1) : 0) + s;
   }
+  __syncthreads();  // every wave has read err and fault before thread 0 resets them
   if (threadIdx.x == 0) {
     const uint64_t tot = tile_inclusive(L.status, L.ntiles - 1);
     if (fault) write_result(L.result, ST_DEVICE, 0, 0);

@@ -7,7 +7,9 @@
 // hold it; within a step, placements are 16-byte aligned, inside the arenas and disjoint
 // (staged from the start, direct from the end); each queue is served in arrival order;
 // steps hold 1..max_items requests; a bulk step starts only when no bulk step is in
-// flight or no small request waits.  Prints "ok <counts>" or the first violation.
+// flight or no small request waits.  Some step launches fail (as a failed copy or
+// batched call would): their requests must complete exactly once, through the failed
+// list, with the slot free at once.  Prints "ok <counts>" or the first violation.
 #include <stdint.h>
 #include <stdio.h>
 
@@ -65,10 +67,21 @@ static int run(uint64_t seed, uint32_t n_slots, uint32_t max_items, double rate_
   std::deque<uint64_t> small, bulk;
   std::vector<int> done(n, 0);
   std::vector<int> rejected(n, 0);
-  uint64_t last_small = 0, last_bulk = 0, now = 0, steps = 0, n_done = 0, n_rej = 0;
+  std::vector<int> failed_ids(n, 0);
+  FailedRequests failed;
+  uint64_t last_small = 0, last_bulk = 0, now = 0, steps = 0, n_done = 0, n_rej = 0, n_fail = 0, failed_steps = 0;
   bool seen_small = false, seen_bulk = false;
   uint32_t next = 0;
   while (n_done + n_rej < n) {
+    // failed steps' requests complete first (the server reports them on its next call)
+    while (!failed.empty()) {
+      const uint64_t id = failed.pop();
+      if (done[id]++) return fail("completed twice", id, 0);
+      if (!failed_ids[id]) return fail("completed as failed without a failed step", id, 0);
+      ++n_done;
+      ++n_fail;
+    }
+    if (n_done + n_rej >= n) break;
     // the next event: an arrival or a step's end
     uint64_t te = UINT64_MAX;
     if (next < n) te = reqs[next].arrival;
@@ -141,6 +154,15 @@ static int run(uint64_t seed, uint32_t n_slots, uint32_t max_items, double rate_
           if ((*v)[k].lo < (*v)[k - 1].hi) return fail("overlapping placements", (*v)[k].lo, (*v)[k - 1].hi);
       }
       if (s.ids.empty()) continue;
+      if (u(g) < 0.02) {  // the launch fails: the slot stays free, its requests fail once
+        for (uint64_t id : s.ids) {
+          if (failed_ids[id]++) return fail("failed twice", id, 0);
+          failed.add(id);
+        }
+        s.ids.clear();
+        ++failed_steps;
+        continue;
+      }
       s.busy = true;
       s.bulk = which == 1;
       bulk_busy |= s.bulk;
@@ -150,8 +172,10 @@ static int run(uint64_t seed, uint32_t n_slots, uint32_t max_items, double rate_
   }
   for (uint32_t i = 0; i < n; ++i)
     if (done[i] + rejected[i] != 1) return fail("request lost", i, 0);
-  printf("ok seed=%llu slots=%u max_items=%u steps=%llu done=%llu rejected=%llu\n", (unsigned long long)seed,
-         n_slots, max_items, (unsigned long long)steps, (unsigned long long)n_done, (unsigned long long)n_rej);
+  if (failed_steps == 0 || n_fail == 0) return fail("no failed step was exercised", failed_steps, n_fail);
+  printf("ok seed=%llu slots=%u max_items=%u steps=%llu done=%llu rejected=%llu failed_steps=%llu failed=%llu\n",
+         (unsigned long long)seed, n_slots, max_items, (unsigned long long)steps, (unsigned long long)n_done,
+         (unsigned long long)n_rej, (unsigned long long)failed_steps, (unsigned long long)n_fail);
   return 0;
 }
 
