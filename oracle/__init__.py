@@ -119,6 +119,10 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.argtypes = [p8, sz, sz, p8, p8]
             fn.restype = ctypes.c_uint64
+        for name in ("utfx_ref_utf8_to_utf16le_fixed", "utfx_ref_utf16le_to_utf8_fixed"):
+            fn = getattr(L, name)
+            fn.argtypes = [p8, sz, sz, p8, p8, p8]
+            fn.restype = ctypes.c_uint64
         L.utfx_ref_batch.argtypes = [p8, sz, p8, sz, p8, sz, p8]
         L.utfx_ref_batch.restype = ctypes.c_uint64
         ci = ctypes.c_int
@@ -309,6 +313,25 @@ def validate_utf16le_fixed(buf: np.ndarray, length: int, want_arrays: bool = Tru
         _ptr(a), n, length, _ptr(st) if want_arrays else None, _ptr(ct) if want_arrays else None
     )
     return int(nv), st, ct
+
+
+def transcode_fixed(buf: np.ndarray, length: int, utf16_in: bool = False, out=None):
+    """Transcode back-to-back strings of `length` units (UTF-8 -> UTF-16LE, or UTF-16LE
+    -> UTF-8 with utf16_in), outputs discarded.  Returns (n_valid, status, count,
+    written); `out` may supply the three arrays (int32, uint64, uint64, contiguous)."""
+    a = _u16(buf) if utf16_in else _u8(buf)
+    n = a.size // length if length else 0
+    if out is None:
+        st = np.empty(n, dtype=np.int32)
+        ct = np.empty(n, dtype=np.uint64)
+        wr = np.empty(n, dtype=np.uint64)
+    else:
+        st, ct, wr = out
+        assert st.dtype == np.int32 and ct.dtype == wr.dtype == np.uint64 and min(st.size, ct.size, wr.size) >= n
+        assert st.flags.c_contiguous and ct.flags.c_contiguous and wr.flags.c_contiguous
+    fn = lib().utfx_ref_utf16le_to_utf8_fixed if utf16_in else lib().utfx_ref_utf8_to_utf16le_fixed
+    nv = fn(_ptr(a), n, length, _ptr(st), _ptr(ct), _ptr(wr))
+    return int(nv), st, ct, wr
 
 
 # ---- batches: each item is the single-string call on its bytes --------------------

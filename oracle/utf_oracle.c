@@ -351,6 +351,36 @@ uint64_t utfx_ref_validate_utf16le_fixed(const uint16_t *buf, size_t n_strings, 
   return valid;
 }
 
+uint64_t utfx_ref_utf8_to_utf16le_fixed(const uint8_t *buf, size_t n_strings, size_t len,
+                                        int32_t *status, uint64_t *count, uint64_t *written) {
+  uint64_t valid = 0;
+  uint16_t out[64];
+  if (len > 64) return 0;
+  for (size_t s = 0; s < n_strings; s++) {
+    utfx_ref_result r = utfx_ref_utf8_to_utf16le(buf + s * len, len, out, len);
+    if (status) status[s] = r.status;
+    if (count) count[s] = r.count;
+    if (written) written[s] = r.written;
+    if (r.status == UTFX_REF_OK) valid++;
+  }
+  return valid;
+}
+
+uint64_t utfx_ref_utf16le_to_utf8_fixed(const uint16_t *buf, size_t n_strings, size_t len,
+                                        int32_t *status, uint64_t *count, uint64_t *written) {
+  uint64_t valid = 0;
+  uint8_t out[192];
+  if (len > 64) return 0;
+  for (size_t s = 0; s < n_strings; s++) {
+    utfx_ref_result r = utfx_ref_utf16le_to_utf8(buf + s * len, len, out, 3 * len);
+    if (status) status[s] = r.status;
+    if (count) count[s] = r.count;
+    if (written) written[s] = r.written;
+    if (r.status == UTFX_REF_OK) valid++;
+  }
+  return valid;
+}
+
 /* ---- batched reference: every item is the single-string call on its bytes ------- */
 
 uint64_t utfx_ref_batch(const uint8_t *in_arena, size_t in_bytes, uint8_t *out_arena, size_t out_bytes,

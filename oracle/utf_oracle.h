@@ -88,6 +88,12 @@ uint64_t utfx_ref_validate_utf8_fixed(const uint8_t *buf, size_t n_strings, size
                                       int32_t *status, uint64_t *count);
 uint64_t utfx_ref_validate_utf16le_fixed(const uint16_t *buf, size_t n_strings, size_t len,
                                          int32_t *status, uint64_t *count);
+/* The same loop over the validating transcodes (output room: len words, or 3 len
+ * bytes, per string, discarded): per-string status, count and written. */
+uint64_t utfx_ref_utf8_to_utf16le_fixed(const uint8_t *buf, size_t n_strings, size_t len,
+                                        int32_t *status, uint64_t *count, uint64_t *written);
+uint64_t utfx_ref_utf16le_to_utf8_fixed(const uint16_t *buf, size_t n_strings, size_t len,
+                                        int32_t *status, uint64_t *count, uint64_t *written);
 
 /* Batched reference (the invariant a batched call must meet: each string gets the
  * result of the single-string call on its bytes).  One item per string, with byte

@@ -400,6 +400,19 @@ def make_batch(n_strings: int, seed_key: Sequence[int] = (0, 4), median: float =
     return Batch(arena, in_off, in_len, dirs, profs.astype(np.uint8), err_pos)
 
 
+def batch_output_layout(b: Batch, gap: int = 16):
+    """Output slots of a batch with room for every string's worst case (n words for
+    UTF-8 -> UTF-16LE, 3n bytes for UTF-16LE -> UTF-8), laid out back to back with
+    `gap` bytes between slots, UTF-16 slots at even offsets.  Returns (caps in output
+    units, out_off in bytes, total output bytes)."""
+    caps = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
+    sizes = np.where(b.direction == 0, 2 * caps, caps).astype(np.uint64)
+    out_off = np.concatenate([[0], np.cumsum(sizes + gap)[:-1]]).astype(np.uint64)
+    out_off += out_off % 2
+    total = int(out_off[-1] + sizes[-1] + 64) if len(out_off) else 64
+    return caps, out_off, total
+
+
 @dataclass
 class Trace:
     arrival_s: np.ndarray     # float64 arrival times, ascending

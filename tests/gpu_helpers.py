@@ -223,3 +223,30 @@ def check_u32_to_u16(ctx, units, cap=None, in_shift=0, out_shift=0, guard=32, be
     assert np.array_equal(got[out_shift:out_shift + w], ref[:w])
     assert np.all(got[:out_shift] == 0x5A5A) and np.all(got[out_shift + cap:] == 0x5A5A)
     return r
+
+
+def spans(starts, lengths, size):
+    """Boolean mask of the union of [start, start + length) over the items."""
+    d = np.zeros(size + 1, dtype=np.int32)
+    np.add.at(d, np.asarray(starts).astype(np.int64), 1)
+    np.add.at(d, (np.asarray(starts) + np.asarray(lengths)).astype(np.int64), -1)
+    return np.cumsum(d[:-1]) > 0
+
+
+def compare_batch(got_res, got_out, ora_res, ora_out, items, label, guard=None):
+    """A batched call against the oracle's batched reference, vectorised: every item's
+    status, count and written; every byte of every output prefix; and, with `guard`,
+    that every byte outside the output slots still holds the guard value."""
+    g = np.ascontiguousarray(got_res).view(np.uint8).view(O.RESULT_DTYPE)
+    for f in ("status", "count", "written"):
+        bad = np.nonzero(g[f] != ora_res[f])[0]
+        assert bad.size == 0, (label, f, bad[:5], g[bad[:5]], ora_res[bad[:5]], items[bad[:5]])
+    unit = np.where(items["dir"] == 0, 2, 1).astype(np.uint64)
+    w = np.minimum(ora_res["written"], items["out_cap"]) * unit
+    w[ora_res["status"] == O.E_OUTPUT_TOO_SMALL] = 0
+    m = spans(items["out_off"], w, got_out.size)
+    diff = np.nonzero(got_out[m] != ora_out[m])[0]
+    assert diff.size == 0, (label, "output bytes differ", diff[:5])
+    if guard is not None:
+        slots = spans(items["out_off"], items["out_cap"] * unit, got_out.size)
+        assert np.all(got_out[~slots] == guard), (label, "stored outside the output slots")

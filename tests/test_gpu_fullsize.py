@@ -74,7 +74,7 @@ def test_full_size_injected_utf8(ctx, prof, rate):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("prof,rate", [("cjk", 1e-6), ("mixed4", 1e-3)])
+@pytest.mark.parametrize("prof,rate", [("cjk", 1e-6), ("cjk", 1e-3), ("mixed4", 1e-6), ("mixed4", 1e-3)])
 def test_full_size_injected_utf16(ctx, prof, rate):
     import torch
 
