@@ -167,6 +167,27 @@ utfx_status utfx_utf8_to_utf16le_async(utfx_ctx *ctx, const uint8_t *in, size_t 
 utfx_status utfx_utf16le_to_utf8_async(utfx_ctx *ctx, const uint16_t *in, size_t n_words,
                                        uint8_t *out, size_t cap_bytes, utfx_result *d_result);
 
+/* ---- allocation-free UTF-8 -> UTF-16LE ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same operation and result as
+ * utfx_utf8_to_utf16le_async, without a context: queued on hip_stream (a hipStream_t;
+ * NULL = the default stream) of the current device, with the result stored to the
+ * device pointer d_result.  in, out and d_result are device pointers owned by the
+ * caller; out needs 2-byte alignment.
+ *
+ * The call allocates nothing.  Its workspace (a header and one status word per 32 KiB
+ * of input, 2 MiB in all) is a static device array that each device holds until the
+ * process ends; its first call on a device looks the array up and queues a kernel
+ * that clears it (make that first call outside a graph capture).  Every call on a
+ * device shares that device's array, so calls that overlap in time on one device (on
+ * different streams or from different threads) race and give wrong results: order
+ * them on one stream.  n_bytes above UTFX_NOALLOC_MAX_BYTES, a null pointer with a
+ * nonzero size, a null d_result or a misaligned out give UTFX_E_INVALID_ARG with
+ * nothing queued; a HIP failure gives UTFX_E_DEVICE. */
+#define UTFX_NOALLOC_MAX_BYTES ((((uint64_t)1) << 29) - 32)
+utfx_status utfx_utf8_to_utf16le_noalloc(const uint8_t *in, size_t n_bytes, uint16_t *out, size_t cap_words,
+                                         utfx_result *d_result, void *hip_stream);
+
 /* ---- UTF-16BE ------------------------------------------------------------------
  * The same operations with big-endian UTF-16 code units (section 2: the paper works
  * in UTF-16LE, and big-endian input or output differs only by the byte order within

@@ -134,6 +134,7 @@ def lib() -> ctypes.CDLL:
         "utfx_validate_utf16le_async": (I, [P, P, Z, P]),
         "utfx_utf8_to_utf16le_async": (I, [P, P, Z, P, Z, P]),
         "utfx_utf16le_to_utf8_async": (I, [P, P, Z, P, Z, P]),
+        "utfx_utf8_to_utf16le_noalloc": (I, [P, Z, P, Z, P, P]),
         "utfx_utf8_length_from_utf16be": (CResult, [P, P, Z]),
         "utfx_validate_utf16be": (CResult, [P, P, Z]),
         "utfx_utf8_to_utf16be": (CResult, [P, P, Z, P, Z]),
@@ -657,6 +658,21 @@ def result_tensor(n: int = 1, device="cuda"):
     import torch
 
     return torch.zeros(n * 24, dtype=torch.uint8, device=device)
+
+
+NOALLOC_MAX_BYTES = (1 << 29) - 32
+
+
+def utf8_to_utf16le_noalloc(src, dst, d_result, stream=None) -> int:
+    """utfx_utf8_to_utf16le_noalloc: the asynchronous UTF-8 -> UTF-16LE call without a
+    context or any allocation, on `stream` (default: torch's current stream).  Returns
+    the status of queueing it; the result goes to the device tensor d_result."""
+    import torch
+
+    p, n = _ptr_len(src, 1)
+    q, cap = _ptr_len(dst, 2)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(lib().utfx_utf8_to_utf16le_noalloc(p, n, q, cap, d_result.data_ptr(), ctypes.c_void_p(s.cuda_stream)))
 
 
 _default_ctx: Optional[Context] = None

@@ -13,6 +13,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "utfx.h"
 #include "utfx_kernels.hpp"
 #include "utfx_transcode.hpp"
@@ -60,6 +62,18 @@ struct utfx_ctx {
   hipEvent_t kev_stop = nullptr;
   char err[256];
 };
+
+// Workspace of the allocation-free call (utfx_utf8_to_utf16le_noalloc): a workspace
+// header and one status word per segment of 32 KiB, STATUS_STRIDE words apart.  Each
+// device holds its own copy for the life of the process.
+constexpr uint32_t kNoAllocWg = 512, kNoAllocSeg = 4;
+constexpr uint64_t kNoAllocSegUnits = 16ull * kNoAllocWg * kNoAllocSeg;
+constexpr uint64_t kNoAllocSegs = 16384;
+constexpr uint64_t kNoAllocWords = sizeof(WsHeader) / 8 + kNoAllocSegs * STATUS_STRIDE;
+static_assert(UTFX_NOALLOC_MAX_BYTES + 15 + 1 <= kNoAllocSegs * kNoAllocSegUnits, "scratch covers the size limit");
+static_assert(sizeof(WsHeader) % 8 == 0, "header in whole words");
+
+static __device__ __align__(256) unsigned long long scratch[kNoAllocWords];
 
 struct utfx_graph {
   utfx_ctx* ctx = nullptr;
@@ -620,6 +634,97 @@ utfx_result stream_transcode(utfx_ctx* c, utfx_stream* st, const void* in, uint6
   return mkres(UTFX_OK, total, total);
 }
 
+// ---------------------------------------------------------------- allocation-free call
+//
+// utfx_utf8_to_utf16le_noalloc runs the kernels of utfx_utf8_to_utf16le_async with its
+// workspace in the file-scope array `scratch` (a workspace header and one status word per segment,
+// STATUS_STRIDE words apart) instead of a context's.  Host code never passes the
+// array's name to a kernel: it looks up the array's device address once per device
+// (hipGetSymbolAddress, with that device current) and passes that.
+
+// Clears the status words and initialises the header (the k_ws_init state), as one
+// ordinary kernel so that a graph may record it.
+__global__ void k_noalloc_clear(unsigned long long* words, uint64_t n_words) {
+  const uint64_t hdr = sizeof(WsHeader) / 8;
+  for (uint64_t i = hdr + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_words;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    words[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    WsHeader* ws = reinterpret_cast<WsHeader*>(words);
+    ws->spare0 = 0;
+    ws->spare1 = 0;
+    ws->err = NO_ERR;
+    ws->acc = 0;
+    ws->epoch = 1;
+    ws->fault = 0;
+  }
+}
+
+constexpr int kNoAllocMaxDevices = 64;
+struct NoAllocDevice {
+  unsigned long long* ptr = nullptr;  // device address of `scratch` on this device
+  uint64_t launches = 0;              // calls since the status words were last cleared
+};
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+utfx_status noalloc_u8u16(const uint8_t* in, uint64_t n, uint16_t* out, uint64_t cap, void* d_result,
+                          hipStream_t stream) {
+  if (!d_result || (n > 0 && !in) || (cap > 0 && !out) || (reinterpret_cast<uintptr_t>(out) & 1))
+    return UTFX_E_INVALID_ARG;
+  if (n > UTFX_NOALLOC_MAX_BYTES) return UTFX_E_INVALID_ARG;
+  if (n == 0) {
+    hipLaunchKernelGGL(k_store_result, dim3(1), dim3(64), 0, stream, reinterpret_cast<Result*>(d_result), UTFX_OK,
+                       0ull, 0ull);
+    return hipGetLastError() == hipSuccess ? UTFX_OK : UTFX_E_DEVICE;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return UTFX_E_DEVICE;
+  unsigned long long* words = nullptr;
+  bool clear = false;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoAllocDevice& d = g_noalloc[dev];
+    if (!d.ptr) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return UTFX_E_DEVICE;
+      d.ptr = static_cast<unsigned long long*>(p);
+      d.launches = 0;
+    }
+    // the first call on a device, and every kEpochClearEvery calls, clears the status
+    // words before the 25-bit launch epoch can come round again
+    clear = (d.launches % kEpochClearEvery) == 0;
+    d.launches++;
+    words = d.ptr;
+  }
+  if (clear) {
+    hipLaunchKernelGGL(k_noalloc_clear, dim3(256), dim3(256), 0, stream, words, kNoAllocWords);
+    if (hipGetLastError() != hipSuccess) return UTFX_E_DEVICE;
+  }
+  Launch L;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(in);
+  L.base = reinterpret_cast<const uint8_t*>(a & ~static_cast<uintptr_t>(15));
+  L.mis = a & 15;
+  L.n = n;
+  L.out = out;
+  L.cap = cap;
+  L.ws = reinterpret_cast<WsHeader*>(words);
+  L.err = &L.ws->err;
+  L.status = words + sizeof(WsHeader) / 8;
+  L.result = d_result;
+  L.seg = kNoAllocSeg;
+  L.wg = kNoAllocWg;
+  L.be = 0;
+  L.seg_units = kNoAllocSegUnits;
+  L.ntiles = (L.mis + n + 1 + kNoAllocSegUnits - 1) / kNoAllocSegUnits;  // + 1: the position after the input
+  if (L.ntiles > kNoAllocSegs) return UTFX_E_INVALID_ARG;
+  hipLaunchKernelGGL((k_u8_to_u16<kNoAllocWg, kNoAllocSeg>), dim3((uint32_t)L.ntiles), dim3(kNoAllocWg), 0, stream,
+                     L);
+  if (hipGetLastError() != hipSuccess) return UTFX_E_DEVICE;
+  hipLaunchKernelGGL(k_fin_u8u16<kNoAllocWg>, dim3(1), dim3(kNoAllocWg), 0, stream, L);
+  return hipGetLastError() == hipSuccess ? UTFX_OK : UTFX_E_DEVICE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -817,6 +922,11 @@ utfx_status utfx_utf8_to_utf16le_async(utfx_ctx* c, const uint8_t* in, size_t n,
 utfx_status utfx_utf16le_to_utf8_async(utfx_ctx* c, const uint16_t* in, size_t n, uint8_t* out, size_t cap,
                                        utfx_result* r) {
   return run(c, U16U8, in, n, out, cap, r);
+}
+
+utfx_status utfx_utf8_to_utf16le_noalloc(const uint8_t* in, size_t n, uint16_t* out, size_t cap, utfx_result* r,
+                                         void* hip_stream) {
+  return noalloc_u8u16(in, n, out, cap, r, reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 utfx_result utfx_utf8_length_from_utf16be(utfx_ctx* c, const uint16_t* in, size_t n) {
