@@ -11,6 +11,7 @@
 #include <stddef.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -58,6 +59,7 @@ struct utfx_ctx {
   // generation of the workspace memory: bumped whenever the single-buffer or the
   // batch workspace is reallocated, so that a graph holding the old addresses is refused
   uint64_t ws_gen = 0;
+  uint32_t dbg = 0;                       // look-back delay injection (UTFX_DEBUG_LOOKBACK_DELAY)
   hipEvent_t kev_start = nullptr;         // kernel timing events (utfx_set_kernel_events)
   hipEvent_t kev_stop = nullptr;
   char err[256];
@@ -178,6 +180,7 @@ utfx_status prep_cfg(utfx_ctx* c, uint32_t wg_, uint32_t seg_tiles, const void* 
   L.seg = seg_tiles;
   L.wg = wg;
   L.be = 0;
+  L.dbg = c->dbg;
   const uint64_t per_seg = static_cast<uint64_t>(wg) * (16 / unit) * L.seg;
   L.seg_units = per_seg;
   L.ntiles = (L.mis + n + extra + per_seg - 1) / per_seg;
@@ -715,6 +718,7 @@ utfx_status noalloc_u8u16(const uint8_t* in, uint64_t n, uint16_t* out, uint64_t
   L.seg = kNoAllocSeg;
   L.wg = kNoAllocWg;
   L.be = 0;
+  L.dbg = 0;
   L.seg_units = kNoAllocSegUnits;
   L.ntiles = (L.mis + n + 1 + kNoAllocSegUnits - 1) / kNoAllocSegUnits;  // + 1: the position after the input
   if (L.ntiles > kNoAllocSegs) return UTFX_E_INVALID_ARG;
@@ -801,6 +805,12 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
   if (!c) return UTFX_E_DEVICE;
   c->err[0] = 0;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // debug mode: a nonzero UTFX_DEBUG_LOOKBACK_DELAY (1..64) makes the kernels hold back
+  // some segments' look-back publications (debug_delay); results must not change
+  if (const char* dd = getenv("UTFX_DEBUG_LOOKBACK_DELAY")) {
+    const long v = strtol(dd, nullptr, 10);
+    c->dbg = v < 0 ? 0u : (v > 64 ? 64u : (uint32_t)v);
+  }
   for (int i = 0; i < UTFX_OP_COUNT_; ++i) {
     c->tile_bytes[i] = 8192;
     c->seg_tiles[i] = 8;
@@ -962,7 +972,7 @@ utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
   const void* mem = c->batch.mem;
-  utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, in_arena,
+  utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, c->dbg, in_arena,
                              in_bytes, out_arena, out_bytes, d_items, n_items, total_in_units, d_results, c->err,
                              sizeof(c->err));
   if (c->batch.mem != mem) c->ws_gen++;

@@ -2,27 +2,31 @@
 //
 // Every string (item) gets the result the single-buffer call would give on its bytes.
 // Kernels, in stream order:
-//   k_batch_begin  advance the batch epoch; clear the segment totals, the large-item
-//                  count, the length sum and the fault flag (one thread, so the call
-//                  needs no memset and can be captured into a graph);
-//   k_batch_plan   per item: check its descriptor and, for a large item (more than
-//                  SMALL_MAX input units), count its segments; exclusive scans of the
-//                  counts over items, one per direction (workgroup scan + decoupled
-//                  look-back across workgroups); each large item writes the segment ->
-//                  item map of its segments and enters the large-item list; each tiny
-//                  item enters its direction's tiny-item list;
+//   k_batch_begin  advance the batch epoch; clear the segment totals, the list counts,
+//                  the length sum and the fault flag (one thread, so the call needs no
+//                  memset and can be captured into a graph);
+//   k_batch_plan   per item: check its descriptor (an invalid one gets its result
+//                  here) and, for a large item (more than SMALL_MAX input units), count
+//                  its segments; exclusive scans of the counts over items, one per
+//                  direction (workgroup scan + decoupled look-back across workgroups);
+//                  each large item writes the segment -> item map of its segments and
+//                  enters the large-item list; each tiny item enters its direction's
+//                  tiny-item list; every other item enters the list of its length
+//                  class (by the number of 1 KiB steps it takes);
 //   k_batch_tiny   four tiny items (at most TINY8 bytes / TINY16 words) per wave, one per
 //                  16-lane row: a row holds the whole string in one step;
-//   k_batch_small  one wave per other item of at most SMALL_MAX units: the wave walks the
-//                  string 1 KiB (512 words) at a time carrying the output offset, so it
-//                  needs no look-back and no barrier, and writes the item's result;
-//   k_batch_large  one workgroup per segment of the large items (one launch per
-//                  direction) runs the single-buffer segment code; a segment's look-back
-//                  ends at its item's first segment, which publishes its prefix directly;
+//   k_batch_small  one wave per item of the length-class lists, longest class first:
+//                  the wave walks the string 1 KiB (512 words) at a time carrying the
+//                  output offset (no look-back, no barrier) and writes the item's result;
+//   k_batch_large  one persistent launch per direction: each workgroup takes every G-th
+//                  segment of the large items (G = its grid) and runs the single-buffer
+//                  segment code on it, the look-back ending at the item's first segment;
 //   k_batch_fin    one workgroup per large item: the result from its segments.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdio.h>
+
+#include <type_traits>
 
 #include "utfx.h"
 #include "utfx_transcode.hpp"
@@ -36,13 +40,15 @@ struct BItem {  // utfx_item
 
 // Items up to this many input units are transcoded by one wave.
 constexpr uint64_t SMALL_MAX = 16384;
+// Length classes of the wave-walked items, by the steps (1 KiB of UTF-8 or 512 words of
+// UTF-16) a wave takes: class 0 = more than 8 steps, 1 = 5..8, 2 = 3..4, 3 = 1..2.
+constexpr int NCLS = 4;
 // Geometry of the large-item segments (workgroup size, tiles per segment per direction).
 constexpr int BWG = 512, BS8 = 4, BS16 = 4;
 constexpr uint64_t BSEG8 = 16ull * BWG * BS8;   // UTF-8 bytes per segment
 constexpr uint64_t BSEG16 = 8ull * BWG * BS16;  // UTF-16 words per segment
 constexpr int PLAN_WG = 256;
 constexpr int PLAN_ITEMS = 4;  // items per plan thread
-constexpr int SMALL_WG = 256;
 
 struct BatchArgs {
   const uint8_t* in;
@@ -61,10 +67,13 @@ struct BatchArgs {
   uint32_t* unit_item[2];            // cap_units each: item of each segment
   uint32_t* large;                   // n_items: list of large items
   uint32_t* tiny[2];                 // n_items each: list of tiny items per direction
+  uint32_t* small[NCLS];             // n_items each: wave-walked items per length class
+  unsigned long long* cls_count;     // NCLS: lengths of the small[] lists
   unsigned long long* plan_status[2];  // one status word per plan workgroup and direction (strided)
   uint64_t cap_units;
   uint64_t total_in;                 // the caller's bound on the sum of in_len
   uint32_t rows;                     // tiny items go to k_batch_tiny (large calls only)
+  uint32_t dbg;                      // look-back delay injection (debug_delay); 0 = off
 };
 
 // Whether the plan holds: the items add up to at most the caller's bound, and so
@@ -122,11 +131,14 @@ __device__ __forceinline__ Launch item_launch(const BatchArgs& A, const BItem& i
   L.seg = it.dir ? BS16 : BS8;
   L.wg = BWG;
   L.be = 0;
+  L.dbg = A.dbg;
   return L;
 }
 
-__global__ void k_batch_begin(WsHeader* ws) {
+__global__ void k_batch_begin(WsHeader* ws, unsigned long long* cls_count) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) st_agent(&cls_count[c], 0);
     const uint32_t ep = __hip_atomic_load(&ws->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ws->epoch, (ep + 1) & EPOCH_MASK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     st_agent(&ws->spare0, 0);
@@ -139,13 +151,23 @@ __global__ void k_batch_begin(WsHeader* ws) {
   }
 }
 
+// Length class of a wave-walked item: the wave takes floor((mis + n) / step) + 1 steps.
+__device__ __forceinline__ uint32_t item_class(const BatchArgs& A, const BItem& it) {
+  const uint32_t unit = it.dir ? 2u : 1u;
+  const uint64_t mis = (((uintptr_t)(A.in + it.in_off)) & 15) / unit;
+  const uint64_t steps = (mis + it.in_len) / (it.dir ? 512 : 1024) + 1;
+  return steps > 8 ? 0u : (steps > 4 ? 1u : (steps > 2 ? 2u : 3u));
+}
+
 __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
-  __shared__ uint32_t scr[4][PLAN_WG / 64];
+  __shared__ uint32_t scr[6][PLAN_WG / 64];
+  __shared__ unsigned long long cbase[NCLS];
   __shared__ unsigned long long pfx[2], lbase[3];
   __shared__ unsigned long long sum_scr[PLAN_WG / 64 + 2];
   // PLAN_ITEMS consecutive items per thread
   const uint64_t i0 = ((uint64_t)blockIdx.x * PLAN_WG + threadIdx.x) * PLAN_ITEMS;
   uint32_t units[PLAN_ITEMS], dir[PLAN_ITEMS], tsum[2] = {0, 0}, tiny = 0, ntiny[2] = {0, 0};
+  uint32_t cls = 0, ncls[NCLS] = {0, 0, 0, 0};  // cls: 3 bits per item (class + 1, 0 = none)
   uint64_t len = 0;
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) {
@@ -156,15 +178,20 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
       const BItem it = A.items[i];
       if (item_ok(A, it)) {
         len += it.in_len;
-        if (A.rows && item_tiny(it)) {
-          tiny |= (1u + it.dir) << (2 * j);  // 1: UTF-8, 2: UTF-16
-          ntiny[it.dir]++;
-        }
         if (it.in_len > SMALL_MAX) {
           units[j] = (uint32_t)item_units(A, it);
           dir[j] = it.dir;
           tsum[it.dir] += units[j];
+        } else if (A.rows && item_tiny(it)) {
+          tiny |= (1u + it.dir) << (2 * j);  // 1: UTF-8, 2: UTF-16
+          ntiny[it.dir]++;
+        } else {
+          const uint32_t c = item_class(A, it);
+          cls |= (c + 1u) << (3 * j);
+          ncls[c]++;
         }
+      } else {
+        write_result(A.results + i, ST_INVALID_ARG, 0, 0);
       }
     }
   }
@@ -177,8 +204,21 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
   if (threadIdx.x < 64) {
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
-      if (threadIdx.x == 0) publish_aggregate(A.plan_status[d], blockIdx.x, total[d], epoch);
-      const uint64_t b = lookback_wave(A.plan_status[d], blockIdx.x, total[d], epoch, A.ws);
+      if (threadIdx.x == 0) {
+        debug_delay(A.dbg, blockIdx.x);
+        publish_aggregate(A.plan_status[d], blockIdx.x, total[d], epoch);
+      }
+      // a plan workgroup's aggregate, recomputed from its items if it is late
+      const uint64_t b = lookback_wave(A.plan_status[d], blockIdx.x, total[d], epoch, A.ws, [&](uint64_t blk) {
+        const uint64_t a0 = blk * (uint64_t)(PLAN_WG * PLAN_ITEMS);
+        const uint64_t a1 = a0 + PLAN_WG * PLAN_ITEMS < A.n_items ? a0 + PLAN_WG * PLAN_ITEMS : A.n_items;
+        uint64_t acc = 0;
+        for (uint64_t i = a0 + (threadIdx.x & 63); i < a1; i += 64) {
+          const BItem it = A.items[i];
+          if (item_ok(A, it) && it.in_len > SMALL_MAX && (int)it.dir == d) acc += item_units(A, it);
+        }
+        return wave_sum_u64(acc);
+      });
       if (threadIdx.x == 0) pfx[d] = b;
     }
   }
@@ -187,18 +227,25 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
   uint32_t nlarge = 0;
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) nlarge += units[j] != 0;
-  uint32_t ctot[2];
+  uint32_t ctot[4];
   const uint32_t c0 = block_excl_scan<PLAN_WG>(nlarge | (ntiny[0] << 16), ctot[0], scr[2]);
   const uint32_t c1 = block_excl_scan<PLAN_WG>(ntiny[1], ctot[1], scr[3]);
+  const uint32_t c2 = block_excl_scan<PLAN_WG>(ncls[0] | (ncls[1] << 16), ctot[2], scr[4]);
+  const uint32_t c3 = block_excl_scan<PLAN_WG>(ncls[2] | (ncls[3] << 16), ctot[3], scr[5]);
   if (threadIdx.x == 0) {
     const uint32_t want[3] = {ctot[0] & 0xFFFFu, ctot[0] >> 16, ctot[1]};
     unsigned long long* ctr[3] = {&A.ws->acc, ntiny_of(A.ws, 0), ntiny_of(A.ws, 1)};
 #pragma unroll
     for (int q = 0; q < 3; ++q) lbase[q] = want[q] ? atomicAdd(ctr[q], (unsigned long long)want[q]) : 0ull;
+    const uint32_t wc[NCLS] = {ctot[2] & 0xFFFFu, ctot[2] >> 16, ctot[3] & 0xFFFFu, ctot[3] >> 16};
+#pragma unroll
+    for (int q = 0; q < NCLS; ++q) cbase[q] = wc[q] ? atomicAdd(&A.cls_count[q], (unsigned long long)wc[q]) : 0ull;
   }
   __syncthreads();
   unsigned long long slot = lbase[0] + (c0 & 0xFFFFu);
   unsigned long long tslot[2] = {lbase[1] + (c0 >> 16), lbase[2] + c1};
+  unsigned long long cslot[NCLS] = {cbase[0] + (c2 & 0xFFFFu), cbase[1] + (c2 >> 16), cbase[2] + (c3 & 0xFFFFu),
+                                    cbase[3] + (c3 >> 16)};
   uint64_t run[2] = {pfx[0] + local[0], pfx[1] + local[1]};
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) {
@@ -206,6 +253,11 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
     if (i >= A.n_items) break;
     const uint32_t tj = (tiny >> (2 * j)) & 3u;
     if (tj) A.tiny[tj - 1][tslot[tj - 1]++] = (uint32_t)i;
+    const uint32_t cj = (cls >> (3 * j)) & 7u;
+#pragma unroll
+    for (int q = 0; q < NCLS; ++q) {
+      if (cj == (uint32_t)q + 1u) A.small[q][cslot[q]++] = (uint32_t)i;
+    }
     const int d = (int)dir[j];
     const uint64_t start = run[d];
     A.unit_start[i] = start;
@@ -229,12 +281,6 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
     const uint64_t o = __shfl_xor(v, d, 64);
     v = o < v ? o : v;
   }
-  return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
   return v;
 }
 
@@ -594,21 +640,56 @@ __global__ void __launch_bounds__(TINY_WG) k_batch_tiny(BatchArgs A) {
   else rows_u16_to_u8(A, it, mine, res, st, alo, ahi);
 }
 
-// At most 96 VGPRs: five waves per SIMD (left to itself the compiler takes 102 and four).
+// Persistent over the segments of the large items of one direction: workgroup g takes
+// segments g, g + G, g + 2G, ... (G = its grid).  A look-back that waits too long
+// recomputes its predecessor's aggregate, so no order of workgroups can stall it.
+template <int DIR>
+__global__ void __launch_bounds__(BWG) __attribute__((amdgpu_waves_per_eu(4))) k_batch_large(BatchArgs A) {
+  typedef typename std::conditional<DIR == 0, Seg8Smem<BWG, BS8>, Seg16Smem<BWG, BS16>>::type Smem;
+  __shared__ __attribute__((aligned(16))) Smem sm;
+  if (!plan_ok(A)) return;
+  const uint64_t total = uniform_u64(ld_agent(total_of(A.ws, DIR)));
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const uint32_t i = __builtin_amdgcn_readfirstlane(A.unit_item[DIR][t]);
+    const BItem it = A.items[i];
+    const Launch L = item_launch(A, it, i);
+    const uint64_t seg = t - A.unit_start[i];
+    if constexpr (DIR == 0) {
+      uint32_t x[BS8][4];
+      load_seg8<BWG, BS8>(L, seg, x);
+      seg_u8_to_u16<BWG, BS8>(L, seg, sm, x);
+    } else {
+      uint32_t x[BS16][4];
+      load_seg16<BWG, BS16>(L, seg, x);
+      seg_u16_to_u8<BWG, BS16>(L, seg, sm, x);
+    }
+    __syncthreads();  // the stage is reused by the next segment
+  }
+}
+
+// One wave per wave-walked item, taken from the length-class lists in order, the
+// longest class first: the waves of a workgroup get strings of about the same length
+// and the longest strings start first.  Waves past the lists' end exit; the list
+// lengths are read through the scalar cache, so those waves leave quickly.  (A
+// persistent loop over the lists instead needs more than 96 VGPRs and spills.)  At
+// most 96 VGPRs: five waves per SIMD.
+constexpr int SMALL_WG = 256;
 __global__ void __launch_bounds__(SMALL_WG) __attribute__((amdgpu_waves_per_eu(5))) k_batch_small(BatchArgs A) {
   constexpr int NW = SMALL_WG / 64;
   __shared__ __attribute__((aligned(16))) uint8_t smem[NW * WSTAGE];
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const uint64_t i = (uint64_t)blockIdx.x * NW + wid;
-  if (i >= A.n_items) return;
+  uint64_t k = (uint64_t)blockIdx.x * NW + wid;
+  const unsigned long long* __restrict__ cc = A.cls_count;
+  int c = 0;
+  for (; c < NCLS; ++c) {
+    const uint64_t n = cc[c];
+    if (k < n) break;
+    k -= n;
+  }
+  if (c == NCLS) return;
+  const uint32_t i = __builtin_amdgcn_readfirstlane(A.small[c][k]);
   const BItem it = A.items[i];
   Result* res = A.results + i;
-  if (!item_ok(A, it)) {
-    if ((threadIdx.x & 63) == 0) write_result(res, ST_INVALID_ARG, 0, 0);
-    return;
-  }
-  if (it.in_len > SMALL_MAX) return;  // a large item: k_batch_large and k_batch_fin
-  if (A.rows && item_tiny(it)) return;  // k_batch_tiny
   uint8_t* st = smem + wid * WSTAGE;
   const uintptr_t alo = (uintptr_t)A.in, ahi = (uintptr_t)(A.in + A.in_bytes);
   if (it.dir == 0)
@@ -617,30 +698,6 @@ __global__ void __launch_bounds__(SMALL_WG) __attribute__((amdgpu_waves_per_eu(5
   else
     wave_u16_to_u8(reinterpret_cast<const uint16_t*>(A.in + it.in_off), it.in_len, A.out + it.out_off,
                    it.out_cap, st, res, alo, ahi);
-}
-
-// One workgroup per segment of the long strings of one direction (grid: the plan's
-// bound on segments; workgroups past the real count exit at once).  Workgroups are
-// dispatched in order, so every predecessor a look-back waits for is running or done.
-template <int DIR>
-__global__ void __launch_bounds__(BWG) __attribute__((amdgpu_waves_per_eu(DIR == 1 ? 6 : 1))) k_batch_large(BatchArgs A) {
-  const uint64_t t = blockIdx.x;
-  if (t >= ld_agent(total_of(A.ws, DIR)) || !plan_ok(A)) return;
-  const uint32_t i = __builtin_amdgcn_readfirstlane(A.unit_item[DIR][t]);
-  const BItem it = A.items[i];
-  const Launch L = item_launch(A, it, i);
-  const uint64_t seg = t - A.unit_start[i];
-  if (DIR == 0) {
-    __shared__ __attribute__((aligned(16))) Seg8Smem<BWG, BS8> sm;
-    uint32_t x[BS8][4];
-    load_seg8<BWG, BS8>(L, seg, x);
-    seg_u8_to_u16<BWG, BS8>(L, seg, sm, x);
-  } else {
-    __shared__ __attribute__((aligned(16))) Seg16Smem<BWG, BS16> sm;
-    uint32_t x[BS16][4];
-    load_seg16<BWG, BS16>(L, seg, x);
-    seg_u16_to_u8<BWG, BS16>(L, seg, sm, x);
-  }
 }
 
 constexpr int FIN_WG = 256;
@@ -687,6 +744,8 @@ struct BatchWs {
   uint32_t* unit_item[2] = {nullptr, nullptr};
   uint32_t* large = nullptr;
   uint32_t* tiny[2] = {nullptr, nullptr};
+  uint32_t* small[utfx_dev::NCLS] = {nullptr, nullptr, nullptr, nullptr};
+  unsigned long long* cls_count = nullptr;
   unsigned long long* plan_status[2] = {nullptr, nullptr};
   uint64_t cap_items = 0, cap_units = 0;
   uint64_t launches = 0;
@@ -736,6 +795,11 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   const uint64_t o_start = o; o += al(ni * 8);
   const uint64_t o_err = o; o += al(ni * 8);
   const uint64_t o_large = o; o += al(ni * 4);
+  const uint64_t o_ccount = o; o += al(utfx_dev::NCLS * 8);
+  uint64_t o_small[utfx_dev::NCLS];
+  for (int c = 0; c < utfx_dev::NCLS; ++c) {
+    o_small[c] = o; o += al(ni * 4);
+  }
   uint64_t o_plan[2], o_status[2], o_uitem[2], o_tiny[2];
   for (int d = 0; d < 2; ++d) {
     o_tiny[d] = o; o += al(ni * 4);
@@ -753,6 +817,8 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   b.unit_start = reinterpret_cast<unsigned long long*>(m + o_start);
   b.item_err = reinterpret_cast<unsigned long long*>(m + o_err);
   b.large = reinterpret_cast<uint32_t*>(m + o_large);
+  b.cls_count = reinterpret_cast<unsigned long long*>(m + o_ccount);
+  for (int c = 0; c < utfx_dev::NCLS; ++c) b.small[c] = reinterpret_cast<uint32_t*>(m + o_small[c]);
   for (int d = 0; d < 2; ++d) {
     b.tiny[d] = reinterpret_cast<uint32_t*>(m + o_tiny[d]);
     b.plan_status[d] = reinterpret_cast<unsigned long long*>(m + o_plan[d]);
@@ -764,7 +830,7 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   return batch_ws_clear(b, s);
 }
 
-inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_cus,
+inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_cus, uint32_t dbg,
                              const uint8_t* in,
                              uint64_t in_bytes, uint8_t* out, uint64_t out_bytes, const utfx_item* d_items,
                              uint32_t n_items, uint64_t total_in_units, utfx_result* d_results, char* err,
@@ -800,6 +866,8 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   A.unit_start = b.unit_start;
   A.item_err = b.item_err;
   A.large = b.large;
+  A.cls_count = b.cls_count;
+  for (int c = 0; c < NCLS; ++c) A.small[c] = b.small[c];
   for (int d = 0; d < 2; ++d) {
     A.tiny[d] = b.tiny[d];
     A.status[d] = b.status[d];
@@ -810,18 +878,23 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   A.total_in = total_in_units;
   // rows pay off on many strings; a call with few (a serving step) saves the launch
   A.rows = n_items >= TINY_ROWS_MIN;
+  A.dbg = dbg;
   const uint32_t plan_blocks = (n_items + PLAN_WG * PLAN_ITEMS - 1) / (PLAN_WG * PLAN_ITEMS);
-  const uint32_t small_blocks = (n_items + SMALL_WG / 64 - 1) / (SMALL_WG / 64);
   // tiny waves: at most n/4 + 2 (four items per wave, per direction, rounded up)
   const uint32_t tiny_blocks = (uint32_t)((n_items / 4 + 2 + TINY_WG / 64 - 1) / (TINY_WG / 64));
-  const uint32_t large_blocks = (uint32_t)(cap_units < 0x7FFFFFFFull ? cap_units : 0x7FFFFFFFull);
+  // the large segments: persistent grids of two workgroups per CU (128 VGPRs; the
+  // UTF-8 stage is 64 KiB), fewer for a call with few segments; the wave-walked items:
+  // one wave each
+  const uint64_t cus = (uint64_t)(num_cus > 0 ? num_cus : 256);
+  const uint64_t large_blocks = cap_units < 2 * cus ? cap_units : 2 * cus;
+  const uint64_t small_blocks = (n_items + SMALL_WG / 64 - 1) / (SMALL_WG / 64);
   const uint32_t fin_blocks = n_items < 1024 ? n_items : 1024;
-  hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ws);
+  hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ws, b.cls_count);
   hipLaunchKernelGGL(k_batch_plan, dim3(plan_blocks), dim3(PLAN_WG), 0, s, A);
   if (A.rows) hipLaunchKernelGGL(k_batch_tiny, dim3(tiny_blocks), dim3(TINY_WG), 0, s, A);
-  hipLaunchKernelGGL(k_batch_small, dim3(small_blocks), dim3(SMALL_WG), 0, s, A);
-  hipLaunchKernelGGL(k_batch_large<0>, dim3(large_blocks), dim3(BWG), 0, s, A);
-  hipLaunchKernelGGL(k_batch_large<1>, dim3(large_blocks), dim3(BWG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_small, dim3((uint32_t)small_blocks), dim3(SMALL_WG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_large<0>, dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
+  hipLaunchKernelGGL(k_batch_large<1>, dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
   hipLaunchKernelGGL(k_batch_fin, dim3(fin_blocks), dim3(FIN_WG), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) {

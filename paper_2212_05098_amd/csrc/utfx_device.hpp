@@ -65,6 +65,7 @@ struct Launch {
   uint32_t wg;          // threads per workgroup of the main kernel
   uint32_t be;          // UTF-16 side is big-endian: input words (UTF-16 -> UTF-8) or
                         // output words (UTF-8 -> UTF-16) have their bytes swapped
+  uint32_t dbg;         // look-back delay injection (debug_delay); 0 = off
 };
 
 // Swaps the bytes of both 16-bit halves (UTF-16BE <-> UTF-16LE code units).
@@ -224,49 +225,112 @@ __device__ __forceinline__ void publish_aggregate(unsigned long long* status, ui
   st_agent(&status[tile * STATUS_STRIDE], tag | ((tile == 0 ? FLAG_PFX : FLAG_AGG) << VAL_BITS) | agg);
 }
 
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Aggregate of segment `seg` recomputed by the calling wave from the input: the sum of
+// chunk_count(q0) over the segment's chunks [seg * seg_units, (seg + 1) * seg_units),
+// chunk_units units apart (the same chunks and masks the segment's own workgroup
+// counted).  Returns the same value in every lane.
+template <class F>
+__device__ __forceinline__ uint64_t wave_segment_sum(uint64_t seg, uint64_t seg_units, uint32_t chunk_units,
+                                                     const F& chunk_count) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t acc = 0;
+  const uint64_t end = (seg + 1) * seg_units;
+  for (uint64_t q0 = seg * seg_units + (uint64_t)lane * chunk_units; q0 < end; q0 += 64ull * chunk_units)
+    acc += chunk_count(q0);
+  return wave_sum_u64(acc);
+}
+
+// Polls of one look-back window before the waiting wave stops relying on its
+// predecessors' workgroups and computes the nearest missing aggregate itself; after it
+// has done so once, it waits only LB_PATIENCE_AFTER polls for the next.
+constexpr uint32_t LB_PATIENCE = 64;
+constexpr uint32_t LB_PATIENCE_AFTER = 4;
+
 // Decoupled look-back (Merrill & Garland), run by one whole wave after the tile has
 // published its aggregate.  Each round loads the status words of the 128 nearest
 // unaccounted predecessors (2 per lane, lane 0 nearest) in one coalesced access; if
 // every one of them up to the nearest inclusive prefix is ready, their values are
 // summed and the walk ends at that prefix (or continues 128 tiles further back).
 // Then the tile's own inclusive prefix is published.  Returns the exclusive prefix
-// (same value in every lane).  Every predecessor has been dispatched before this tile
-// or will be once smaller workgroups finish, so every wait ends; the watchdog only
-// guards against a broken invariant and reports it through ws->fault.
+// (same value in every lane).
+//
+// Every wait ends whatever order the hardware runs workgroups in: a predecessor that
+// has not published after LB_PATIENCE polls gets its aggregate from agg_of(index) (a
+// whole-wave call that recomputes it from the input, e.g. with wave_segment_sum), so
+// the walk never depends on another workgroup being resident.  Tile 0's aggregate is
+// also its inclusive prefix.  The watchdog stays as a guard against a broken
+// invariant and reports through ws->fault.
 constexpr int LB_PER_LANE = 2;
+template <class AggOf>
 __device__ __forceinline__ uint64_t lookback_wave(unsigned long long* status, uint64_t tile, uint64_t agg,
-                                                  uint32_t epoch, WsHeader* ws) {
+                                                  uint32_t epoch, WsHeader* ws, const AggOf& agg_of) {
   const int lane = threadIdx.x & 63;
   const unsigned long long tag = (unsigned long long)(epoch & EPOCH_MASK) << (VAL_BITS + 2);
   if (tile == 0) return 0;
   uint64_t excl = 0;
   int64_t top = (int64_t)tile - 1;  // nearest predecessor not yet accounted for
   uint32_t spins = 0;
+  uint32_t patience = LB_PATIENCE;
+  // aggregates this wave computed for the words of its lane in the current window
+  bool fx[LB_PER_LANE];
+  uint64_t fv[LB_PER_LANE];
+#pragma unroll
+  for (int j = 0; j < LB_PER_LANE; ++j) {
+    fx[j] = false;
+    fv[j] = 0;
+  }
   while (true) {
     unsigned long long s[LB_PER_LANE];
 #pragma unroll
     for (int j = 0; j < LB_PER_LANE; ++j) {
       const int64_t idx = top - (LB_PER_LANE * lane + j);
       s[j] = (idx >= 0) ? ld_agent(&status[idx * STATUS_STRIDE]) : (tag | (FLAG_PFX << VAL_BITS));
+      if (fx[j]) s[j] = tag | ((idx == 0 ? FLAG_PFX : FLAG_AGG) << VAL_BITS) | fv[j];
     }
+    bool ok[LB_PER_LANE];
     int lane_first = LB_PER_LANE;  // first inclusive prefix among this lane's words
-    bool ok_upto = true;           // every word up to it (or all four) is ready
 #pragma unroll
     for (int j = LB_PER_LANE - 1; j >= 0; --j) {
-      const bool ok = (s[j] >> (VAL_BITS + 2)) == (epoch & EPOCH_MASK) && ((s[j] >> VAL_BITS) & 3) != 0;
-      const bool pfx = ok && ((s[j] >> VAL_BITS) & 3) == FLAG_PFX;
-      if (pfx) lane_first = j;
-    }
-#pragma unroll
-    for (int j = 0; j < LB_PER_LANE; ++j) {
-      const bool ok = (s[j] >> (VAL_BITS + 2)) == (epoch & EPOCH_MASK) && ((s[j] >> VAL_BITS) & 3) != 0;
-      if (j <= lane_first && !ok) ok_upto = false;
+      ok[j] = (s[j] >> (VAL_BITS + 2)) == (epoch & EPOCH_MASK) && ((s[j] >> VAL_BITS) & 3) != 0;
+      if (ok[j] && ((s[j] >> VAL_BITS) & 3) == FLAG_PFX) lane_first = j;
     }
     const unsigned long long pm = __ballot(lane_first < LB_PER_LANE);
     const int F = pm ? __builtin_ctzll(pm) : 64;  // lane holding the nearest prefix
-    const bool need_ok = (lane <= F) ? ok_upto : true;
-    if (__ballot(!need_ok)) {
-      if (++spins > SPIN_LIMIT) {
+    // the first word of this lane that is needed (at or before the nearest prefix) and
+    // not ready (LB_PER_LANE: none)
+    int miss = LB_PER_LANE;
+#pragma unroll
+    for (int j = LB_PER_LANE - 1; j >= 0; --j) {
+      const bool needed = lane < F || (lane == F && j <= lane_first);
+      if (needed && !ok[j]) miss = j;
+    }
+    const unsigned long long mm = __ballot(miss < LB_PER_LANE);
+    if (mm) {
+      ++spins;
+      if (spins >= patience) {
+        // compute the nearest missing aggregate here instead of waiting for it
+        const int L0 = __builtin_ctzll(mm);
+        const int j0 = __shfl(miss, L0, 64);
+        const int64_t idx = top - (LB_PER_LANE * L0 + j0);
+        const uint64_t v = agg_of((uint64_t)idx);
+#pragma unroll
+        for (int j = 0; j < LB_PER_LANE; ++j) {
+          if (lane == L0 && j == j0) {
+            fx[j] = true;
+            fv[j] = v;
+          }
+        }
+        patience = LB_PATIENCE_AFTER;
+        spins = 0;
+        continue;
+      }
+      if (spins > SPIN_LIMIT) {
         if (lane == 0) atomicOr(&ws->fault, 1u);
         break;
       }
@@ -279,15 +343,30 @@ __device__ __forceinline__ uint64_t lookback_wave(unsigned long long* status, ui
       const bool take = (lane < F) || (lane == F && j <= lane_first);
       v += take ? (uint64_t)(s[j] & VAL_MASK) : 0;
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    excl += v;
+    excl += wave_sum_u64(v);
     if (F < 64) break;
     top -= 64 * LB_PER_LANE;
     spins = 0;
+#pragma unroll
+    for (int j = 0; j < LB_PER_LANE; ++j) fx[j] = false;
   }
   if (lane == 0) st_agent(&status[tile * STATUS_STRIDE], tag | (FLAG_PFX << VAL_BITS) | (excl + agg));
   return excl;
+}
+
+// Debug mode (look-back delay injection): holds back the publication of one segment in
+// sixteen, chosen by a hash of its index, by a pseudo-random number of s_sleep(127)
+// rounds below 64 * dbg (about 3.4 us each), so that look-backs meet late and missing
+// predecessors.  dbg = 0 (the default) skips it.
+__device__ __forceinline__ void debug_delay(uint32_t dbg, uint64_t seg) {
+  if (dbg == 0) return;
+  uint32_t h = (uint32_t)seg * 0x9E3779B1u + (uint32_t)(seg >> 32);
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  if ((h & 15u) != 0) return;
+  const uint32_t n = (h >> 4) % (64u * dbg);
+  for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(127);
 }
 
 // Inclusive prefix of a finished tile (valid after every tile of the launch is done).

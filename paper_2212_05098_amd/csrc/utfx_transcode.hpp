@@ -296,7 +296,10 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);  // contains a barrier
 
-  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+  if (threadIdx.x == 0) {
+    debug_delay(L.dbg, seg);
+    publish_aggregate(L.status, seg, seg_total, epoch);
+  }
 
   // ---- phase B: per chunk, validate + decode + scatter into the stage
 #pragma unroll
@@ -319,7 +322,14 @@ __device__ __forceinline__ void seg_u8_to_u16(const Launch& L, uint64_t seg, Seg
   }
   if (wid == 0) {
     // the look-back runs after the wave's own work, when predecessors are likely done
-    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws, [&](uint64_t j) {
+      return wave_segment_sum(j, SEGB, 16, [&](uint64_t q) {
+        uint32_t xx[4], mm[4];
+        load8(L, q, xx);
+        range_masks(q, lo, hi, mm);
+        return (uint64_t)count8(xx, mm);
+      });
+    });
     if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
@@ -617,7 +627,10 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, wtot);
 
-  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+  if (threadIdx.x == 0) {
+    debug_delay(L.dbg, seg);
+    publish_aggregate(L.status, seg, seg_total, epoch);
+  }
 
   // ---- phase B
 #pragma unroll
@@ -644,7 +657,14 @@ __device__ __forceinline__ void seg_u16_to_u8(const Launch& L, uint64_t seg, Seg
   }
   if (wid == 0) {
     // the look-back runs after the wave's own work, when predecessors are likely done
-    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws, [&](uint64_t j) {
+      return wave_segment_sum(j, SEGW, 8, [&](uint64_t q) {
+        uint32_t xx[4], mm[4];
+        load16(L, q, xx);
+        word_masks(q, lo, hi, mm);
+        return (uint64_t)count16(xx, mm);
+      });
+    });
     if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();

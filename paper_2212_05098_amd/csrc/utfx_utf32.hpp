@@ -149,7 +149,10 @@ __global__ void __launch_bounds__(WG) k_u8_to_u32(Launch L) {
   if (threadIdx.x == 0) sm.werr = NO_ERR;
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, sm.wtot);  // contains a barrier
-  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+  if (threadIdx.x == 0) {
+    debug_delay(L.dbg, seg);
+    publish_aggregate(L.status, seg, seg_total, epoch);
+  }
 
   // ---- validate, decode, scatter into the stage
 #pragma unroll
@@ -171,7 +174,14 @@ __global__ void __launch_bounds__(WG) k_u8_to_u32(Launch L) {
     }
   }
   if (wid == 0) {
-    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws, [&](uint64_t j) {
+      return wave_segment_sum(j, SEGB, 16, [&](uint64_t q) {
+        uint32_t xx[4], mm[4];
+        load8(L, q, xx);
+        range_masks(q, lo, hi, mm);
+        return (uint64_t)count8_chars(xx, mm);
+      });
+    });
     if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
@@ -301,7 +311,10 @@ __global__ void __launch_bounds__(WG) k_u32_to(Launch L) {
   if (threadIdx.x == 0) sm.werr = NO_ERR;
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, sm.wtot);  // contains a barrier
-  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+  if (threadIdx.x == 0) {
+    debug_delay(L.dbg, seg);
+    publish_aggregate(L.status, seg, seg_total, epoch);
+  }
 
   // ---- encode into the stage; the first invalid unit of a chunk is exact
 #pragma unroll
@@ -345,7 +358,13 @@ __global__ void __launch_bounds__(WG) k_u32_to(Launch L) {
     }
   }
   if (wid == 0) {
-    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws, [&](uint64_t j) {
+      return wave_segment_sum(j, SEGU, 4, [&](uint64_t q) {
+        uint32_t xx[4], fbx;
+        load32(L, q, xx);
+        return (uint64_t)count32<OUT16>(xx, q, lo, hi, false, &fbx);
+      });
+    });
     if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
@@ -462,7 +481,10 @@ __global__ void __launch_bounds__(WG) k_u16_to_u32(Launch L) {
   if (threadIdx.x == 0) sm.werr = NO_ERR;
   uint32_t off[S];
   const uint32_t seg_total = segment_offsets<WG, S>(c, off, sm.wtot);  // contains a barrier
-  if (threadIdx.x == 0) publish_aggregate(L.status, seg, seg_total, epoch);
+  if (threadIdx.x == 0) {
+    debug_delay(L.dbg, seg);
+    publish_aggregate(L.status, seg, seg_total, epoch);
+  }
 
 #pragma unroll
   for (int k = 0; k < S; ++k) {
@@ -501,7 +523,13 @@ __global__ void __launch_bounds__(WG) k_u16_to_u32(Launch L) {
     }
   }
   if (wid == 0) {
-    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws);
+    const uint64_t b = lookback_wave(L.status, seg, seg_total, epoch, L.ws, [&](uint64_t j) {
+      return wave_segment_sum(j, SEGW, 8, [&](uint64_t q) {
+        uint32_t xx[4];
+        load16(L, q, xx);
+        return (uint64_t)count16_chars(xx, q, lo, hi, false);
+      });
+    });
     if (lane == 0) sm.seg_base = b;
   }
   __syncthreads();
