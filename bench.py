@@ -41,7 +41,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size-mib", type=int, default=256, help="bytes per buffer (MiB)")
     ap.add_argument("--rotate", type=int, default=3, help="device copies per input")
-    ap.add_argument("--cpu-sample-mib", type=int, default=256, help="oracle sample per case (MiB)")
+    ap.add_argument("--cpu-sample-mib", type=int, default=128, help="oracle sample per C2 case (MiB)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profiles", default="ascii,latin,cjk,emoji")
     ap.add_argument("--u8", default="", help="UTF-8 -> UTF-16 launch: tile_bytes,tiles_per_segment")
@@ -52,7 +52,7 @@ def main():
                     help="strings of the batch run with one launch each, for the comparison")
     ap.add_argument("--serve-rates", default="20000,50000,100000,200000,500000",
                     help="offered request rates of the serving runs (empty = skip)")
-    ap.add_argument("--serve-seconds", type=float, default=0.5)
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="trace length per offered rate (s)")
     ap.add_argument("--serve-inflight", type=int, default=3, help="server steps in flight")
     ap.add_argument("--small-calls", type=int, default=200, help="64 KiB synchronous calls timed (0 = skip)")
     ap.add_argument("--run-mib", type=int, default=64, help="run-structured buffers per profile (MiB, 0 = skip)")
@@ -129,17 +129,29 @@ def main():
             call(i, w)
     torch.cuda.synchronize()
 
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
-          for _ in range(args.steps)]
+    def evpair():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # per call: events around the whole call (main kernel + finalisation) on the stream,
+    # and kernel-only events that the library records immediately before and after the
+    # main kernel (hipExtLaunchKernel)
+    ev = [[evpair() for _ in cases] for _ in range(args.steps)]
+    kev = [[evpair() for _ in cases] for _ in range(args.steps)]
+    for row in kev:
+        for a_, b_ in row:
+            a_.record(stream)
+            b_.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         for i in range(len(cases)):
             ev[s][i][0].record(stream)
+            ctx.set_kernel_events(*kev[s][i])
             call(i, s + 1)
             ev[s][i][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ctx.set_kernel_events(None, None)
     rs = utfx.results_from_tensor(res)
     assert all(r.status == utfx.OK for r in rs[: len(cases)])
 
@@ -148,30 +160,40 @@ def main():
     per_case = []
     for i, c in enumerate(cases):
         ms = [ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]
-        avg = sum(ms) / len(ms)
+        kms = [kev[s][i][0].elapsed_time(kev[s][i][1]) for s in range(args.steps)]
+        avg, kavg = sum(ms) / len(ms), sum(kms) / len(kms)
         per_case.append({
             "profile": c[0], "dir": "utf8->utf16le" if c[1] == 0 else "utf16le->utf8",
-            "in_bytes": c[5], "out_bytes": c[6], "ms_avg": round(avg, 4), "ms_min": round(min(ms), 4),
-            "in_GBps": round(c[5] / (avg * 1e6), 1),
-            "hbm_frac": round((c[5] + c[6]) / (avg * 1e6) / HBM_PEAK_GBS, 4),
+            "kernel": "k_u8_to_u16" if c[1] == 0 else "k_u16_to_u8",
+            "in_bytes": c[5], "out_bytes": c[6],
+            "kernel_ms_avg": round(kavg, 4), "kernel_ms_min": round(min(kms), 4),
+            "call_ms_avg": round(avg, 4),
+            "in_GBps": round(c[5] / (kavg * 1e6), 1),
+            "hbm_frac": round((c[5] + c[6]) / (kavg * 1e6) / HBM_PEAK_GBS, 4),
         })
-    # dominant kernel: the transcode kernel with the most device time per step, over all
-    # its launches (one per profile); per launch = averages over those launches
-    by_dir = {}
-    for i, c in enumerate(cases):
-        t, b, n = by_dir.get(c[1], (0.0, 0, 0))
-        by_dir[c[1]] = (t + per_case[i]["ms_avg"], b + c[5] + c[6], n + 1)
-    dom_dir = max(by_dir, key=lambda d: by_dir[d][0])
-    dom_ms, dom_bytes, dom_n = by_dir[dom_dir]
-    launch_ms = dom_ms / dom_n
-    launch_bytes = dom_bytes / dom_n
-    achieved = launch_bytes / (launch_ms * 1e6)
-    kernel = "k_u8_to_u16" if dom_dir == synth.DIR_8TO16 else "k_u16_to_u8"
-    case_name = "%s, one launch per profile (%s)" % ("utf8->utf16le" if dom_dir == synth.DIR_8TO16 else
+    # per transcode kernel (one launch per profile): algorithmic bytes per launch and
+    # kernel-only duration per launch, both averaged over its launches
+    kernels = {}
+    for d in (synth.DIR_8TO16, synth.DIR_16TO8):
+        pcs = [pc for pc, c in zip(per_case, cases) if c[1] == d]
+        if not pcs:
+            continue
+        launch_ms = sum(pc["kernel_ms_avg"] for pc in pcs) / len(pcs)
+        launch_bytes = sum(pc["in_bytes"] + pc["out_bytes"] for pc in pcs) / len(pcs)
+        name = pcs[0]["kernel"]
+        kernels[name] = {
+            "dir": d, "total_ms": sum(pc["kernel_ms_avg"] for pc in pcs), "launch_ms": launch_ms,
+            "launch_bytes": launch_bytes, "achieved": launch_bytes / (launch_ms * 1e6),
+            "frac_by_profile": {pc["profile"]: pc["hbm_frac"] for pc in pcs},
+        }
+    kernel = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    dom = kernels[kernel]
+    achieved = dom["achieved"]
+    case_name = "%s, one launch per profile (%s)" % ("utf8->utf16le" if dom["dir"] == synth.DIR_8TO16 else
                                                      "utf16le->utf8", ",".join(profiles))
     for pc in per_case:
-        log("%-6s %-14s %8.3f ms  in %7.1f GB/s  hbm %.3f" % (pc["profile"], pc["dir"], pc["ms_avg"],
-                                                               pc["in_GBps"], pc["hbm_frac"]))
+        log("%-6s %-14s kernel %8.4f ms (call %8.4f)  in %7.1f GB/s  hbm %.3f" % (
+            pc["profile"], pc["dir"], pc["kernel_ms_avg"], pc["call_ms_avg"], pc["in_GBps"], pc["hbm_frac"]))
 
     # practical ceiling: a plain device-to-device copy of one input buffer
     csrc = cases[0][3][0].view(torch.uint8)
@@ -200,38 +222,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        import oracle as O
-
-        sample = args.cpu_sample_mib * MIB
-        tot_in = 0
-        tot_t = 0.0
-        for c in cases:
-            host = c[2]
-            if c[1] == synth.DIR_8TO16:
-                part = host[:sample]
-                part = np.frombuffer(bytes(part).decode("utf-8", errors="ignore").encode("utf-8"), np.uint8)
-                best = None
-                for _ in range(2):
-                    ta = time.perf_counter()
-                    O.utf8_to_utf16le(part)
-                    tb = time.perf_counter()
-                    best = tb - ta if best is None else min(best, tb - ta)
-                tot_in += part.size
-            else:
-                part = host[: sample // 2]
-                if part.size and 0xD800 <= part[-1] < 0xDC00:
-                    part = part[:-1]
-                best = None
-                for _ in range(2):
-                    ta = time.perf_counter()
-                    O.utf16le_to_utf8(part)
-                    tb = time.perf_counter()
-                    best = tb - ta if best is None else min(best, tb - ta)
-                tot_in += 2 * part.size
-            tot_t += best
-        cpu = {"value": round(tot_in / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d MiB of each of the %d (profile, direction) inputs, cut at a character "
-                             "boundary; best of 2; single thread" % (args.cpu_sample_mib, len(cases))}
+        cpu = cpu_baseline(cases, args.cpu_sample_mib, log)
 
     small = run_small(ctx, log, args.small_calls) if args.small_calls else None
     runs = run_structured(ctx, log, args.run_mib) if args.run_mib else None
@@ -261,8 +252,16 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kernel, "case": case_name,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "algorithmic_bytes": int(launch_bytes), "ms_avg": round(launch_ms, 4),
-                     "traffic": traffic},
+                     "algorithmic_bytes": int(dom["launch_bytes"]), "ms_avg": round(dom["launch_ms"], 4),
+                     "timing": "kernel-only HIP events around each launch of the kernel (hipExtLaunchKernel)",
+                     "frac_by_profile": dom["frac_by_profile"],
+                     "traffic": traffic,
+                     "other_kernels": {k: {"achieved": round(v["achieved"], 1),
+                                           "frac": round(v["achieved"] / HBM_PEAK_GBS, 4),
+                                           "ms_avg": round(v["launch_ms"], 4),
+                                           "algorithmic_bytes": int(v["launch_bytes"]),
+                                           "frac_by_profile": v["frac_by_profile"]}
+                                       for k, v in kernels.items() if k != kernel}},
         "device_copy_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
         "per_case": per_case,
@@ -275,6 +274,81 @@ def main():
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def cpu_baseline(cases, sample_mib, log):
+    """The oracle timed on this host by its C harness (steady clock inside C, threads
+    pinned to the CPUs of the affinity mask, fastest of 3 repetitions after a warm-up,
+    the input cut at character boundaries for several threads): on a bounded sample of
+    the C2 buffers with 1 thread and with every CPU of the affinity mask, plus the 64 KiB
+    buffer (C1), a validation-stress sample (C3) and the batch (C4, in run_batch).  The
+    all-CPU result of every sample must equal the 1-thread result."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2212_05098_amd import synth
+
+    n_cpu = len(os.sched_getaffinity(0))
+    sample = sample_mib * MIB
+    t1_s = tn_s = 0.0
+    nbytes = 0
+    used = 1
+    for c in cases:
+        host = c[2]
+        if c[1] == synth.DIR_8TO16:
+            part = host[:sample]
+            if part.size < host.size:  # cut before the last character that starts in the sample
+                lead = part.size - 1
+                while lead > 0 and (int(part[lead]) & 0xC0) == 0x80:
+                    lead -= 1
+                part = part[:lead]
+            op, nb = O.TIME_U8_TO_U16, part.size
+        else:
+            part = host[: sample // 2]
+            if part.size and 0xD800 <= part[-1] < 0xDC00:
+                part = part[:-1]
+            op, nb = O.TIME_U16_TO_U8, 2 * part.size
+        one = O.time_buffer(op, part, threads=1, reps=3)
+        alln = O.time_buffer(op, part, threads=0, reps=3)
+        assert tuple(alln.result) == tuple(one.result), (c[0], c[1], alln.result, one.result)
+        assert alln.result.status == 0
+        t1_s += one.seconds
+        tn_s += alln.seconds
+        nbytes += nb
+        used = alln.threads
+    out = {"value": round(nbytes / tn_s / 1e9, 3), "unit": "GB/s", "cores": used, "kind": "oracle",
+           "sample": "first %d MiB of each of the %d C2 (profile, direction) buffers, cut at a character "
+                     "boundary; C harness, steady clock, fastest of 3 after a warm-up; %d pinned threads "
+                     "(every CPU of the affinity mask), input split at character boundaries" %
+                     (sample_mib, len(cases), used),
+           "single_thread": {"value": round(nbytes / t1_s / 1e9, 3), "unit": "GB/s", "cores": 1},
+           "affinity_cpus": n_cpu}
+    log("oracle C2 sample: %.3f GB/s on 1 thread, %.3f GB/s on %d threads" %
+        (out["single_thread"]["value"], out["value"], used))
+    # C1: the 64 KiB buffer, UTF-8 -> UTF-16LE and back
+    d1 = synth.config1_buffer()
+    a = O.time_buffer(O.TIME_U8_TO_U16, d1, threads=1, reps=20)
+    w = a.out
+    b = O.time_buffer(O.TIME_U16_TO_U8, w, threads=1, reps=20)
+    out["c1_64KiB"] = {"utf8_to_utf16le_us": round(a.seconds * 1e6, 1), "utf16le_to_utf8_us": round(b.seconds * 1e6, 1),
+                       "cores": 1}
+    # C3: validation stress samples at the 1e-3 rate, transcode and validate, both directions
+    st = {}
+    rng = synth.rng_for(0, 3, 1)
+    inj8 = synth.inject_utf8("cjk", 32 * MIB, 1e-3, rng)
+    inj16 = synth.inject_utf16("mixed4", 16 * MIB, 1e-3, rng)
+    for name, op, data in (("utf8->utf16le", O.TIME_U8_TO_U16, inj8.data), ("validate utf8", O.TIME_VALIDATE_U8, inj8.data),
+                           ("utf16le->utf8", O.TIME_U16_TO_U8, inj16.data),
+                           ("validate utf16le", O.TIME_VALIDATE_U16, inj16.data)):
+        one = O.time_buffer(op, data, threads=1, reps=3)
+        alln = O.time_buffer(op, data, threads=0, reps=3)
+        assert tuple(alln.result) == tuple(one.result) and one.result.status != 0
+        st[name] = {"ms_to_verdict_1": round(one.seconds * 1e3, 4), "ms_to_verdict_all": round(alln.seconds * 1e3, 4),
+                    "first_error": int(one.result.count)}
+    out["c3_stress_1e-3"] = {"sample": "32 MiB CJK UTF-8 and 32 MiB mixed UTF-16LE with errors at rate 1e-3; "
+                                       "the oracle stops at the first error, so its time is the time to the verdict",
+                             "cases": st}
+    return out
 
 
 def run_small(ctx, log, reps=200):
@@ -510,6 +584,45 @@ def run_batch(args, ctx, log):
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     ms = np.array(ms)
+    out_bytes = int(sum(2 * r.written if b.direction[j] == 0 else r.written for j, r in enumerate(rs)))
+    # the same call captured into a hipGraph and replayed
+    ctx.capture_begin()
+    try:
+        assert ctx.batch_run(d_in, d_out, items, n, total, res) == utfx.OK
+    finally:
+        g = ctx.capture_end()
+    g.launch()
+    torch.cuda.synchronize()
+    gms = []
+    for _ in range(args.batch_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms.append(e0.elapsed_time(e1))
+    g.close()
+    gms = np.array(gms)
+    rs_graph = utfx.results_from_tensor(res)
+    # parity of every string's result with the oracle's batched reference, and the
+    # oracle timed on the same batch (1 thread, every CPU of the affinity mask)
+    oracle_leg = None
+    if not args.no_cpu:
+        import oracle as O
+
+        items_np = O.items_array(b.in_off, b.in_len, out_off, caps, b.direction)
+        o_bytes = int(out_off[-1] + sizes[-1] + 64)
+        t1, used1, ores, n_ok = O.time_batch(b.arena, items_np, o_bytes, threads=1, reps=3)
+        tn, usedn, ores_n, _ = O.time_batch(b.arena, items_np, o_bytes, threads=0, reps=3)
+        got = np.array([(r.status, r.count, r.written) for r in rs_graph], dtype=np.int64)
+        want = np.stack([ores["status"].astype(np.int64), ores["count"].astype(np.int64),
+                         ores["written"].astype(np.int64)], axis=1)
+        mism = int(np.count_nonzero(np.any(got != want, axis=1)))
+        assert np.array_equal(ores_n["count"], ores["count"])
+        oracle_leg = {"GBps_1": round(in_bytes / t1 / 1e9, 3), "GBps_all": round(in_bytes / tn / 1e9, 3),
+                      "cores": usedn, "result_mismatches": mism, "checked": n}
+        log("batch oracle: %.3f GB/s on 1 thread, %.3f GB/s on %d; %d of %d results differ from the GPU's" %
+            (oracle_leg["GBps_1"], oracle_leg["GBps_all"], usedn, mism, n))
     # one launch per string on a sample (the first k strings), same kernels' results
     k = min(args.single_sample, n)
     one = utfx.result_tensor(1)
@@ -533,17 +646,61 @@ def run_batch(args, ctx, log):
     batch_ms = float(np.median(ms))
     log("batch: %.3f ms median per call (%.1f GB/s); one launch per string: %.2f us each" %
         (batch_ms, in_bytes / (batch_ms * 1e6), per_string_us))
-    return {"strings": n, "input_bytes": in_bytes, "errors": n_err, "reps": args.batch_reps,
+    graph_ms = float(np.median(gms))
+    log("batch graph replay: %.3f ms median per call (%.1f GB/s)" % (graph_ms, in_bytes / (graph_ms * 1e6)))
+    return {"strings": n, "input_bytes": in_bytes, "output_bytes": out_bytes, "errors": n_err,
+            "reps": args.batch_reps,
             "ms_p50": round(batch_ms, 4), "ms_p99": round(float(np.percentile(ms, 99)), 4),
             "ms_min": round(float(ms.min()), 4), "GBps": round(in_bytes / (batch_ms * 1e6), 2),
+            "hbm_frac": round((in_bytes + out_bytes) / (batch_ms * 1e6) / HBM_PEAK_GBS, 4),
+            "graph_ms_p50": round(graph_ms, 4), "graph_ms_p99": round(float(np.percentile(gms, 99)), 4),
+            "graph_GBps": round(in_bytes / (graph_ms * 1e6), 2),
+            "oracle": oracle_leg,
             "one_launch_per_string_us": round(per_string_us, 2) if k else None, "one_launch_sample": k,
             "speedup_vs_one_launch_per_string": round(per_string_us * n / (batch_ms * 1e3), 1) if k else None}
 
 
+def check_served(w, res, out_bytes_at, log, label):
+    """The served results and outputs of the workload's checked sample against the
+    oracle, one request at a time: returns (checked, mismatches).  out_bytes_at(off, n)
+    gives n bytes of the sample's output buffer at byte offset off."""
+    import ctypes
+
+    import numpy as np
+
+    import oracle as O
+
+    bad = 0
+    for idx, off in zip(w.checked.tolist(), w.check_off.tolist()):
+        d = int(w.dirs[idx]) & 1
+        n = int(w.len_units[idx])
+        raw = ctypes.string_at(int(w.data_ptrs[idx]), n * (2 if d else 1)) if n else b""
+        if d == 0:
+            want, ref = O.utf8_to_utf16le(np.frombuffer(raw, dtype=np.uint8))
+            unit = 2
+        else:
+            want, ref = O.utf16le_to_utf8(np.frombuffer(raw, dtype=np.uint16))
+            unit = 1
+        r = res[idx]
+        ok = (int(r["status"]), int(r["count"]), int(r["written"])) == tuple(want)
+        if ok and want.written:
+            got = np.frombuffer(out_bytes_at(off, int(want.written) * unit), dtype=ref.dtype)
+            ok = np.array_equal(got, ref[: want.written])
+        bad += 0 if ok else 1
+    if bad:
+        log("%s: %d of %d sampled requests differ from the oracle" % (label, bad, w.checked.size))
+    return int(w.checked.size), bad
+
+
 def run_serving(args, log):
     """Continuous-batching server (--serve-inflight steps in flight) on Poisson traces at
-    each offered rate, and one launch per request at the lowest rate; each server
-    first replays an unrecorded 0.2 s warm-up trace."""
+    each offered rate: host-resident requests (latency includes PCIe both ways),
+    device-resident requests (payload and output in device memory, only results cross
+    PCIe), and one launch per request.  Each server first replays an unrecorded 0.2 s
+    warm-up trace.  A 1 % sample of each run's requests gets its own output buffer and
+    is checked against the oracle."""
+    import ctypes
+
     import numpy as np
     import torch
 
@@ -552,13 +709,18 @@ def run_serving(args, log):
 
     t0 = time.time()
     pool = serve.PayloadPool(mib_per_pool=32, seed=0)
+    # the same payloads in device memory, for the device-resident runs
+    dev_pool = {k: t.cuda() for k, t in pool.buf.items()}
     scratch = torch.empty(64 << 20, dtype=torch.uint8, pin_memory=True)
-    check = torch.empty(64 << 20, dtype=torch.uint8, pin_memory=True)
+    check = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
+    d_scratch = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    d_check = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     log("serving: payload pool in %.1fs" % (time.time() - t0))
     rates = [float(r) for r in args.serve_rates.split(",") if r]
     out = {"server": {"inflight": args.serve_inflight, "arena_in_MiB": 256, "arena_out_MiB": 768,
                       "device_cap_GiB": 32},
-           "duration_s": args.serve_seconds, "runs": []}
+           "duration_s": args.serve_seconds, "check_every": 100, "runs": [], "device_resident": [],
+           "one_launch_per_request": []}
     srv = utfx.Server(arena_in_bytes=256 << 20, arena_out_bytes=768 << 20, max_items=1 << 18,
                       inflight=args.serve_inflight)
 
@@ -569,30 +731,61 @@ def run_serving(args, log):
         w = serve.make_workload(pool, 200000, 0.2, seed=1000, scratch_ptr=scratch.data_ptr(), check_every=50,
                                 check_ptr=check.data_ptr(), check_bytes=check.numel())
         server.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
+        data, outs, dirs = to_device(w)
+        server.replay(w.arrival_ns, data, w.len_units, dirs, outs, w.out_caps)
+
+    def host_reader(off, n):
+        return ctypes.string_at(check.data_ptr() + off, n)
+
+    def to_device(w):
+        """Device pointers for the same requests: payloads in the device copy of the
+        pool, outputs in device buffers (the checked sample at the same offsets)."""
+        data = w.data_ptrs.copy()
+        for key, t in pool.buf.items():
+            lo, hi = t.data_ptr(), t.data_ptr() + t.numel()
+            m = (w.data_ptrs >= lo) & (w.data_ptrs < hi)
+            data[m] = w.data_ptrs[m] - lo + dev_pool[key].data_ptr()
+        outs = np.full(w.out_ptrs.size, d_scratch.data_ptr(), dtype=np.uint64)
+        outs[w.checked] = d_check.data_ptr() + w.check_off.astype(np.uint64)
+        return data, outs, (w.dirs | utfx.SERVER_DEVICE_BUFFERS).astype(np.uint32)
+
+    def run(server, w, rate, device, label):
+        if device:
+            data, outs, dirs = to_device(w)
+            lat, res, wall = server.replay(w.arrival_ns, data, w.len_units, dirs, outs, w.out_caps)
+            host_check = d_check.cpu().numpy()
+            reader = lambda off, n: host_check[off:off + n].tobytes()  # noqa: E731
+        else:
+            lat, res, wall = server.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
+            reader = host_reader
+        row = serve.summarize(w, lat, wall, rate)
+        row["ok"] = int(np.sum(res["status"] == 0))
+        row["parity_sample"], row["parity_mismatches"] = check_served(w, res, reader, log, label)
+        row["parity_sample_ok"] = row["parity_mismatches"] == 0
+        log("%s %7.0f req/s: %d requests in %.2f s, p50 %.1f us, p99 %.1f us, %.2f GB/s; sample %d, %d mismatches" %
+            (label, rate, row["requests"], w.arrival_ns[-1] / 1e9 if w.arrival_ns.size else 0.0, row["p50_us"],
+             row["p99_us"], row["delivered_GBps"], row["parity_sample"], row["parity_mismatches"]))
+        return row
 
     warm(srv)
     for k, rate in enumerate(rates):
         w = serve.make_workload(pool, rate, args.serve_seconds, seed=k, scratch_ptr=scratch.data_ptr(),
-                                check_every=1000, check_ptr=check.data_ptr(), check_bytes=check.numel())
-        lat, res, wall = srv.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
-        ok = int(np.sum(res["status"] == 0))
-        row = serve.summarize(w, lat, wall, rate)
-        row["ok"] = ok
-        out["runs"].append(row)
-        log("serving %7.0f req/s: %d requests, p50 %.1f us, p99 %.1f us, %.2f GB/s" %
-            (rate, row["requests"], row["p50_us"], row["p99_us"], row["delivered_GBps"]))
+                                check_every=100, check_ptr=check.data_ptr(), check_bytes=check.numel())
+        out["runs"].append(run(srv, w, rate, False, "serving"))
+        out["device_resident"].append(run(srv, w, rate, True, "serving (device-resident)"))
     srv.close()
-    # one launch per request (max_items = 1) at the lowest rate, for comparison
+    # one launch per request (max_items = 1): it cannot keep up with the higher rates,
+    # so its traces are cut to at most 100,000 requests (stated per run)
     one = utfx.Server(arena_in_bytes=64 << 20, arena_out_bytes=192 << 20, max_items=1, inflight=2)
     warm(one)
-    rate = rates[0]
-    w = serve.make_workload(pool, rate, min(args.serve_seconds, 0.25), seed=99, scratch_ptr=scratch.data_ptr(),
-                            check_every=1000, check_ptr=check.data_ptr(), check_bytes=check.numel())
-    lat, res, wall = one.replay(w.arrival_ns, w.data_ptrs, w.len_units, w.dirs, w.out_ptrs, w.out_caps)
+    for k, rate in enumerate(rates):
+        dur = min(args.serve_seconds, 100000.0 / rate)
+        w = serve.make_workload(pool, rate, dur, seed=k, scratch_ptr=scratch.data_ptr(), check_every=100,
+                                check_ptr=check.data_ptr(), check_bytes=check.numel())
+        row = run(one, w, rate, False, "one launch per request")
+        row["duration_s"] = round(dur, 3)
+        out["one_launch_per_request"].append(row)
     one.close()
-    row = serve.summarize(w, lat, wall, rate)
-    out["one_launch_per_request"] = row
-    log("one launch per request %7.0f req/s: p50 %.1f us, p99 %.1f us" % (rate, row["p50_us"], row["p99_us"]))
     return out
 
 

@@ -110,8 +110,12 @@ utfx_status utfx_set_kernel_events(utfx_ctx *ctx, void *start_event, void *stop_
  *             registers and its output in LDS, so they take only these pairs:
  *             UTF-8 -> UTF-16 (4096, 2, 4 or 8), (8192, 2 or 4); UTF-16 -> UTF-8
  *             (4096 or 8192, 2, 4 or 8);
- * wgs_per_cu: 0..16, recorded with the other values; no kernel of this version uses it
- *             (every launch is one workgroup per segment).
+ * wgs_per_cu: 0..16, the most workgroups of the operation's main kernel resident on one
+ *             CU at a time (0 = as many as its registers and LDS allow).  A launch
+ *             asks for unused dynamic LDS so that no more fit; a value at or above
+ *             what the kernel reaches anyway changes nothing.  It shapes overlap
+ *             (loads, decode, look-back and stores of different workgroups), not
+ *             results.
  * Returns UTFX_E_INVALID_ARG for an unsupported value. */
 typedef enum {
   UTFX_OP_UTF8_TO_UTF16 = 0,
@@ -329,7 +333,7 @@ typedef struct {
 
 /* Runs the batch: the arenas hold in_bytes and out_bytes bytes; d_items (device,
  * n_items entries) describe the strings, d_results (device, n_items entries) receive
- * one result each.  Strings of up to 16,384 units
+ * one result each.  Strings of up to 16,384 units (the wave_max_units tunable below)
  * are transcoded by one wavefront each; longer ones are cut into segments, one
  * workgroup each, with a look-back that ends at the string's first segment (sections 6
  * and 7 per string).  The plan is built on the device, so
@@ -343,6 +347,17 @@ typedef struct {
 utfx_status utfx_batch_run(utfx_ctx *ctx, const uint8_t *in_arena, size_t in_bytes, uint8_t *out_arena,
                            size_t out_bytes, const utfx_item *d_items, uint32_t n_items,
                            uint64_t total_in_units, utfx_result *d_results);
+/* Tunables of the batched call, picked by the autotuner (they shape the schedule, never
+ * the results): wave_max_units (1024 .. 262144, default 16384): strings of at most this
+ * many units are walked by one wavefront, longer ones take segments;
+ * large_tiles_per_segment (2 or 4, default 4): a segment is that many 8 KiB tiles of
+ * UTF-8 (4096 words of UTF-16); large_wgs_per_cu (1 or 2, default 2): persistent
+ * segment workgroups launched per CU.  The "more than 16,384 units" above reads "more
+ * than wave_max_units".  UTFX_E_INVALID_ARG for other values. */
+utfx_status utfx_set_batch_tuning(utfx_ctx *ctx, uint32_t wave_max_units, uint32_t large_tiles_per_segment,
+                                  uint32_t large_wgs_per_cu);
+utfx_status utfx_get_batch_tuning(const utfx_ctx *ctx, uint32_t *wave_max_units,
+                                  uint32_t *large_tiles_per_segment, uint32_t *large_wgs_per_cu);
 
 /* ---- HIP graphs: record a sequence of calls once, replay it many times ---------- */
 /* Between utfx_capture_begin and utfx_capture_end, the context's _async calls and
@@ -402,7 +417,12 @@ void utfx_server_destroy(utfx_server *srv);
 const char *utfx_server_last_error(const utfx_server *srv);
 /* Queues one request: len_units input units at host address data, direction dir
  * (0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8), output to host address out with room
- * for out_cap_units output units. */
+ * for out_cap_units output units.  With UTFX_SERVER_DEVICE_BUFFERS or-ed into dir, data
+ * and out are device addresses instead (a device-resident request): a kernel on the
+ * slot's stream gathers the payload into the step's input arena and another copies the
+ * valid prefix of the output (`written` units, at most out_cap_units) to out, so only
+ * the 24-byte result crosses PCIe. */
+#define UTFX_SERVER_DEVICE_BUFFERS 0x100u
 utfx_status utfx_server_submit(utfx_server *srv, uint64_t tag, const void *data, uint64_t len_units,
                                uint32_t dir, void *out, uint64_t out_cap_units);
 /* Reports up to max_done completions (drains a slot only when all its requests fit)

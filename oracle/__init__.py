@@ -95,7 +95,9 @@ _lib: Optional[ctypes.CDLL] = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        path = build()
+        # UTFX_ORACLE_LIB: an already built copy to load instead (the sanitizer test
+        # points it at the AddressSanitizer / UndefinedBehaviorSanitizer build)
+        path = os.environ.get("UTFX_ORACLE_LIB") or build()
         L = ctypes.CDLL(path)
         p8 = ctypes.c_void_p
         sz = ctypes.c_size_t

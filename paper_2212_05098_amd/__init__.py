@@ -42,6 +42,8 @@ OP_BATCH = 6
 
 DIR_8TO16 = 0
 DIR_16TO8 = 1
+# or-ed into a server request's direction: its payload and output are device memory
+SERVER_DEVICE_BUFFERS = 0x100
 
 
 class CResult(ctypes.Structure):
@@ -122,6 +124,8 @@ def lib() -> ctypes.CDLL:
         "utfx_set_kernel_events": (I, [P, P, P]),
         "utfx_set_tuning": (I, [P, I, U32, U32, U32]),
         "utfx_get_tuning": (I, [P, I, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32)]),
+        "utfx_set_batch_tuning": (I, [P, U32, U32, U32]),
+        "utfx_get_batch_tuning": (I, [P, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32)]),
         "utfx_utf16_length_from_utf8": (CResult, [P, P, Z]),
         "utfx_utf8_length_from_utf16le": (CResult, [P, P, Z]),
         "utfx_validate_utf8": (CResult, [P, P, Z]),
@@ -261,16 +265,30 @@ class Context:
             raise UtfxError("bad tuning %r" % ((op, tile_bytes, tiles_per_segment, wgs_per_cu),))
 
     def load_tuning(self, path=None) -> bool:
-        """Apply a tuning cache written by paper_2212_05098_amd.tune (default: the
-        package's tune_cache.json).  Returns False if there is none."""
+        """Apply the entry for this GPU (architecture, HIP version, CU count) of a tuning
+        cache written by paper_2212_05098_amd.tune (default: the package's
+        tune_cache.json).  Returns False if there is none."""
         from paper_2212_05098_amd import tune
 
-        cache = tune.load(path or tune.DEFAULT_CACHE)
-        if not cache:
+        entry = tune.load(path or tune.DEFAULT_CACHE)
+        if not entry:
             return False
-        for op, (tile, seg, wgs) in cache["ops"].items():
+        for op, (tile, seg, wgs) in entry["ops"].items():
             self.set_tuning(int(op), int(tile), int(seg), int(wgs))
+        if entry.get("batch"):
+            self.set_batch_tuning(*(int(v) for v in entry["batch"]))
         return True
+
+    def set_batch_tuning(self, wave_max_units: int, large_tiles_per_segment: int, large_wgs_per_cu: int):
+        st = self._lib.utfx_set_batch_tuning(self._h, wave_max_units, large_tiles_per_segment, large_wgs_per_cu)
+        if st != OK:
+            raise UtfxError("bad batch tuning %r" % ((wave_max_units, large_tiles_per_segment, large_wgs_per_cu),))
+
+    def get_batch_tuning(self):
+        """(wave_max_units, large_tiles_per_segment, large_wgs_per_cu) of the batched call."""
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        self._lib.utfx_get_batch_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return int(a.value), int(b.value), int(c.value)
 
     def get_tuning(self, op: int):
         """(tile_bytes, tiles_per_segment, wgs_per_cu) of an operation."""

@@ -36,6 +36,7 @@ struct utfx_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int num_cus = 256;
+  uint32_t cu_lds = 160u << 10;           // LDS bytes of one CU
   WsHeader* ws = nullptr;                 // device header
   unsigned long long* status = nullptr;   // device status words
   uint64_t cap_tiles = 0;
@@ -50,6 +51,7 @@ struct utfx_ctx {
   uint32_t seg_tiles[UTFX_OP_COUNT_];
   uint32_t wgs_per_cu[UTFX_OP_COUNT_];
   BatchWs batch;                          // batched-path workspace
+  BatchTuning batch_tuning;               // utfx_set_batch_tuning
   // graph capture: while capturing, calls are recorded on cap_stream
   bool capturing = false;
   hipStream_t user_stream = nullptr;
@@ -217,8 +219,46 @@ struct Launcher;
 // context has none or is capturing.  Set by run() for the duration of one launch.
 thread_local hipEvent_t t_kev_start = nullptr, t_kev_stop = nullptr;
 
-#define UTFX_KLAUNCH(K, GRID, WG, S, L) \
-  hipExtLaunchKernelGGL(K, GRID, dim3(WG), 0, S, t_kev_start, t_kev_stop, 0, L)
+// Residency cap of the launch being made (workgroups per CU, 0 = none) and the LDS of
+// one CU; set by run() like the events.
+thread_local uint32_t t_wgs_per_cu = 0;
+thread_local uint32_t t_cu_lds = 0;
+
+// Dynamic LDS (unused by the kernel) that caps its residency at `wgs` workgroups per
+// CU: with it, one workgroup takes more than 1/(wgs + 1) of the CU's LDS, so at most
+// wgs fit.  0 when wgs is 0 or the kernel's own LDS already allows no more.  The
+// kernel's static LDS is looked up once per kernel.
+uint32_t lds_pad(const void* kernel, uint32_t wgs, uint32_t cu_lds) {
+  if (!wgs || !cu_lds) return 0;
+  static std::mutex mu;
+  static const void* keys[64];
+  static uint32_t vals[64];
+  static int nk = 0;
+  uint32_t stat = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    int i = 0;
+    while (i < nk && keys[i] != kernel) ++i;
+    if (i == nk) {
+      hipFuncAttributes a;
+      if (hipFuncGetAttributes(&a, kernel) != hipSuccess) return 0;
+      if (nk < 64) {
+        keys[nk] = kernel;
+        vals[nk] = (uint32_t)a.sharedSizeBytes;
+        ++nk;
+      }
+      stat = (uint32_t)a.sharedSizeBytes;
+    } else {
+      stat = vals[i];
+    }
+  }
+  const uint32_t need = ((cu_lds / (wgs + 1) + 1) + 511) & ~511u;
+  return need > stat ? need - stat : 0;
+}
+
+#define UTFX_KLAUNCH(K, GRID, WG, S, L)                                                                   \
+  hipExtLaunchKernelGGL(K, GRID, dim3(WG), lds_pad(reinterpret_cast<const void*>(&K), t_wgs_per_cu, t_cu_lds), \
+                        S, t_kev_start, t_kev_stop, 0, L)
 
 UTFX_DEFINE_LAUNCH(launch_len8, k_len8)
 UTFX_DEFINE_LAUNCH(launch_len16, k_len16)
@@ -424,6 +464,10 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
     t_kev_start = c->kev_start;
     t_kev_stop = c->kev_stop;
   }
+  t_wgs_per_cu = (kind == LEN8 || kind == LEN16 || kind == VAL8 || kind == VAL16 || kind == U8U16 || kind == U16U8)
+                     ? c->wgs_per_cu[op]
+                     : 0u;
+  t_cu_lds = c->cu_lds;
   switch (kind) {
     case LEN8: e = launch_len8(wg, L.ntiles, L, c->stream); break;
     case LEN16: e = launch_len16(wg, L.ntiles, L, c->stream); break;
@@ -454,6 +498,7 @@ utfx_status run(utfx_ctx* c, Kind kind, const void* in, uint64_t n, void* out, u
       break;
   }
   t_kev_start = t_kev_stop = nullptr;
+  t_wgs_per_cu = 0;
   if (e == hipSuccess) e = launch_fin(kind, wg, L, c->stream);
   if (e != hipSuccess) {
     set_err(c, "kernel launch", e);
@@ -825,6 +870,10 @@ utfx_status utfx_create(utfx_ctx** out, void* hip_stream) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
       c->num_cus = cus;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) == hipSuccess &&
+        lds > 0)
+      c->cu_lds = (uint32_t)lds;
   }
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->d_result), sizeof(Result));
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(Result), hipHostMallocDefault);
@@ -882,6 +931,26 @@ utfx_status utfx_set_tuning(utfx_ctx* c, int op, uint32_t tile_bytes, uint32_t t
   c->tile_bytes[op] = tile_bytes;
   c->seg_tiles[op] = tiles_per_segment;
   c->wgs_per_cu[op] = wgs_per_cu;
+  return UTFX_OK;
+}
+
+utfx_status utfx_set_batch_tuning(utfx_ctx* c, uint32_t wave_max_units, uint32_t large_tiles_per_segment,
+                                  uint32_t large_wgs_per_cu) {
+  if (!c || wave_max_units < 1024 || wave_max_units > (1u << 18) ||
+      (large_tiles_per_segment != 2 && large_tiles_per_segment != 4) || large_wgs_per_cu < 1 || large_wgs_per_cu > 2)
+    return UTFX_E_INVALID_ARG;
+  c->batch_tuning.small_max = wave_max_units;
+  c->batch_tuning.bs = large_tiles_per_segment;
+  c->batch_tuning.large_wgs = large_wgs_per_cu;
+  return UTFX_OK;
+}
+
+utfx_status utfx_get_batch_tuning(const utfx_ctx* c, uint32_t* wave_max_units, uint32_t* large_tiles_per_segment,
+                                  uint32_t* large_wgs_per_cu) {
+  if (!c) return UTFX_E_INVALID_ARG;
+  if (wave_max_units) *wave_max_units = (uint32_t)c->batch_tuning.small_max;
+  if (large_tiles_per_segment) *large_tiles_per_segment = c->batch_tuning.bs;
+  if (large_wgs_per_cu) *large_wgs_per_cu = c->batch_tuning.large_wgs;
   return UTFX_OK;
 }
 
@@ -972,7 +1041,7 @@ utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
   const void* mem = c->batch.mem;
-  utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, c->dbg, in_arena,
+  utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, c->dbg, c->batch_tuning, in_arena,
                              in_bytes, out_arena, out_bytes, d_items, n_items, total_in_units, d_results, c->err,
                              sizeof(c->err));
   if (c->batch.mem != mem) c->ws_gen++;

@@ -6,7 +6,7 @@
 //                  the length sum and the fault flag (one thread, so the call needs no
 //                  memset and can be captured into a graph);
 //   k_batch_plan   per item: check its descriptor (an invalid one gets its result
-//                  here) and, for a large item (more than SMALL_MAX input units), count
+//                  here) and, for a large item (more than small_max input units), count
 //                  its segments; exclusive scans of the counts over items, one per
 //                  direction (workgroup scan + decoupled look-back across workgroups);
 //                  each large item writes the segment -> item map of its segments and
@@ -38,15 +38,16 @@ struct BItem {  // utfx_item
   uint32_t dir, pad;
 };
 
-// Items up to this many input units are transcoded by one wave.
+// Items up to this many input units are transcoded by one wave (the default of the
+// tunable BatchArgs::small_max).
 constexpr uint64_t SMALL_MAX = 16384;
 // Length classes of the wave-walked items, by the steps (1 KiB of UTF-8 or 512 words of
 // UTF-16) a wave takes: class 0 = more than 8 steps, 1 = 5..8, 2 = 3..4, 3 = 1..2.
 constexpr int NCLS = 4;
 // Geometry of the large-item segments (workgroup size, tiles per segment per direction).
-constexpr int BWG = 512, BS8 = 4, BS16 = 4;
-constexpr uint64_t BSEG8 = 16ull * BWG * BS8;   // UTF-8 bytes per segment
-constexpr uint64_t BSEG16 = 8ull * BWG * BS16;  // UTF-16 words per segment
+// Geometry of the large-item segments: 512-thread workgroups of bs tiles (2 or 4,
+// tunable), so bs * 8 KiB of UTF-8 or bs * 4096 words of UTF-16 per segment.
+constexpr int BWG = 512;
 constexpr int PLAN_WG = 256;
 constexpr int PLAN_ITEMS = 4;  // items per plan thread
 
@@ -73,6 +74,8 @@ struct BatchArgs {
   uint64_t cap_units;
   uint64_t total_in;                 // the caller's bound on the sum of in_len
   uint32_t rows;                     // tiny items go to k_batch_tiny (large calls only)
+  uint64_t small_max;                // items above this many units take segments
+  uint32_t bs;                       // tiles per large-item segment (2 or 4)
   uint32_t dbg;                      // look-back delay injection (debug_delay); 0 = off
 };
 
@@ -108,7 +111,7 @@ __device__ __forceinline__ bool item_ok(const BatchArgs& A, const BItem& it) {
 __device__ __forceinline__ uint64_t item_units(const BatchArgs& A, const BItem& it) {
   const uint32_t unit = it.dir ? 2u : 1u;
   const uint64_t mis = (((uintptr_t)(A.in + it.in_off)) & 15) / unit;
-  const uint64_t seg = it.dir ? BSEG16 : BSEG8;
+  const uint64_t seg = (it.dir ? 8ull : 16ull) * BWG * A.bs;
   return (mis + it.in_len + 1 + seg - 1) / seg;
 }
 
@@ -127,8 +130,8 @@ __device__ __forceinline__ Launch item_launch(const BatchArgs& A, const BItem& i
   L.status = A.status[it.dir] + A.unit_start[i] * STATUS_STRIDE;
   L.result = A.results + i;
   L.ntiles = item_units(A, it);
-  L.seg_units = it.dir ? BSEG16 : BSEG8;
-  L.seg = it.dir ? BS16 : BS8;
+  L.seg_units = (it.dir ? 8ull : 16ull) * BWG * A.bs;
+  L.seg = A.bs;
   L.wg = BWG;
   L.be = 0;
   L.dbg = A.dbg;
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
       const BItem it = A.items[i];
       if (item_ok(A, it)) {
         len += it.in_len;
-        if (it.in_len > SMALL_MAX) {
+        if (it.in_len > A.small_max) {
           units[j] = (uint32_t)item_units(A, it);
           dir[j] = it.dir;
           tsum[it.dir] += units[j];
@@ -215,7 +218,7 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
         uint64_t acc = 0;
         for (uint64_t i = a0 + (threadIdx.x & 63); i < a1; i += 64) {
           const BItem it = A.items[i];
-          if (item_ok(A, it) && it.in_len > SMALL_MAX && (int)it.dir == d) acc += item_units(A, it);
+          if (item_ok(A, it) && it.in_len > A.small_max && (int)it.dir == d) acc += item_units(A, it);
         }
         return wave_sum_u64(acc);
       });
@@ -319,7 +322,7 @@ __device__ __forceinline__ bool wave_load8(const Launch& L, uint64_t c0, uint64_
   return full;
 }
 
-// One wave transcodes a UTF-8 string of n bytes (n <= SMALL_MAX) 1 KiB at a time; the
+// One wave transcodes a UTF-8 string of n bytes (any n; n <= small_max here) 1 KiB at a time; the
 // next step's bytes are loaded while the current step is decoded and stored.
 // stage: the wave's LDS (WSTAGE bytes); [alo, ahi): the input arena.  A chunk with any
 // lane partly outside the string runs the masked path on every lane, so the wave
@@ -428,7 +431,7 @@ __device__ __forceinline__ bool wave_load16(const Launch& L, uint64_t c0, uint64
   return full;
 }
 
-// One wave transcodes a UTF-16LE string of n words (n <= SMALL_MAX) 512 words at a
+// One wave transcodes a UTF-16LE string of n words (any n; n <= small_max here) 512 words at a
 // time, loading the next step while the current one is encoded and stored.
 __device__ __forceinline__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, uint8_t* out, uint64_t cap, uint8_t* stage,
                                Result* res, uintptr_t alo, uintptr_t ahi) {
@@ -643,9 +646,9 @@ __global__ void __launch_bounds__(TINY_WG) k_batch_tiny(BatchArgs A) {
 // Persistent over the segments of the large items of one direction: workgroup g takes
 // segments g, g + G, g + 2G, ... (G = its grid).  A look-back that waits too long
 // recomputes its predecessor's aggregate, so no order of workgroups can stall it.
-template <int DIR>
+template <int DIR, int BS>
 __global__ void __launch_bounds__(BWG) __attribute__((amdgpu_waves_per_eu(4))) k_batch_large(BatchArgs A) {
-  typedef typename std::conditional<DIR == 0, Seg8Smem<BWG, BS8>, Seg16Smem<BWG, BS16>>::type Smem;
+  typedef typename std::conditional<DIR == 0, Seg8Smem<BWG, BS>, Seg16Smem<BWG, BS>>::type Smem;
   __shared__ __attribute__((aligned(16))) Smem sm;
   if (!plan_ok(A)) return;
   const uint64_t total = uniform_u64(ld_agent(total_of(A.ws, DIR)));
@@ -655,13 +658,13 @@ __global__ void __launch_bounds__(BWG) __attribute__((amdgpu_waves_per_eu(4))) k
     const Launch L = item_launch(A, it, i);
     const uint64_t seg = t - A.unit_start[i];
     if constexpr (DIR == 0) {
-      uint32_t x[BS8][4];
-      load_seg8<BWG, BS8>(L, seg, x);
-      seg_u8_to_u16<BWG, BS8>(L, seg, sm, x);
+      uint32_t x[BS][4];
+      load_seg8<BWG, BS>(L, seg, x);
+      seg_u8_to_u16<BWG, BS>(L, seg, sm, x);
     } else {
-      uint32_t x[BS16][4];
-      load_seg16<BWG, BS16>(L, seg, x);
-      seg_u16_to_u8<BWG, BS16>(L, seg, sm, x);
+      uint32_t x[BS][4];
+      load_seg16<BWG, BS>(L, seg, x);
+      seg_u16_to_u8<BWG, BS>(L, seg, sm, x);
     }
     __syncthreads();  // the stage is reused by the next segment
   }
@@ -830,7 +833,15 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   return batch_ws_clear(b, s);
 }
 
+// Tunables of the batched call (utfx_set_batch_tuning).
+struct BatchTuning {
+  uint64_t small_max = utfx_dev::SMALL_MAX;  // largest string one wave walks
+  uint32_t bs = 4;                           // tiles per large-item segment: 2 or 4
+  uint32_t large_wgs = 2;                    // persistent large-segment workgroups per CU: 1 or 2
+};
+
 inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_cus, uint32_t dbg,
+                             const BatchTuning& tun,
                              const uint8_t* in,
                              uint64_t in_bytes, uint8_t* out, uint64_t out_bytes, const utfx_item* d_items,
                              uint32_t n_items, uint64_t total_in_units, utfx_result* d_results, char* err,
@@ -841,10 +852,10 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
     snprintf(err, errlen, "null pointer");
     return UTFX_E_INVALID_ARG;
   }
-  // segments of large items per direction: an item of n > SMALL_MAX units has at most
-  // n / BSEG + 2, and there are at most total / SMALL_MAX such items
-  const uint64_t seg_min = BSEG16 < BSEG8 ? BSEG16 : BSEG8;
-  const uint64_t cap_units = total_in_units / seg_min + 2 * (total_in_units / SMALL_MAX) + 2;
+  // segments of large items per direction: an item of n > small_max units has at most
+  // n / seg + 2, and there are at most total / small_max such items
+  const uint64_t seg_min = 8ull * BWG * tun.bs;  // the UTF-16 segment, in units, is the smaller
+  const uint64_t cap_units = total_in_units / seg_min + 2 * (total_in_units / tun.small_max) + 2;
   if (capturing && (n_items > b.cap_items || cap_units > b.cap_units || b.launches >= (1ull << 24))) {
     snprintf(err, errlen, "batch workspace must grow during graph capture; make the same call once before capturing");
     return UTFX_E_INVALID_ARG;
@@ -878,23 +889,30 @@ inline utfx_status batch_run(BatchWs& b, hipStream_t s, bool capturing, int num_
   A.total_in = total_in_units;
   // rows pay off on many strings; a call with few (a serving step) saves the launch
   A.rows = n_items >= TINY_ROWS_MIN;
+  A.small_max = tun.small_max;
+  A.bs = tun.bs;
   A.dbg = dbg;
   const uint32_t plan_blocks = (n_items + PLAN_WG * PLAN_ITEMS - 1) / (PLAN_WG * PLAN_ITEMS);
   // tiny waves: at most n/4 + 2 (four items per wave, per direction, rounded up)
   const uint32_t tiny_blocks = (uint32_t)((n_items / 4 + 2 + TINY_WG / 64 - 1) / (TINY_WG / 64));
-  // the large segments: persistent grids of two workgroups per CU (128 VGPRs; the
-  // UTF-8 stage is 64 KiB), fewer for a call with few segments; the wave-walked items:
-  // one wave each
+  // the large segments: persistent grids of tun.large_wgs workgroups per CU (at most two
+  // are resident: 128 VGPRs), fewer for a call with few segments; the wave-walked
+  // items: one wave each
   const uint64_t cus = (uint64_t)(num_cus > 0 ? num_cus : 256);
-  const uint64_t large_blocks = cap_units < 2 * cus ? cap_units : 2 * cus;
+  const uint64_t large_blocks = cap_units < tun.large_wgs * cus ? cap_units : tun.large_wgs * cus;
   const uint64_t small_blocks = (n_items + SMALL_WG / 64 - 1) / (SMALL_WG / 64);
   const uint32_t fin_blocks = n_items < 1024 ? n_items : 1024;
   hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, b.ws, b.cls_count);
   hipLaunchKernelGGL(k_batch_plan, dim3(plan_blocks), dim3(PLAN_WG), 0, s, A);
   if (A.rows) hipLaunchKernelGGL(k_batch_tiny, dim3(tiny_blocks), dim3(TINY_WG), 0, s, A);
   hipLaunchKernelGGL(k_batch_small, dim3((uint32_t)small_blocks), dim3(SMALL_WG), 0, s, A);
-  hipLaunchKernelGGL(k_batch_large<0>, dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
-  hipLaunchKernelGGL(k_batch_large<1>, dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
+  if (tun.bs == 2) {
+    hipLaunchKernelGGL((k_batch_large<0, 2>), dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
+    hipLaunchKernelGGL((k_batch_large<1, 2>), dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
+  } else {
+    hipLaunchKernelGGL((k_batch_large<0, 4>), dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
+    hipLaunchKernelGGL((k_batch_large<1, 4>), dim3((uint32_t)large_blocks), dim3(BWG), 0, s, A);
+  }
   hipLaunchKernelGGL(k_batch_fin, dim3(fin_blocks), dim3(FIN_WG), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) {

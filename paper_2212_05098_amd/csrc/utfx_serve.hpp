@@ -11,7 +11,8 @@
 // wait, so that the many small requests never wait behind a multi-MiB transfer.  Completion copies each
 // request's output to its destination and reports its result.  Single-threaded: the
 // caller drives it with utfx_server_progress, or replays a whole arrival trace in real
-// time with utfx_server_replay.
+// time with utfx_server_replay.  Device-resident requests (payload and output in device
+// memory) are gathered into the arena and scattered back by two kernels per step.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -34,7 +35,44 @@ struct Req {
   uint32_t dir;
   uint8_t* out;
   uint64_t out_cap;   // output units
+  bool dev;           // data and out are device addresses
 };
+
+// One copy of a device-resident request: its device buffer, its place in the step's
+// arena, and (scatter) its item and output unit size.
+struct DevCopy {
+  uint64_t ptr;
+  uint64_t off;
+  uint64_t bytes;     // gather: payload bytes; scatter: output capacity in bytes
+  uint32_t item;
+  uint32_t unit;      // output bytes per unit (scatter)
+};
+
+// Gathers device-resident payloads into the step's input arena: one workgroup per
+// request (grid-strided), byte by byte, so any source alignment works.
+__global__ void k_srv_gather(const DevCopy* c, uint32_t n, uint8_t* arena) {
+  for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const DevCopy d = c[k];
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(d.ptr);
+    uint8_t* dst = arena + d.off;
+    for (uint64_t i = threadIdx.x; i < d.bytes; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
+// Copies each device-resident request's valid prefix (written units, at most its
+// capacity; nothing on OUTPUT_TOO_SMALL) from the output arena to its buffer.
+__global__ void k_srv_scatter(const DevCopy* c, uint32_t n, const uint8_t* arena, const utfx_result* res) {
+  for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const DevCopy d = c[k];
+    const utfx_result r = res[d.item];
+    if (r.status == UTFX_E_OUTPUT_TOO_SMALL) continue;
+    uint64_t bytes = r.written * d.unit;
+    if (bytes > d.bytes) bytes = d.bytes;
+    const uint8_t* src = arena + d.off;
+    uint8_t* dst = reinterpret_cast<uint8_t*>(d.ptr);
+    for (uint64_t i = threadIdx.x; i < bytes; i += blockDim.x) dst[i] = src[i];
+  }
+}
 
 struct Slot {
   utfx_ctx* ctx = nullptr;  // own context: batch workspaces are per context
@@ -48,6 +86,10 @@ struct Slot {
   utfx_item* d_items = nullptr;
   utfx_result* h_res = nullptr;
   utfx_result* d_res = nullptr;
+  DevCopy* h_gather = nullptr;      // device-resident requests of the step (pinned)
+  DevCopy* d_gather = nullptr;
+  DevCopy* h_scatter = nullptr;
+  DevCopy* d_scatter = nullptr;
   std::vector<Req> reqs;
   std::vector<uint8_t> direct_out;  // per request: output copied straight to its buffer
   std::vector<uint64_t> direct_in_off, direct_out_off;
@@ -108,6 +150,8 @@ inline void free_slot(Slot& s) {
   if (s.d_out) (void)hipFree(s.d_out);
   if (s.d_items) (void)hipFree(s.d_items);
   if (s.d_res) (void)hipFree(s.d_res);
+  if (s.h_gather) (void)hipHostFree(s.h_gather);
+  if (s.d_gather) (void)hipFree(s.d_gather);
   s = Slot();
 }
 
@@ -122,6 +166,13 @@ inline hipError_t alloc_slot(Slot& s, const utfx_server_config& c) {
   if (e == hipSuccess) e = hipMalloc((void**)&s.d_out, c.arena_out_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&s.d_items, c.max_items * sizeof(utfx_item));
   if (e == hipSuccess) e = hipMalloc((void**)&s.d_res, c.max_items * sizeof(utfx_result));
+  // gather list, then scatter list, in one allocation each side
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_gather, 2 * c.max_items * sizeof(DevCopy), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&s.d_gather, 2 * c.max_items * sizeof(DevCopy));
+  if (e == hipSuccess) {
+    s.h_scatter = s.h_gather + c.max_items;
+    s.d_scatter = s.d_gather + c.max_items;
+  }
   if (e == hipSuccess && utfx_create(&s.ctx, s.stream) != UTFX_OK) e = hipErrorOutOfMemory;
   return e;
 }
@@ -160,10 +211,12 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
   s.direct_in_off.clear();
   s.direct_out_off.clear();
   std::vector<uint32_t> direct_in_idx;
+  uint32_t n_gather = 0, n_scatter = 0;
   while (!q.empty()) {
     const Req& r = q.front();
-    const ReqShape sh{in_bytes(r), out_bytes(r), r.dir, in_bytes(r) >= kDirectMin && is_pinned(r.data),
-                      out_bytes(r) >= kDirectMin && is_pinned(r.out)};
+    ReqShape sh{in_bytes(r), out_bytes(r), r.dir, !r.dev && in_bytes(r) >= kDirectMin && is_pinned(r.data),
+                !r.dev && out_bytes(r) >= kDirectMin && is_pinned(r.out)};
+    sh.device = r.dev;
     Placement pl;
     const PackVerdict v = pk.place(sh, &pl);
     if (v == PACK_REJECT) {
@@ -174,8 +227,16 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
     if (v == PACK_FULL) break;  // no room left in this step
     const uint64_t io = pl.in_off, oo = pl.out_off;
     const bool din = pl.direct_in, dout = pl.direct_out;
-    if (din) direct_in_idx.push_back((uint32_t)s.reqs.size());
-    else if (in_bytes(r)) memcpy(s.h_in + io, r.data, in_bytes(r));
+    if (r.dev) {
+      const uint32_t item = (uint32_t)s.reqs.size();
+      if (in_bytes(r)) s.h_gather[n_gather++] = DevCopy{(uint64_t)(uintptr_t)r.data, io, in_bytes(r), item, 0};
+      if (out_bytes(r))
+        s.h_scatter[n_scatter++] = DevCopy{(uint64_t)(uintptr_t)r.out, oo, out_bytes(r), item, r.dir ? 1u : 2u};
+    } else if (din) {
+      direct_in_idx.push_back((uint32_t)s.reqs.size());
+    } else if (in_bytes(r)) {
+      memcpy(s.h_in + io, r.data, in_bytes(r));
+    }
     utfx_item& it = s.h_items[s.reqs.size()];
     it.in_off = io;
     it.in_len = r.len;
@@ -198,6 +259,15 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
     e = hipMemcpyAsync(s.d_in + s.h_items[k].in_off, s.reqs[k].data, in_bytes(s.reqs[k]), hipMemcpyHostToDevice,
                        s.stream);
   }
+  if (e == hipSuccess && n_gather)
+    e = hipMemcpyAsync(s.d_gather, s.h_gather, n_gather * sizeof(DevCopy), hipMemcpyHostToDevice, s.stream);
+  if (e == hipSuccess && n_scatter)
+    e = hipMemcpyAsync(s.d_scatter, s.h_scatter, n_scatter * sizeof(DevCopy), hipMemcpyHostToDevice, s.stream);
+  if (e == hipSuccess && n_gather) {
+    hipLaunchKernelGGL(k_srv_gather, dim3(n_gather < 1024 ? n_gather : 1024), dim3(256), 0, s.stream, s.d_gather,
+                       n_gather, s.d_in);
+    e = hipGetLastError();
+  }
   utfx_status bs = UTFX_OK;
   if (e == hipSuccess)
     bs = utfx_batch_run(s.ctx, s.d_in, c.arena_in_bytes, s.d_out, c.arena_out_bytes, s.d_items, n, units, s.d_res);
@@ -205,8 +275,13 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
     e = hipMemcpyAsync(s.h_res, s.d_res, n * sizeof(utfx_result), hipMemcpyDeviceToHost, s.stream);
   if (e == hipSuccess && bs == UTFX_OK && out_lo)
     e = hipMemcpyAsync(s.h_out, s.d_out, out_lo, hipMemcpyDeviceToHost, s.stream);
+  if (e == hipSuccess && bs == UTFX_OK && n_scatter) {
+    hipLaunchKernelGGL(k_srv_scatter, dim3(n_scatter < 1024 ? n_scatter : 1024), dim3(256), 0, s.stream,
+                       s.d_scatter, n_scatter, s.d_out, s.d_res);
+    e = hipGetLastError();
+  }
   for (uint32_t k = 0; k < n && e == hipSuccess && bs == UTFX_OK; ++k) {
-    if (s.direct_out[k])
+    if (s.direct_out[k] && !s.reqs[k].dev)
       e = hipMemcpyAsync(s.reqs[k].out, s.d_out + s.h_items[k].out_off, out_bytes(s.reqs[k]), hipMemcpyDeviceToHost,
                          s.stream);
   }
@@ -277,8 +352,9 @@ const char* utfx_server_last_error(const utfx_server* S) { return S ? S->err : "
 utfx_status utfx_server_submit(utfx_server* S, uint64_t tag, const void* data, uint64_t len_units, uint32_t dir,
                                void* out, uint64_t out_cap_units) {
   if (!S || (len_units && !data) || (out_cap_units && !out)) return UTFX_E_INVALID_ARG;
-  const utfx_srv::Req r{tag, static_cast<const uint8_t*>(data), len_units, dir, static_cast<uint8_t*>(out),
-                        out_cap_units};
+  const bool dev = (dir & UTFX_SERVER_DEVICE_BUFFERS) != 0;
+  const utfx_srv::Req r{tag, static_cast<const uint8_t*>(data), len_units, dir & ~UTFX_SERVER_DEVICE_BUFFERS,
+                        static_cast<uint8_t*>(out), out_cap_units, dev};
   (utfx_srv::in_bytes(r) >= utfx_srv::kBulkMin ? S->pending_bulk : S->pending).push_back(r);
   return UTFX_OK;
 }

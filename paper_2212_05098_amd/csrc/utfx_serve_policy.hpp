@@ -17,6 +17,7 @@ struct ReqShape {
   uint32_t dir;     // 0 = UTF-8 -> UTF-16LE, 1 = UTF-16LE -> UTF-8; anything else is rejected
   bool pinned_in;   // the caller's input buffer is pinned host memory
   bool pinned_out;  // the caller's output buffer is pinned host memory
+  bool device = false;  // payload and output live in device memory (never staged)
 };
 
 struct PackLimits {
@@ -28,7 +29,8 @@ struct PackLimits {
 
 // Where a placed request lives in the step's arenas.  Staged data (copied through the
 // slot's pinned mirror) grows from the start of each arena, 16-byte aligned; direct data
-// (copied straight from or to the caller's pinned buffer) grows down from the end.
+// (copied straight from or to the caller's pinned buffer, or by the gather and scatter
+// kernels for device-resident requests) grows down from the end.
 struct Placement {
   uint64_t in_off;
   uint64_t out_off;
@@ -53,8 +55,8 @@ struct StepPacker {
   PackVerdict place(const ReqShape& r, Placement* p) {
     if (r.dir > 1 || r.in_bytes > lim.arena_in || r.out_bytes > lim.arena_out) return PACK_REJECT;
     if (count >= lim.max_items) return PACK_FULL;
-    const bool din = r.in_bytes >= lim.direct_min && r.pinned_in;
-    const bool dout = r.out_bytes >= lim.direct_min && r.pinned_out;
+    const bool din = r.device || (r.in_bytes >= lim.direct_min && r.pinned_in);
+    const bool dout = r.device || (r.out_bytes >= lim.direct_min && r.pinned_out);
     uint64_t io, oo, nlo = in_lo, nhi = in_hi, olo = out_lo, ohi = out_hi;
     if (din) {
       if (r.in_bytes > nhi) return PACK_FULL;

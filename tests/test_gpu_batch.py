@@ -187,3 +187,22 @@ def test_batch_back_to_back(ctx):
         rng = synth.rng_for(13, k, 5)
         caps = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
         run_and_check(ctx, b.arena, b.in_off, b.in_len, b.direction, caps, rng)
+
+
+@pytest.mark.parametrize("tuning", [(1024, 2, 1), (4096, 4, 1), (65536, 2, 2), (262144, 4, 2)])
+def test_batch_tunings_same_results(tuning):
+    """Every batch tuning (longest wave-walked string, segment tiles, persistent
+    segment workgroups per CU) gives the oracle's results on the same batch: strings up
+    to 1 MiB, 5 % with errors, caps cut on 5 %."""
+    b = synth.make_batch(4000, seed_key=(7, 5), median=512, sigma=2.5, hi=1 << 20, err_frac=0.05)
+    rng = synth.rng_for(7, 6)
+    caps = np.where(b.direction == 0, b.in_len, 3 * b.in_len).astype(np.uint64)
+    short = rng.random(len(caps)) < 0.05
+    caps[short] = (caps[short] * rng.random(int(short.sum()))).astype(np.uint64)
+    with utfx.Context() as c:
+        c.set_batch_tuning(*tuning)
+        assert c.get_batch_tuning() == tuning
+        note("batch tuning %s" % (tuning,))
+        run_and_check(c, b.arena, b.in_off, b.in_len, b.direction, caps, rng)
+        with pytest.raises(utfx.UtfxError):
+            c.set_batch_tuning(512, 4, 2)

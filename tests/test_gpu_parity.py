@@ -309,3 +309,29 @@ def test_async_result_buffer(ctx):
     assert tuple(r[0]) == tuple(want)
     assert tuple(r[1]) == tuple(O.validate_utf8(data))
     assert tuple(r[2]) == tuple(O.utf16_length_from_utf8(data))
+
+
+@pytest.mark.parametrize("wgs", [1, 2, 3, 4])
+def test_residency_cap_same_results(wgs):
+    """Capping the resident workgroups per CU (utfx_set_tuning's wgs_per_cu, through
+    unused dynamic LDS) changes the schedule, never the results: both transcodes,
+    validation and the length queries on 8 MiB buffers with an error late in one."""
+    rng = synth.rng_for(12, wgs)
+    d8 = synth.utf8_buffer("mixed4", (8 << 20) + 5, rng)
+    bad = d8.copy()
+    bad[bad.size - 3000] = 0xC1
+    w = synth.utf16_buffer("emoji", (4 << 20) + 3, rng)
+    with utfx.Context() as c:
+        for op in range(6):
+            t, s_, _ = c.get_tuning(op)
+            c.set_tuning(op, t, s_, wgs)
+        note("residency cap %d" % wgs)
+        for data in (d8, bad):
+            check_u8_to_u16(c, data)
+            src, _ = dev_u8(data)
+            assert tuple(c.validate_utf8(src)) == tuple(O.validate_utf8(data))
+            assert tuple(c.utf16_length_from_utf8(src)) == tuple(O.utf16_length_from_utf8(data))
+        check_u16_to_u8(c, w)
+        src, _ = dev_u16(w)
+        assert tuple(c.validate_utf16le(src)) == tuple(O.validate_utf16le(w))
+        assert tuple(c.utf8_length_from_utf16le(src)) == tuple(O.utf8_length_from_utf16le(w))

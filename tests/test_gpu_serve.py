@@ -150,3 +150,64 @@ def test_server_bulk_and_direct_requests():
 def test_server_device_cap():
     with pytest.raises(utfx.UtfxError):
         utfx.Server(arena_in_bytes=1 << 30, arena_out_bytes=2 << 30, inflight=2, device_cap_bytes=4 << 30)
+
+
+def test_device_resident_requests_mixed_with_host_requests():
+    """Device-resident requests (payload and output in device memory, flag
+    SERVER_DEVICE_BUFFERS) served in the same steps as host requests: every result and
+    output matches the oracle, and the device outputs leave the bytes after their valid
+    prefix untouched."""
+    import torch
+
+    rng = synth.rng_for(31, 7)
+    srv = utfx.Server(arena_in_bytes=1 << 20, arena_out_bytes=3 << 20, max_items=256, inflight=3)
+    reqs = []
+    for i in range(600):
+        d = int(rng.integers(0, 2))
+        prof = synth.SCRIPT_PROFILES[int(rng.integers(0, 4))]
+        L = int(synth.lognormal_lengths(rng, 1, 500, 2.0, 1, 200000)[0])
+        if d == 0:
+            data = synth.utf8_buffer(prof, L, rng)
+            if rng.random() < 0.1 and L > 4:
+                data[int(rng.integers(0, L))] = 0xFF
+            cap, out_len = data.size, 2 * data.size
+        else:
+            data = synth.utf16_buffer(prof, max(L // 2, 1), rng)
+            if rng.random() < 0.1:
+                data[int(rng.integers(0, data.size))] = 0xDC00
+            cap, out_len = 3 * data.size, 3 * data.size
+        dev = bool(rng.random() < 0.6)
+        if dev:
+            raw = data.view(np.uint8)
+            shift = int(rng.integers(0, 16)) & (~1 if d == 1 else ~0)  # any start; UTF-16 stays 2-byte aligned
+            src_t = torch.zeros(raw.size + 32, dtype=torch.uint8, device="cuda")
+            src_t[shift:shift + raw.size] = torch.from_numpy(raw.copy()).cuda()
+            out_t = torch.full((out_len + 32,), 0xA5, dtype=torch.uint8, device="cuda")
+            reqs.append((data, d, cap, out_t, src_t, shift, True))
+        else:
+            reqs.append((data, d, cap, np.zeros(out_len + 2, dtype=np.uint8), None, 0, False))
+    torch.cuda.synchronize()
+    for i, (data, d, cap, out, src_t, shift, dev) in enumerate(reqs):
+        if dev:
+            st = srv.submit(i, src_t.data_ptr() + shift, data.size, d | utfx.SERVER_DEVICE_BUFFERS, out.data_ptr(),
+                            cap)
+        else:
+            st = srv.submit(i, data.ctypes.data, data.size, d, out.ctypes.data, cap)
+        assert st == utfx.OK
+    got = {}
+    note("server with device-resident requests: %d requests" % len(reqs))
+    for _ in range(2_000_000):
+        for tag, r in srv.progress():
+            got[tag] = r
+        if len(got) == len(reqs):
+            break
+    assert len(got) == len(reqs)
+    for i, (data, d, cap, out, src_t, shift, dev) in enumerate(reqs):
+        if dev:
+            host = out.cpu().numpy()
+            _check(data, d, host, got[i])
+            w = got[i].written * (2 if d == 0 else 1)
+            assert np.all(host[w:] == 0xA5), i
+        else:
+            _check(data, d, out, got[i])
+    srv.close()
