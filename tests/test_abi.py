@@ -94,11 +94,12 @@ def test_tune_cache_round_trip(tmp_path):
     """The tuning cache is plain JSON that load() returns unchanged."""
     from paper_2212_05098_amd import tune
 
-    cache = {"device": "x", "size_mib": 1, "ops": {"0": [8192, 4, 4], "6": [8192, 4, 2]}}
+    entry = {"key": "gfx950|hip x|256 CUs", "device": "x", "size_mib": 1, "ops": {"0": [8192, 4, 4]},
+             "batch": [16384, 4, 2]}
     p = str(tmp_path / "c.json")
-    tune.save(cache, p)
-    assert tune.load(p) == cache
-    assert tune.load(str(tmp_path / "missing.json")) is None
+    tune.save(entry, p)
+    assert tune.load(p, key=entry["key"]) == entry
+    assert tune.load(str(tmp_path / "missing.json"), key=entry["key"]) is None
 
 
 def test_header_is_plain_c(tmp_path):
