@@ -38,39 +38,105 @@ struct Req {
   bool dev;           // data and out are device addresses
 };
 
-// One copy of a device-resident request: its device buffer, its place in the step's
-// arena, and (scatter) its item and output unit size.
+// One piece (at most kPiece bytes) of a device-resident request's payload or output:
+// its device address, its place in the step's arena (16-byte aligned), its size, and
+// for outputs the item, the output unit size and the piece's offset in the output.
+constexpr uint64_t kPiece = 16 << 10;
 struct DevCopy {
   uint64_t ptr;
   uint64_t off;
-  uint64_t bytes;     // gather: payload bytes; scatter: output capacity in bytes
+  uint64_t bytes;     // gather: payload bytes of the piece; scatter: its capacity in bytes
+  uint64_t start;     // scatter: byte offset of the piece in the request's output
   uint32_t item;
-  uint32_t unit;      // output bytes per unit (scatter)
+  uint32_t unit;      // scatter: output bytes per unit
 };
 
-// Gathers device-resident payloads into the step's input arena: one workgroup per
-// request (grid-strided), byte by byte, so any source alignment works.
-__global__ void k_srv_gather(const DevCopy* c, uint32_t n, uint8_t* arena) {
+// Bytes [a, a + 16) of the 32 bytes lo:hi (a in 0..15, wave-uniform).
+__device__ __forceinline__ uint4 funnel16(const uint4 lo, const uint4 hi, uint32_t a) {
+  const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  const uint32_t r = a & 3;
+  uint4 o;
+  switch (a >> 2) {
+    case 0: o = {__builtin_amdgcn_alignbyte(w[1], w[0], r), __builtin_amdgcn_alignbyte(w[2], w[1], r),
+                 __builtin_amdgcn_alignbyte(w[3], w[2], r), __builtin_amdgcn_alignbyte(w[4], w[3], r)}; break;
+    case 1: o = {__builtin_amdgcn_alignbyte(w[2], w[1], r), __builtin_amdgcn_alignbyte(w[3], w[2], r),
+                 __builtin_amdgcn_alignbyte(w[4], w[3], r), __builtin_amdgcn_alignbyte(w[5], w[4], r)}; break;
+    case 2: o = {__builtin_amdgcn_alignbyte(w[3], w[2], r), __builtin_amdgcn_alignbyte(w[4], w[3], r),
+                 __builtin_amdgcn_alignbyte(w[5], w[4], r), __builtin_amdgcn_alignbyte(w[6], w[5], r)}; break;
+    default: o = {__builtin_amdgcn_alignbyte(w[4], w[3], r), __builtin_amdgcn_alignbyte(w[5], w[4], r),
+                  __builtin_amdgcn_alignbyte(w[6], w[5], r), __builtin_amdgcn_alignbyte(w[7], w[6], r)}; break;
+  }
+  return o;
+}
+
+__device__ __forceinline__ void store_bytes(uint8_t* p, const uint4 v, uint32_t i0, uint32_t i1) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  for (uint32_t i = i0; i < i1; ++i) p[i] = (uint8_t)(w[i >> 2] >> (8 * (i & 3)));
+}
+
+// Gathers device-resident payload pieces into the step's input arena, one workgroup per
+// piece (grid-strided), 16 bytes per thread: the source (any alignment) is read as the
+// aligned 16-byte blocks that hold the chunk's bytes (a block holding at least one byte
+// of the buffer never crosses a page) and funnel-shifted; the arena side is aligned.
+__global__ void __launch_bounds__(256) k_srv_gather(const DevCopy* c, uint32_t n, uint8_t* arena) {
   for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
     const DevCopy d = c[k];
-    const uint8_t* src = reinterpret_cast<const uint8_t*>(d.ptr);
+    const uint32_t a = (uint32_t)(d.ptr & 15);
+    const uint8_t* b0 = reinterpret_cast<const uint8_t*>(d.ptr - a);
     uint8_t* dst = arena + d.off;
-    for (uint64_t i = threadIdx.x; i < d.bytes; i += blockDim.x) dst[i] = src[i];
+    const uint64_t nch = (d.bytes + 15) / 16;
+    for (uint64_t ch = threadIdx.x; ch < nch; ch += blockDim.x) {
+      const uint4 lo = *reinterpret_cast<const uint4*>(b0 + 16 * ch);
+      uint4 v = lo;
+      if (a) {
+        uint4 hi = {0, 0, 0, 0};
+        if (16 * ch + 16 - a < d.bytes) hi = *reinterpret_cast<const uint4*>(b0 + 16 * ch + 16);
+        v = funnel16(lo, hi, a);
+      }
+      if (16 * ch + 16 <= d.bytes) *reinterpret_cast<uint4*>(dst + 16 * ch) = v;
+      else store_bytes(dst + 16 * ch, v, 0, (uint32_t)(d.bytes - 16 * ch));
+    }
   }
 }
 
-// Copies each device-resident request's valid prefix (written units, at most its
-// capacity; nothing on OUTPUT_TOO_SMALL) from the output arena to its buffer.
-__global__ void k_srv_scatter(const DevCopy* c, uint32_t n, const uint8_t* arena, const utfx_result* res) {
+// Copies the valid prefix of each device-resident request's output (written units, at
+// most its capacity; nothing on OUTPUT_TOO_SMALL) from the output arena to its buffer,
+// piece by piece: whole aligned 16-byte blocks of the destination are stored at once,
+// the partly covered first and last blocks byte by byte, so nothing outside the
+// prefix is touched.
+__global__ void __launch_bounds__(256) k_srv_scatter(const DevCopy* c, uint32_t n, const uint8_t* arena,
+                                                     const utfx_result* res) {
   for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
     const DevCopy d = c[k];
     const utfx_result r = res[d.item];
     if (r.status == UTFX_E_OUTPUT_TOO_SMALL) continue;
-    uint64_t bytes = r.written * d.unit;
-    if (bytes > d.bytes) bytes = d.bytes;
+    const uint64_t total = r.written * d.unit;
+    if (total <= d.start) continue;
+    const uint64_t nb = total - d.start < d.bytes ? total - d.start : d.bytes;
     const uint8_t* src = arena + d.off;
-    uint8_t* dst = reinterpret_cast<uint8_t*>(d.ptr);
-    for (uint64_t i = threadIdx.x; i < bytes; i += blockDim.x) dst[i] = src[i];
+    const uint32_t a = (uint32_t)(d.ptr & 15);
+    uint8_t* B0 = reinterpret_cast<uint8_t*>(d.ptr - a);
+    const uint64_t nblk = (a + nb + 15) / 16;
+    for (uint64_t j = threadIdx.x; j < nblk; j += blockDim.x) {
+      // destination block j holds output bytes [16j - a, 16j - a + 16)
+      uint4 v;
+      if (a == 0) {
+        v = *reinterpret_cast<const uint4*>(src + 16 * j);
+      } else {
+        uint4 lo = {0, 0, 0, 0}, hi = {0, 0, 0, 0};
+        if (j >= 1) lo = *reinterpret_cast<const uint4*>(src + 16 * (j - 1));
+        if (16 * j < nb) hi = *reinterpret_cast<const uint4*>(src + 16 * j);
+        v = funnel16(lo, hi, 16 - a);
+      }
+      const int64_t s0 = (int64_t)(16 * j) - (int64_t)a;
+      if (s0 >= 0 && (uint64_t)s0 + 16 <= nb) {
+        *reinterpret_cast<uint4*>(B0 + 16 * j) = v;
+      } else {
+        const uint32_t i0 = s0 < 0 ? (uint32_t)(-s0) : 0u;
+        const uint32_t i1 = (uint64_t)(s0 + 16) > nb ? (uint32_t)((int64_t)nb - s0) : 16u;
+        store_bytes(B0 + 16 * j, v, i0, i1);
+      }
+    }
   }
 }
 
@@ -155,6 +221,9 @@ inline void free_slot(Slot& s) {
   s = Slot();
 }
 
+inline uint64_t gather_cap(const utfx_server_config& c) { return c.max_items + c.arena_in_bytes / kPiece + 1; }
+inline uint64_t scatter_cap(const utfx_server_config& c) { return c.max_items + c.arena_out_bytes / kPiece + 1; }
+
 inline hipError_t alloc_slot(Slot& s, const utfx_server_config& c) {
   hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
@@ -166,12 +235,14 @@ inline hipError_t alloc_slot(Slot& s, const utfx_server_config& c) {
   if (e == hipSuccess) e = hipMalloc((void**)&s.d_out, c.arena_out_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&s.d_items, c.max_items * sizeof(utfx_item));
   if (e == hipSuccess) e = hipMalloc((void**)&s.d_res, c.max_items * sizeof(utfx_result));
-  // gather list, then scatter list, in one allocation each side
-  if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_gather, 2 * c.max_items * sizeof(DevCopy), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc((void**)&s.d_gather, 2 * c.max_items * sizeof(DevCopy));
+  // gather list, then scatter list, in one allocation each side: a request takes one
+  // piece per kPiece bytes (or part), so a step has at most max_items + arena / kPiece
+  const uint64_t ng = gather_cap(c), ns = scatter_cap(c);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_gather, (ng + ns) * sizeof(DevCopy), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&s.d_gather, (ng + ns) * sizeof(DevCopy));
   if (e == hipSuccess) {
-    s.h_scatter = s.h_gather + c.max_items;
-    s.d_scatter = s.d_gather + c.max_items;
+    s.h_scatter = s.h_gather + ng;
+    s.d_scatter = s.d_gather + ng;
   }
   if (e == hipSuccess && utfx_create(&s.ctx, s.stream) != UTFX_OK) e = hipErrorOutOfMemory;
   return e;
@@ -229,9 +300,14 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
     const bool din = pl.direct_in, dout = pl.direct_out;
     if (r.dev) {
       const uint32_t item = (uint32_t)s.reqs.size();
-      if (in_bytes(r)) s.h_gather[n_gather++] = DevCopy{(uint64_t)(uintptr_t)r.data, io, in_bytes(r), item, 0};
-      if (out_bytes(r))
-        s.h_scatter[n_scatter++] = DevCopy{(uint64_t)(uintptr_t)r.out, oo, out_bytes(r), item, r.dir ? 1u : 2u};
+      for (uint64_t p0 = 0; p0 < in_bytes(r); p0 += kPiece) {
+        const uint64_t nb = in_bytes(r) - p0 < kPiece ? in_bytes(r) - p0 : kPiece;
+        s.h_gather[n_gather++] = DevCopy{(uint64_t)(uintptr_t)r.data + p0, io + p0, nb, 0, item, 0};
+      }
+      for (uint64_t p0 = 0; p0 < out_bytes(r); p0 += kPiece) {
+        const uint64_t nb = out_bytes(r) - p0 < kPiece ? out_bytes(r) - p0 : kPiece;
+        s.h_scatter[n_scatter++] = DevCopy{(uint64_t)(uintptr_t)r.out + p0, oo + p0, nb, p0, item, r.dir ? 1u : 2u};
+      }
     } else if (din) {
       direct_in_idx.push_back((uint32_t)s.reqs.size());
     } else if (in_bytes(r)) {
@@ -264,7 +340,7 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
   if (e == hipSuccess && n_scatter)
     e = hipMemcpyAsync(s.d_scatter, s.h_scatter, n_scatter * sizeof(DevCopy), hipMemcpyHostToDevice, s.stream);
   if (e == hipSuccess && n_gather) {
-    hipLaunchKernelGGL(k_srv_gather, dim3(n_gather < 1024 ? n_gather : 1024), dim3(256), 0, s.stream, s.d_gather,
+    hipLaunchKernelGGL(k_srv_gather, dim3(n_gather < 2048 ? n_gather : 2048), dim3(256), 0, s.stream, s.d_gather,
                        n_gather, s.d_in);
     e = hipGetLastError();
   }
@@ -276,7 +352,7 @@ inline uint32_t launch_step(utfx_server* S, Slot& s, std::deque<Req>& q, bool bu
   if (e == hipSuccess && bs == UTFX_OK && out_lo)
     e = hipMemcpyAsync(s.h_out, s.d_out, out_lo, hipMemcpyDeviceToHost, s.stream);
   if (e == hipSuccess && bs == UTFX_OK && n_scatter) {
-    hipLaunchKernelGGL(k_srv_scatter, dim3(n_scatter < 1024 ? n_scatter : 1024), dim3(256), 0, s.stream,
+    hipLaunchKernelGGL(k_srv_scatter, dim3(n_scatter < 2048 ? n_scatter : 2048), dim3(256), 0, s.stream,
                        s.d_scatter, n_scatter, s.d_out, s.d_res);
     e = hipGetLastError();
   }
