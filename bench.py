@@ -219,6 +219,9 @@ def main():
 
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%dMiB.txt" % (kernel, args.size_mib))
     traffic = profsum.read_traffic(tpath, kernel, case_name)
+    # the same kernel's timed launches under rocprofv3 (committed summary of this build)
+    rp_us = profsum.read_timed_us(os.path.join(ROOT, "profiles", "kernel_trace_transcode_4profiles_%dMiB.txt" %
+                                               args.size_mib), kernel)
 
     cpu = None
     if not args.no_cpu:
@@ -256,6 +259,8 @@ def main():
                      "timing": "kernel-only HIP events around each launch of the kernel (hipExtLaunchKernel)",
                      "frac_by_profile": dom["frac_by_profile"],
                      "traffic": traffic,
+                     "rocprof_ms_avg": round(rp_us / 1e3, 4) if rp_us else None,
+                     "rocprof_frac": round(dom["launch_bytes"] / (rp_us * 1e3) / HBM_PEAK_GBS, 4) if rp_us else None,
                      "other_kernels": {k: {"achieved": round(v["achieved"], 1),
                                            "frac": round(v["achieved"] / HBM_PEAK_GBS, 4),
                                            "ms_avg": round(v["launch_ms"], 4),

@@ -58,10 +58,12 @@ def _short(name: str) -> str:
     return name[:70]
 
 
-def stats_text(d: str, cmd: str, cycle=None) -> str:
+def stats_text(d: str, cmd: str, cycle=None, timed: int = 0) -> str:
     """Per-kernel dispatch count and durations from a kernel-trace run.  With `cycle`
     (the inputs a kernel is dispatched on, in the order the program cycles through
-    them), the main kernels are also split per input by dispatch index."""
+    them), the main kernels are also split per input by dispatch index; with `timed`,
+    also the average over the last `timed` dispatches per input (the launches the
+    benchmark times, after its correctness and warm-up passes)."""
     rows = list(csv.DictReader(open(_find(d, "kernel_trace.csv"))))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     per = collections.defaultdict(list)
@@ -83,6 +85,14 @@ def stats_text(d: str, cmd: str, cycle=None) -> str:
                 w = v[j::len(cycle)]
                 out.append(fmt % ("%s [%s]" % (_short(k)[:52], name), len(w), sum(w) / len(w) / 1e3,
                                   min(w) / 1e3, max(w) / 1e3, 100.0 * sum(w) / tot))
+        if timed:
+            out.append("# timed launches: the last %d dispatches per input of each main kernel" % timed)
+            for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+                if not ("k_u8_to_u16<" in k or "k_u16_to_u8<" in k) or len(v) % len(cycle):
+                    continue
+                w = [x for j in range(len(cycle)) for x in v[j::len(cycle)][-timed:]]
+                out.append(fmt % ("%s [timed]" % _short(k)[:52], len(w), sum(w) / len(w) / 1e3, min(w) / 1e3,
+                                  max(w) / 1e3, 100.0 * sum(w) / tot))
     return "\n".join(out) + "\n"
 
 
@@ -155,6 +165,22 @@ def read_traffic(path: str, kernel: str, case: str):
     return int(kv["traffic_bytes_per_launch"])
 
 
+def read_timed_us(path: str, kernel: str):
+    """Average duration (us) of the timed launches of a main kernel from a kernel-trace
+    summary, or None if absent or taken from kernel sources that have changed since."""
+    if not os.path.exists(path):
+        return None
+    src = None
+    for line in open(path):
+        if line.startswith("# kernel sources:"):
+            src = line.split(":", 1)[1].strip()
+        elif kernel + "<" in line and "[timed]" in line:
+            if src != source_hash():
+                return None
+            return float(line.split()[-4])
+    return None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -162,6 +188,7 @@ def main(argv=None):
     s.add_argument("dir")
     s.add_argument("--cmd", required=True)
     s.add_argument("--cycle", default="", help="comma-separated inputs the kernels cycle through")
+    s.add_argument("--timed", type=int, default=0, help="last dispatches per input the benchmark times")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -172,7 +199,7 @@ def main(argv=None):
     t.add_argument("--cmd-write", required=True)
     a = ap.parse_args(argv)
     if a.what == "stats":
-        sys.stdout.write(stats_text(a.dir, a.cmd, [c for c in a.cycle.split(",") if c]))
+        sys.stdout.write(stats_text(a.dir, a.cmd, [c for c in a.cycle.split(",") if c], a.timed))
     else:
         sys.stdout.write(traffic_text(a.fetch_dir, a.write_dir, a.kernel, a.case, a.copy_bytes, a.cmd_fetch,
                                       a.cmd_write))
