@@ -64,13 +64,29 @@ __device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t
       }
       *reinterpret_cast<uint4*>(out + g0) = o;
     } else {
+      // An edge chunk: its elements i_lo <= i < i_hi lie in the span and in [0, cap).
+      // They are gathered like a whole chunk (s0 >= d, so the window starts inside the
+      // stage; it ends within 20 bytes past the span) and stored one by one.
+      int64_t a = (int64_t)d - (int64_t)l0, b = (int64_t)d + (int64_t)total - (int64_t)l0;
+      a = a > -g0 ? a : -g0;
+      b = b < (int64_t)cap - g0 ? b : (int64_t)cap - g0;
+      const uint32_t i_lo = a <= 0 ? 0u : (a >= (int64_t)PER ? PER : (uint32_t)a);
+      const uint32_t i_hi = b <= 0 ? 0u : (b >= (int64_t)PER ? PER : (uint32_t)b);
+      if (i_lo < i_hi) {
+        const uint32_t b0 = (s0 + l0 - d) * sizeof(U);
+        const uint32_t w0 = b0 >> 2, sh = b0 & 3;
+        const uint32_t v0 = s32[w0], v1 = s32[w0 + 1], v2 = s32[w0 + 2], v3 = s32[w0 + 3], v4 = s32[w0 + 4];
+        uint32_t o[4] = {abyte(v1, v0, sh), abyte(v2, v1, sh), abyte(v3, v2, sh), abyte(v4, v3, sh)};
+        if (sizeof(U) == 2 && swap16) {
 #pragma unroll
-      for (uint32_t i = 0; i < PER; ++i) {
-        const int64_t l = (int64_t)(l0 + i) - (int64_t)d;
-        const int64_t g = g0 + (int64_t)i;
-        if (l >= 0 && l < (int64_t)total && g >= 0 && g < (int64_t)cap) {
-          const U v = stage[s0 + (uint32_t)l];
-          out[g] = (sizeof(U) == 2 && swap16) ? (U)bswap16(v) : v;
+          for (int j = 0; j < 4; ++j) o[j] = bswap16x2(o[j]);
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < PER; ++i) {
+          if (i >= i_lo && i < i_hi) {
+            const uint32_t word = o[(i * sizeof(U)) >> 2];
+            out[g0 + (int64_t)i] = (U)(word >> (8 * ((i * sizeof(U)) & 3)));
+          }
         }
       }
     }
