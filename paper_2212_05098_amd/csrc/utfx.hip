@@ -1040,11 +1040,11 @@ utfx_status utfx_batch_run(utfx_ctx* c, const uint8_t* in_arena, size_t in_bytes
                            utfx_result* d_results) {
   if (!c) return UTFX_E_INVALID_ARG;
   c->err[0] = 0;
-  const void* mem = c->batch.mem;
+  const uint64_t gen = c->batch.gen;
   utfx_status st = batch_run(c->batch, c->stream, c->capturing, c->num_cus, c->dbg, c->batch_tuning, in_arena,
                              in_bytes, out_arena, out_bytes, d_items, n_items, total_in_units, d_results, c->err,
                              sizeof(c->err));
-  if (c->batch.mem != mem) c->ws_gen++;
+  if (c->batch.gen != gen) c->ws_gen++;  // kernels captured before hold freed addresses
   if (st == UTFX_OK && c->capturing) c->cap_batches++;
   return st;
 }

@@ -754,6 +754,8 @@ struct BatchWs {
   unsigned long long* plan_status[2] = {nullptr, nullptr};
   uint64_t cap_items = 0, cap_units = 0;
   uint64_t launches = 0;
+  uint64_t gen = 0;  // workspace generation: +1 whenever the old one is freed (a new
+                    // allocation may come back at the same address)
 };
 
 inline hipError_t batch_ws_init(BatchWs&) { return hipSuccess; }
@@ -794,6 +796,7 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   while (nu < cap_units) nu *= 2;
   if (b.mem) (void)hipFree(b.mem);
   b.mem = nullptr;
+  b.gen++;
   const uint64_t plan_words = (ni + utfx_dev::PLAN_WG - 1) / utfx_dev::PLAN_WG;
   auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
   uint64_t o = al(sizeof(utfx_dev::WsHeader));
@@ -814,7 +817,8 @@ inline hipError_t batch_ws_ensure(BatchWs& b, hipStream_t s, uint64_t n_items, u
   }
   e = hipMalloc(&b.mem, o);
   if (e != hipSuccess) {
-    b = BatchWs();
+    b.mem = nullptr;
+    b.cap_items = b.cap_units = 0;
     return e;
   }
   char* m = static_cast<char*>(b.mem);
