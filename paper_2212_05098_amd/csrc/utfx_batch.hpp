@@ -172,13 +172,18 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
   uint32_t units[PLAN_ITEMS], dir[PLAN_ITEMS], tsum[2] = {0, 0}, tiny = 0, ntiny[2] = {0, 0};
   uint32_t cls = 0, ncls[NCLS] = {0, 0, 0, 0};  // cls: 3 bits per item (class + 1, 0 = none)
   uint64_t len = 0;
+  BItem its[PLAN_ITEMS];  // all of the thread's descriptors are loaded before any is used
+#pragma unroll
+  for (int j = 0; j < PLAN_ITEMS; ++j) {
+    if (i0 + j < A.n_items) its[j] = A.items[i0 + j];
+  }
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) {
     units[j] = 0;
     dir[j] = 0;
     const uint64_t i = i0 + j;
     if (i < A.n_items) {
-      const BItem it = A.items[i];
+      const BItem it = its[j];
       if (item_ok(A, it)) {
         len += it.in_len;
         if (it.in_len > A.small_max) {
@@ -204,29 +209,29 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
   local[0] = block_excl_scan<PLAN_WG>(tsum[0], total[0], scr[0]);
   local[1] = block_excl_scan<PLAN_WG>(tsum[1], total[1], scr[1]);
   const uint32_t epoch = cur_epoch(A.ws);
-  if (threadIdx.x < 64) {
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      if (threadIdx.x == 0) {
-        debug_delay(A.dbg, blockIdx.x);
-        publish_aggregate(A.plan_status[d], blockIdx.x, total[d], epoch);
-      }
-      // a plan workgroup's aggregate, recomputed from its items if it is late
-      const uint64_t b = lookback_wave(A.plan_status[d], blockIdx.x, total[d], epoch, A.ws, [&](uint64_t blk) {
-        const uint64_t a0 = blk * (uint64_t)(PLAN_WG * PLAN_ITEMS);
-        const uint64_t a1 = a0 + PLAN_WG * PLAN_ITEMS < A.n_items ? a0 + PLAN_WG * PLAN_ITEMS : A.n_items;
-        uint64_t acc = 0;
-        for (uint64_t i = a0 + (threadIdx.x & 63); i < a1; i += 64) {
-          const BItem it = A.items[i];
-          if (item_ok(A, it) && it.in_len > A.small_max && (int)it.dir == d) acc += item_units(A, it);
-        }
-        return wave_sum_u64(acc);
-      });
-      if (threadIdx.x == 0) pfx[d] = b;
+  if (threadIdx.x < 128) {
+    // one wave per direction, so that the two look-backs overlap
+    const int d = (int)(threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0) {
+      debug_delay(A.dbg, blockIdx.x);
+      publish_aggregate(A.plan_status[d], blockIdx.x, total[d], epoch);
     }
+    // a plan workgroup's aggregate, recomputed from its items if it is late
+    const uint64_t b = lookback_wave(A.plan_status[d], blockIdx.x, total[d], epoch, A.ws, [&](uint64_t blk) {
+      const uint64_t a0 = blk * (uint64_t)(PLAN_WG * PLAN_ITEMS);
+      const uint64_t a1 = a0 + PLAN_WG * PLAN_ITEMS < A.n_items ? a0 + PLAN_WG * PLAN_ITEMS : A.n_items;
+      uint64_t acc = 0;
+      for (uint64_t i = a0 + (threadIdx.x & 63); i < a1; i += 64) {
+        const BItem it = A.items[i];
+        if (item_ok(A, it) && it.in_len > A.small_max && (int)it.dir == d) acc += item_units(A, it);
+      }
+      return wave_sum_u64(acc);
+    });
+    if ((threadIdx.x & 63) == 0) pfx[d] = b;
   }
-  // slots in the lists of large and tiny items (their order is free): the workgroup's
-  // counts are scanned and one thread takes each list's range with one atomicAdd
+  // slots in the lists of large, tiny and wave-walked items (their order is free): the
+  // workgroup's counts are scanned and one lane per list takes the list's range with
+  // one atomicAdd
   uint32_t nlarge = 0;
 #pragma unroll
   for (int j = 0; j < PLAN_ITEMS; ++j) nlarge += units[j] != 0;
@@ -235,14 +240,17 @@ __global__ void __launch_bounds__(PLAN_WG) k_batch_plan(BatchArgs A) {
   const uint32_t c1 = block_excl_scan<PLAN_WG>(ntiny[1], ctot[1], scr[3]);
   const uint32_t c2 = block_excl_scan<PLAN_WG>(ncls[0] | (ncls[1] << 16), ctot[2], scr[4]);
   const uint32_t c3 = block_excl_scan<PLAN_WG>(ncls[2] | (ncls[3] << 16), ctot[3], scr[5]);
-  if (threadIdx.x == 0) {
-    const uint32_t want[3] = {ctot[0] & 0xFFFFu, ctot[0] >> 16, ctot[1]};
-    unsigned long long* ctr[3] = {&A.ws->acc, ntiny_of(A.ws, 0), ntiny_of(A.ws, 1)};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) lbase[q] = want[q] ? atomicAdd(ctr[q], (unsigned long long)want[q]) : 0ull;
-    const uint32_t wc[NCLS] = {ctot[2] & 0xFFFFu, ctot[2] >> 16, ctot[3] & 0xFFFFu, ctot[3] >> 16};
-#pragma unroll
-    for (int q = 0; q < NCLS; ++q) cbase[q] = wc[q] ? atomicAdd(&A.cls_count[q], (unsigned long long)wc[q]) : 0ull;
+  if (threadIdx.x < 3 + NCLS) {
+    // one list per lane, so that the atomics are in flight together
+    const int q = (int)threadIdx.x;
+    const uint32_t want[3 + NCLS] = {ctot[0] & 0xFFFFu, ctot[0] >> 16, ctot[1],        ctot[2] & 0xFFFFu,
+                                     ctot[2] >> 16,     ctot[3] & 0xFFFFu, ctot[3] >> 16};
+    unsigned long long* const ctr = q == 0 ? &A.ws->acc
+                                    : q < 3 ? ntiny_of(A.ws, q - 1)
+                                            : &A.cls_count[q - 3];
+    const unsigned long long v = want[q] ? atomicAdd(ctr, (unsigned long long)want[q]) : 0ull;
+    if (q < 3) lbase[q] = v;
+    else cbase[q - 3] = v;
   }
   __syncthreads();
   unsigned long long slot = lbase[0] + (c0 & 0xFFFFu);
@@ -310,7 +318,7 @@ __device__ __forceinline__ void load8_masked(const Launch& L, uint64_t q0, const
 __device__ __forceinline__ bool wave_load8(const Launch& L, uint64_t c0, uint64_t lo, uint64_t hi, uintptr_t alo,
                                            uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
   const uint64_t q0 = c0 + 16ull * lane;
-  const bool full = !__any(!(q0 >= lo && q0 + 16 <= hi));
+  const bool full = c0 >= lo && c0 + 1024 <= hi;  // every lane's chunk (the same test per lane)
   if (full) {
     const uint4 v = *reinterpret_cast<const uint4*>(L.base + q0);
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
@@ -419,7 +427,7 @@ __device__ __forceinline__ void load16_masked(const Launch& L, uint64_t q0, cons
 __device__ __forceinline__ bool wave_load16(const Launch& L, uint64_t c0, uint64_t lo, uint64_t hi, uintptr_t alo,
                                             uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
   const uint64_t q0 = c0 + 8ull * lane;
-  const bool full = !__any(!(q0 >= lo && q0 + 8 <= hi));
+  const bool full = c0 >= lo && c0 + 512 <= hi;  // every lane's chunk (the same test per lane)
   if (full) {
     const uint4 v = *reinterpret_cast<const uint4*>(L.base + 2 * q0);
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
