@@ -6,11 +6,13 @@ with full validation (8 calls, 2 GiB of input).  Inputs are resident in HBM befo
 the timed region; each (profile, direction) rotates over several device copies so
 that no call finds its input in the 256 MB Infinity Cache.
 
-Prints ONE JSON line (rank 0).  `value` = input bytes of the step / step time.
-`roofline` describes the dominant kernel (the transcode kernel with the most device
-time in the step, over its four launches, one per profile): algorithmic bytes per
-launch (input + output, averaged over those launches) / its average launch duration
-measured with HIP events on the launch stream, against the 8 TB/s HBM peak.  `cpu_baseline` times the scalar oracle
+Prints ONE JSON line (rank 0).  `value` = input bytes of the step / step time, the
+steps timed with nothing but the calls on the stream.  The same steps then run again
+with events per call for the per-call and per-kernel figures: `roofline` describes the
+dominant kernel (the transcode kernel with the most device time in the step, over its
+four launches, one per profile): algorithmic bytes per launch (input + output,
+averaged over those launches) / its average launch duration measured with HIP events
+on the launch stream, against the 8 TB/s HBM peak.  `cpu_baseline` times the scalar oracle
 on a bounded sample of the same inputs on the host.
 """
 from __future__ import annotations
@@ -132,9 +134,21 @@ def main():
     def evpair():
         return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    # per call: events around the whole call (main kernel + finalisation) on the stream,
-    # and kernel-only events that the library records immediately before and after the
-    # main kernel (hipExtLaunchKernel)
+    # the timed steps: the calls alone, back to back on the stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for i in range(len(cases)):
+            call(i, s + 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_s = (t1 - t0) / args.steps
+    rs = utfx.results_from_tensor(res)
+    assert all(r.status == utfx.OK for r in rs[: len(cases)])
+
+    # the same steps again with events per call: around the whole call (main kernel +
+    # finalisation) on the stream, and kernel-only events that the library records
+    # immediately before and after the main kernel (hipExtLaunchKernel)
     ev = [[evpair() for _ in cases] for _ in range(args.steps)]
     kev = [[evpair() for _ in cases] for _ in range(args.steps)]
     for row in kev:
@@ -142,7 +156,6 @@ def main():
             a_.record(stream)
             b_.record(stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for s in range(args.steps):
         for i in range(len(cases)):
             ev[s][i][0].record(stream)
@@ -150,12 +163,9 @@ def main():
             call(i, s + 1)
             ev[s][i][1].record(stream)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     ctx.set_kernel_events(None, None)
     rs = utfx.results_from_tensor(res)
     assert all(r.status == utfx.OK for r in rs[: len(cases)])
-
-    step_s = (t1 - t0) / args.steps
     in_bytes = sum(c[5] for c in cases)
     per_case = []
     for i, c in enumerate(cases):
