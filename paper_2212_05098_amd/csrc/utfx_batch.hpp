@@ -356,11 +356,10 @@ __device__ __forceinline__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, ui
     const bool full = fulln;
     uint32_t x[4] = {xn[0], xn[1], xn[2], xn[3]};
     if (c0 + 1024 <= hi) fulln = wave_load8(L, c0 + 1024, lo, hi, alo, ahi, lane, xn);
-    uint32_t cnt;
+    uint32_t cnt, m[4];
     if (full) {
       cnt = count8(x, nullptr);
     } else {
-      uint32_t m[4];
       range_masks(q0, lo, hi, m);
       cnt = count8(x, m);
     }
@@ -369,7 +368,8 @@ __device__ __forceinline__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, ui
     const uint32_t xp = wave_shr1(x[3], carry);
     carry = __shfl(x[3], 63, 64);
     uint32_t first, det;
-    const uint32_t end = chunk_u8_to_u16<PAD, LIM, DUMP>(x, xp, full, q0, lo, hi, incl - cnt, stage, &first, &det);
+    const uint32_t end =
+        chunk_u8_to_u16<PAD, LIM, DUMP>(x, xp, full, q0, lo, hi, incl - cnt, stage, &first, &det, m);
     const uint32_t st0 = __shfl(first, 0, 64);
     uint32_t st1 = __shfl(end, 63, 64);
     st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
@@ -557,7 +557,7 @@ __device__ __forceinline__ void rows_u8_to_u16(const BatchArgs& A, const BItem& 
   const uint32_t tot = __shfl(incl, rb + 15, 64);
   uint32_t first, det;
   const uint32_t end = chunk_u8_to_u16<PAD, LIM, DUMP>(x, row_prev(x[3]), false, q0, lo, hi, incl - cnt, stage,
-                                                       &first, &det);
+                                                       &first, &det, m);
   const uint32_t st0 = __shfl(first, rb, 64);
   uint32_t st1 = __shfl(end, rb + 15, 64);
   st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);

@@ -173,15 +173,26 @@ __device__ __forceinline__ uint32_t spill8(uint32_t Cp) {
 template <uint32_t PAD, uint32_t LIM, uint32_t DUMP>
 __device__ __forceinline__ uint32_t chunk_u8_to_u16(const uint32_t x[4], uint32_t xp, bool full, uint64_t q0,
                                                     uint64_t lo, uint64_t hi, uint32_t off, uint16_t* stage,
-                                                    uint32_t* first, uint32_t* det_out) {
+                                                    uint32_t* first, uint32_t* det_out,
+                                                    const uint32_t* mE = nullptr) {
   Chunk8 ch;
 #pragma unroll
   for (int i = 0; i < 4; ++i) ch.x[i] = x[i];
   ch.xp = xp;
   uint32_t inE[4], inD[4], E[4], W[8], cnt, det;
   if (!full) {
-    range_masks(q0, lo, hi, inE);
-    range_masks(q0, lo, hi + 1, inD);
+    // [lo, hi) (the caller's masks when it has them) and [lo, hi]: the same plus the
+    // byte at hi
+    if (mE) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) inE[k] = mE[k];
+    } else {
+      range_masks(q0, lo, hi, inE);
+    }
+    const int64_t t = (int64_t)hi - (int64_t)q0;
+    const uint32_t tt = (t >= 0 && t < 16) ? (uint32_t)t : 16u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) inD[k] = inE[k] | ((tt >> 2) == (uint32_t)k ? 0xFFu << (8 * (tt & 3)) : 0u);
   }
   const int cls = classify8(ch);
   process8_any<true>(cls, full, ch, inE, inD, E, cnt, det, W);
