@@ -39,10 +39,12 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size-mib", type=int, default=256, help="bytes per buffer (MiB)")
     ap.add_argument("--rotate", type=int, default=3, help="device copies per input")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="contexts, each on its own stream, that the timed steps' calls alternate over")
     ap.add_argument("--cpu-sample-mib", type=int, default=128, help="oracle sample per C2 case (MiB)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profiles", default="ascii,latin,cjk,emoji")
@@ -80,11 +82,14 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = utfx.Context()
-    tuned = False if args.no_tune_cache else ctx.load_tuning()
-    for op, spec in ((utfx.OP_UTF8_TO_UTF16, args.u8), (utfx.OP_UTF16_TO_UTF8, args.u16)):
-        if spec:
-            t, sg = (int(v) for v in spec.split(","))
-            ctx.set_tuning(op, t, sg)
+    # further contexts on streams of their own (default priority) for --streams
+    ctxs = [ctx] + [utfx.Context(stream=torch.cuda.Stream()) for _ in range(max(args.streams, 1) - 1)]
+    for c in ctxs:
+        tuned = False if args.no_tune_cache else c.load_tuning()
+        for op, spec in ((utfx.OP_UTF8_TO_UTF16, args.u8), (utfx.OP_UTF16_TO_UTF8, args.u16)):
+            if spec:
+                t, sg = (int(v) for v in spec.split(","))
+                c.set_tuning(op, t, sg)
     nbytes = args.size_mib * MIB
     profiles = args.profiles.split(",")
     cases = []  # (profile, direction, host_input, [device copies], device_output, in_bytes, out_bytes)
@@ -103,16 +108,16 @@ def main():
             log("generated %s dir=%d in %.1fs" % (prof, d, time.time() - t0))
     res = utfx.result_tensor(len(cases) * 2)
 
-    def call(i, rot):
+    def call(i, rot, c=ctx):
         prof, d, host, copies, out, nb, _ = cases[i]
         src = copies[rot % len(copies)]
         r = res[24 * i:24 * i + 24]
         if d == synth.DIR_8TO16:
-            st = ctx.utf8_to_utf16le_async(src, out, r)
+            st = c.utf8_to_utf16le_async(src, out, r)
         else:
-            st = ctx.utf16le_to_utf8_async(src, out, r)
+            st = c.utf16le_to_utf8_async(src, out, r)
         if st != utfx.OK:
-            raise RuntimeError("launch failed: %d %s" % (st, ctx.last_error()))
+            raise RuntimeError("launch failed: %d %s" % (st, c.last_error()))
 
     # correctness of the timed configuration (results only; parity tests cover bytes)
     for i in range(len(cases)):
@@ -128,18 +133,20 @@ def main():
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
         for i in range(len(cases)):
-            call(i, w)
+            call(i, w, ctxs[i % len(ctxs)])
     torch.cuda.synchronize()
 
     def evpair():
         return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    # the timed steps: the calls alone, back to back on the stream
+    # the timed steps: the calls alone, back to back on the stream (with --streams, call i
+    # on context i mod streams, so that a call's finalisation and last workgroups overlap
+    # the next call)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         for i in range(len(cases)):
-            call(i, s + 1)
+            call(i, s + 1, ctxs[i % len(ctxs)])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
@@ -260,6 +267,7 @@ def main():
         "config": {"workload": "four %d MiB buffers (ascii, latin, cjk, emoji profiles), each transcoded "
                                "UTF-8->UTF-16LE and UTF-16LE->UTF-8 with validation" % args.size_mib,
                    "buffers": len(cases), "bytes_per_buffer": nbytes, "rotate": args.rotate,
+                   "streams": len(ctxs),
                    "tuning": {"utf8->utf16le": list(ctx.get_tuning(0)), "utf16le->utf8": list(ctx.get_tuning(1)),
                               "source": "tune_cache.json" if tuned else "defaults"}},
         "roofline": {"bound": "hbm", "kernel": kernel, "case": case_name,
@@ -288,7 +296,8 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
+    for c in ctxs:
+        c.close()
 
 
 def cpu_baseline(cases, sample_mib, log):
