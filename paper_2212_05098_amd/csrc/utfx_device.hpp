@@ -113,6 +113,27 @@ __device__ __forceinline__ uint32_t lanemask_hi(uint32_t f) { return perm(f, f <
 __device__ __forceinline__ uint32_t zx_lo(uint32_t v) { return perm(0u, v, 0x0C010C00u); }
 __device__ __forceinline__ uint32_t zx_hi(uint32_t v) { return perm(0u, v, 0x0C030C02u); }
 
+// a + byte SEL of b in one instruction (an SDWA operand select).  Written out because
+// the compiler extracts the byte with a separate shift and mask.
+template <int SEL>
+__device__ __forceinline__ uint32_t add_byte(uint32_t a, uint32_t b) {
+  static_assert(SEL >= 0 && SEL < 4, "byte select");
+  uint32_t r;
+  if constexpr (SEL == 0)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (SEL == 1)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+        : "=v"(r) : "v"(a), "v"(b));
+  else if constexpr (SEL == 2)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+        : "=v"(r) : "v"(a), "v"(b));
+  else
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+        : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ us2 as_us2(uint32_t v) { return __builtin_bit_cast(us2, v); }
 __device__ __forceinline__ uint32_t as_u32(us2 v) { return __builtin_bit_cast(uint32_t, v); }

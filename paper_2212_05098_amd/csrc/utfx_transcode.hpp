@@ -198,43 +198,43 @@ __device__ __forceinline__ uint32_t chunk_u8_to_u16(const uint32_t x[4], uint32_
   process8_any<true>(cls, full, ch, inE, inD, E, cnt, det, W);
   uint32_t idx = PAD + off - spill8(ch.Cp);
   *first = idx;
-  // Scatter.  In a chunk wholly inside the input, a non-emitting position writes a
-  // placeholder at the slot of the next emit, which that emit overwrites: inside a
-  // valid prefix at most two positions in a row do not emit, so only the last two
-  // positions can lack a later emit in the chunk, and those write only real words.
-  // Past the first error every slot is at or beyond the valid prefix's length, and a
-  // chunk whose slots would leave the stage is past it and writes to a dump area.
-  // Writes that must not land go to the dump slot, so the loop has no branches.
+  // Scatter.  A non-emitting position writes a placeholder at the slot of the next
+  // emit, which that emit overwrites: inside a valid prefix at most two positions in a
+  // row do not emit, so only the last two positions can lack a later emit in the chunk,
+  // and those write only real words.  Positions outside the input (a chunk at an end)
+  // emit nothing: before the input they are followed by the chunk's first emit, and
+  // after it every later chunk is outside too; a chunk with no emit at all writes to the
+  // dump area.  Past the first error every slot is at or beyond the valid prefix's
+  // length, and a chunk whose slots would leave the stage is past it and writes to the
+  // dump area.  The byte address of each write is the previous one plus 2 when the
+  // previous position emitted: B holds those steps per byte, one add of a byte field
+  // each.
   const bool fits = idx + 16 <= LIM;
-  uint16_t* pw = stage + (fits ? idx : DUMP);
+  const bool any = full || (E[0] | E[1] | E[2] | E[3]) != 0;
+  char* const sb = reinterpret_cast<char*>(stage);
   uint16_t* const dump = stage + DUMP;
-  if (full) {
+  uint32_t a = (fits && any) ? 2u * idx : 2u * DUMP;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < 4; ++kk) {
+    const uint32_t B = (E[kk] >> 6) & 0x02020202u;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e = 4 * kk + i;
-        const uint32_t pair = W[2 * kk + (i >> 1)];
-        const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+    for (int i = 0; i < 4; ++i) {
+      const int e = 4 * kk + i;
+      const uint32_t pair = W[2 * kk + (i >> 1)];
+      const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
+      if (e < 14) {
+        *reinterpret_cast<uint16_t*>(sb + a) = word;
+      } else {
         const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
-        *((e < 14 || bit) ? pw : dump) = word;
-        pw += bit;
+        *(bit ? reinterpret_cast<uint16_t*>(sb + a) : dump) = word;
       }
-    }
-  } else {
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t pair = W[2 * kk + (i >> 1)];
-        const uint16_t word = (uint16_t)((i & 1) ? (pair >> 16) : (pair & 0xFFFFu));
-        const uint32_t bit = (E[kk] >> (8 * i + 7)) & 1u;
-        *(bit ? pw : dump) = word;
-        pw += bit;
-      }
+      if (i == 0) a = add_byte<0>(a, B);
+      else if (i == 1) a = add_byte<1>(a, B);
+      else if (i == 2) a = add_byte<2>(a, B);
+      else a = add_byte<3>(a, B);
     }
   }
-  idx = fits ? (uint32_t)(pw - stage) : LIM;
+  idx = !fits ? LIM : (any ? a / 2u : idx);
   *det_out = det;
   return idx;
 }
