@@ -59,3 +59,28 @@ def test_traffic_calibration_and_staleness(tmp_path):
     assert profsum.read_traffic(str(p), "k_u16_to_u8", "case x") is None
     p.write_text(text.replace("kernel_sources: %s" % profsum.source_hash(), "kernel_sources: 0000000000000000"))
     assert profsum.read_traffic(str(p), "k_u8_to_u16", "case x") is None
+
+
+def test_counters_per_input_and_rates(tmp_path):
+    fields = ["Kernel_Name", "Dispatch_Id", "Counter_Name", "Counter_Value"]
+    rows = []
+    for i in range(1, 9):  # dispatches alternate between inputs a (odd) and b (even)
+        a = i % 2 == 1
+        clk = 24000 if a else 48000  # 10 us and 20 us at 2.4 GHz
+        vals = {"GRBM_GUI_ACTIVE": 8 * clk, "SQ_INSTS_VALU": 1024 * (276 if a else 474),
+                "SQ_WAIT_ANY": 256 * clk * (0.5 if a else 0.25)}
+        for c, v in vals.items():
+            rows.append({"Kernel_Name": "void utfx_dev::k_u8_to_u16<512, 4>(Launch)", "Dispatch_Id": i,
+                         "Counter_Name": c, "Counter_Value": float(v)})
+    rows.append({"Kernel_Name": "k_other", "Dispatch_Id": 9, "Counter_Name": "SQ_INSTS_VALU",
+                 "Counter_Value": 1.0})
+    _write(str(tmp_path / "c" / "run_counter_collection.csv"), fields, rows)
+    text = profsum.counters_text(str(tmp_path / "c"), "cmd", ["a", "b"], input_kib=1024.0)
+    lines = text.splitlines()
+    assert "# kernel sources: %s" % profsum.source_hash() in text and "k_other" not in text
+    ia = lines.index("void k_u8_to_u16<512, 4> [a]: 4 launches, 10.0 us at 2.4 GHz")
+    ib = lines.index("void k_u8_to_u16<512, 4> [b]: 4 launches, 20.0 us at 2.4 GHz")
+    a = {l.split()[0]: l.split()[-2] for l in lines[ia + 1:ib]}
+    b = {l.split()[0]: l.split()[-2] for l in lines[ib + 1:]}
+    assert a == {"SQ_INSTS_VALU": "276.0", "SQ_WAIT_ANY": "0.500"}
+    assert b == {"SQ_INSTS_VALU": "474.0", "SQ_WAIT_ANY": "0.250"}
