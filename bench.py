@@ -70,7 +70,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -236,7 +236,8 @@ def main():
 
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%dMiB.txt" % (kernel, args.size_mib))
     traffic = profsum.read_traffic(tpath, kernel, case_name)
-    # the same kernel's timed launches under rocprofv3 (committed summary of this build)
+    # the same kernel's timed launches under rocprofv3 (the committed summary, used while
+    # its kernel sources match the library's)
     rp_us = profsum.read_timed_us(os.path.join(ROOT, "profiles", "kernel_trace_transcode_4profiles_%dMiB.txt" %
                                                args.size_mib), kernel)
 

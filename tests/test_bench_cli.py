@@ -1,5 +1,5 @@
-"""bench.py's contract on the CPU: more than one GPU is refused with a message (this
-build measures one GPU), before anything touches a device."""
+"""bench.py's contract on the CPU: more than one GPU is refused with a message (the
+library runs on one GPU), before anything touches a device."""
 import os
 import subprocess
 import sys
