@@ -96,25 +96,27 @@ def stats_text(d: str, cmd: str, cycle=None, timed: int = 0) -> str:
     return "\n".join(out) + "\n"
 
 
-def counters_text(d: str, cmd: str, cycle, input_kib: float, cus: int = 256, xcds: int = 8) -> str:
-    """Per main kernel and input (dispatch i ran on input i mod len(cycle)): the average
-    value per launch of every counter of a `--pmc` run, SQ_INSTS_* also per KiB of input,
-    the others also per CU per clock; the clocks of a launch are GRBM_GUI_ACTIVE over the
-    XCDs (it counts on each of them)."""
+def counters_text(d: str, cmd: str, cycle, input_kib: float, cus: int = 256, xcds: int = 8,
+                  kernels=("k_u8_to_u16<", "k_u16_to_u8<")) -> str:
+    """Per kernel (names containing one of `kernels`) and input (dispatch i ran on input
+    i mod len(cycle)): the average value per launch of every counter of a `--pmc` run,
+    SQ_INSTS_* also per KiB of input and per CU per clock, the others per CU per clock;
+    the clocks of a launch are GRBM_GUI_ACTIVE over the XCDs (it counts on each of
+    them)."""
     rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
     per = collections.OrderedDict()  # (kernel, dispatch) -> {counter: value}
     for r in rows:
         k = r["Kernel_Name"]
-        if not ("k_u8_to_u16<" in k or "k_u16_to_u8<" in k):
+        if not any(s in k for s in kernels):
             continue
         per.setdefault((_short(k).split("(")[0], int(r["Dispatch_Id"])), {})[r["Counter_Name"]] = \
             float(r["Counter_Value"])
-    out = ["# rocprofv3 counters of the transcode kernels", "# command: %s" % cmd,
+    out = ["# rocprofv3 counters of %s" % ", ".join(s.rstrip("<(") for s in kernels), "# command: %s" % cmd,
            "# kernel sources: %s" % source_hash(),
            "# per launch: average over the launches of each input; /KiB: per KiB of input; /CU/clk: per CU",
            "# per clock, clocks = GRBM_GUI_ACTIVE / %d XCDs (the SQ cycle counters are as read)" % xcds]
-    kernels = sorted({k for k, _ in per}, key=lambda k: min(i for kk, i in per if kk == k))
-    for k in kernels:
+    found = sorted({k for k, _ in per}, key=lambda k: min(i for kk, i in per if kk == k))
+    for k in found:
         disp = sorted(i for kk, i in per if kk == k)
         for j, name in enumerate(cycle):
             ds = disp[j::len(cycle)]
@@ -128,7 +130,8 @@ def counters_text(d: str, cmd: str, cycle, input_kib: float, cus: int = 256, xcd
                 if c == "GRBM_GUI_ACTIVE":
                     continue
                 if c.startswith("SQ_INSTS"):
-                    parts.append("  %-24s %14.0f  %10.1f /KiB" % (c, avg[c], avg[c] / input_kib))
+                    parts.append("  %-24s %14.0f  %10.1f /KiB  %8.3f /CU/clk" %
+                                 (c, avg[c], avg[c] / input_kib, avg[c] / (cus * clk) if clk else 0.0))
                 elif clk:
                     parts.append("  %-24s %14.0f  %10.3f /CU/clk" % (c, avg[c], avg[c] / (cus * clk)))
             out.extend(parts)
@@ -240,10 +243,13 @@ def main(argv=None):
     c.add_argument("dir")
     c.add_argument("--cmd", required=True)
     c.add_argument("--cycle", required=True, help="comma-separated inputs the kernels cycle through")
+    c.add_argument("--kernels", default="k_u8_to_u16<,k_u16_to_u8<",
+                   help="comma-separated parts of the kernel names to summarise")
     c.add_argument("--input-kib", type=float, required=True, help="input KiB per launch")
     a = ap.parse_args(argv)
     if a.what == "counters":
-        sys.stdout.write(counters_text(a.dir, a.cmd, [x for x in a.cycle.split(",") if x], a.input_kib))
+        sys.stdout.write(counters_text(a.dir, a.cmd, [x for x in a.cycle.split(",") if x], a.input_kib,
+                                       kernels=tuple(k for k in a.kernels.split(",") if k)))
     elif a.what == "stats":
         sys.stdout.write(stats_text(a.dir, a.cmd, [c for c in a.cycle.split(",") if c], a.timed))
     else:

@@ -80,7 +80,11 @@ def test_counters_per_input_and_rates(tmp_path):
     assert "# kernel sources: %s" % profsum.source_hash() in text and "k_other" not in text
     ia = lines.index("void k_u8_to_u16<512, 4> [a]: 4 launches, 10.0 us at 2.4 GHz")
     ib = lines.index("void k_u8_to_u16<512, 4> [b]: 4 launches, 20.0 us at 2.4 GHz")
-    a = {l.split()[0]: l.split()[-2] for l in lines[ia + 1:ib]}
-    b = {l.split()[0]: l.split()[-2] for l in lines[ib + 1:]}
-    assert a == {"SQ_INSTS_VALU": "276.0", "SQ_WAIT_ANY": "0.500"}
-    assert b == {"SQ_INSTS_VALU": "474.0", "SQ_WAIT_ANY": "0.250"}
+    a = {l.split()[0]: l.split()[2:] for l in lines[ia + 1:ib]}
+    b = {l.split()[0]: l.split()[2:] for l in lines[ib + 1:]}
+    # instructions per KiB of input and per CU per clock (1024 * 276 / (256 * 24000))
+    assert a == {"SQ_INSTS_VALU": ["276.0", "/KiB", "0.046", "/CU/clk"], "SQ_WAIT_ANY": ["0.500", "/CU/clk"]}
+    assert b == {"SQ_INSTS_VALU": ["474.0", "/KiB", "0.040", "/CU/clk"], "SQ_WAIT_ANY": ["0.250", "/CU/clk"]}
+    # another kernel chosen by name
+    other = profsum.counters_text(str(tmp_path / "c"), "cmd", ["x"], input_kib=1.0, kernels=("k_other",))
+    assert "k_other [x]: 1 launches" in other and "k_u8_to_u16" not in other.split("\n", 1)[1]
