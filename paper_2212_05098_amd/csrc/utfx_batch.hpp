@@ -314,18 +314,33 @@ __device__ __forceinline__ void load8_masked(const Launch& L, uint64_t q0, const
 
 // Loads the wave's 1 KiB step at grid position c0 of a UTF-8 string [lo, hi) into x
 // (bytes outside the string read as 0) and returns whether every lane's chunk lies
-// wholly inside it (wave-uniform).
-__device__ __forceinline__ bool wave_load8(const Launch& L, uint64_t c0, uint64_t lo, uint64_t hi, uintptr_t alo,
-                                           uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
-  const uint64_t q0 = c0 + 16ull * lane;
+// wholly inside it (wave-uniform).  base: the string's start aligned down to 16 bytes;
+// positions are 32-bit (a walked string is far shorter than 2^31 bytes).
+__device__ __forceinline__ bool wave_load8(const uint8_t* base, uint32_t c0, uint32_t lo, uint32_t hi,
+                                           uintptr_t alo, uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
+  const uint32_t q0 = c0 + 16u * lane;
   const bool full = c0 >= lo && c0 + 1024 <= hi;  // every lane's chunk (the same test per lane)
   if (full) {
-    const uint4 v = *reinterpret_cast<const uint4*>(L.base + q0);
+    const uint4 v = *reinterpret_cast<const uint4*>(base + q0);
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
   } else {
     uint32_t m[4];
-    range_masks(q0, lo, hi, m);
-    load8_masked(L, q0, m, alo, ahi, x);
+    range_masks32(q0, lo, hi, m);
+    x[0] = x[1] = x[2] = x[3] = 0;
+    if ((m[0] | m[1] | m[2] | m[3]) != 0) {
+      const uintptr_t a = (uintptr_t)(base + q0);
+      if (a >= alo && a + 16 <= ahi) {
+        const uint4 v = *reinterpret_cast<const uint4*>(a);
+        x[0] = v.x & m[0]; x[1] = v.y & m[1]; x[2] = v.z & m[2]; x[3] = v.w & m[3];
+      } else {
+        // at an end of the arena: only the string's own bytes are read
+#pragma unroll
+        for (uint32_t i = 0; i < 16; ++i) {
+          const uint32_t q = q0 + i;
+          if (q >= lo && q < hi) x[i >> 2] |= (uint32_t)base[q] << (8 * (i & 3));
+        }
+      }
+    }
   }
   return full;
 }
@@ -345,22 +360,26 @@ __device__ __forceinline__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, ui
   L.base = reinterpret_cast<const uint8_t*>((uintptr_t)in & ~(uintptr_t)15);
   L.mis = (uintptr_t)in & 15;
   L.n = n;
-  const uint64_t lo = L.mis, hi = L.mis + n;
-  uint64_t running = 0;  // formula units before the chunk
+  // positions, offsets and the capacity in 32 bits: n <= small_max <= 2^18, so every
+  // position and output offset of the walk stays below 2^20; the capacity is clamped
+  // to 2^30 - 1, which no offset reaches, so that no index difference overflows
+  const uint32_t lo = (uint32_t)L.mis, hi = (uint32_t)(L.mis + n);
+  const int32_t cap32 = cap > 0x3FFFFFFFull ? 0x3FFFFFFF : (int32_t)cap;
+  uint32_t running = 0;  // formula units before the chunk
   uint32_t carry = 0;    // the 4 bytes before the chunk
   uint64_t err = NO_ERR;
   uint32_t xn[4];
-  bool fulln = wave_load8(L, 0, lo, hi, alo, ahi, lane, xn);
-  for (uint64_t c0 = 0; c0 <= hi; c0 += 1024) {
-    const uint64_t q0 = c0 + 16ull * lane;
+  bool fulln = wave_load8(L.base, 0, lo, hi, alo, ahi, lane, xn);
+  for (uint32_t c0 = 0; c0 <= hi; c0 += 1024) {
+    const uint32_t q0 = c0 + 16u * lane;
     const bool full = fulln;
     uint32_t x[4] = {xn[0], xn[1], xn[2], xn[3]};
-    if (c0 + 1024 <= hi) fulln = wave_load8(L, c0 + 1024, lo, hi, alo, ahi, lane, xn);
+    if (c0 + 1024 <= hi) fulln = wave_load8(L.base, c0 + 1024, lo, hi, alo, ahi, lane, xn);
     uint32_t cnt, m[4];
     if (full) {
       cnt = count8(x, nullptr);
     } else {
-      range_masks(q0, lo, hi, m);
+      range_masks32(q0, lo, hi, m);
       cnt = count8(x, m);
     }
     const uint32_t incl = wave_incl_scan(cnt);
@@ -374,7 +393,7 @@ __device__ __forceinline__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, ui
     uint32_t st1 = __shfl(end, 63, 64);
     st1 = st1 < st0 ? st0 : (st1 > LIM ? LIM : st1);
     __builtin_amdgcn_wave_barrier();
-    store_span<uint16_t>(stage, st0, st1 - st0, out, running + st0 - PAD, cap, lane, 64);
+    store_span<uint16_t, int32_t>(stage, st0, st1 - st0, out, (int32_t)(running + st0 - PAD), cap32, lane, 64);
     __builtin_amdgcn_wave_barrier();
     if (__any(det)) {
       uint64_t e = NO_ERR;
@@ -393,11 +412,11 @@ __device__ __forceinline__ void wave_u8_to_u16(const uint8_t* in, uint64_t n, ui
   if (err != NO_ERR) {
     // words of the valid prefix: the length formula over [0, err)
     uint64_t acc = 0;
-    for (uint64_t c0 = 0; c0 < lo + err; c0 += 1024) {
+    for (uint64_t c0 = 0; c0 < L.mis + err; c0 += 1024) {
       const uint64_t q0 = c0 + 16ull * lane;
       uint32_t x[4], m[4];
       load8(L, q0, x);
-      range_masks(q0, lo, lo + err, m);
+      range_masks(q0, L.mis, L.mis + err, m);
       acc += count8(x, m);
     }
     acc = wave_sum_u64(acc);
@@ -424,17 +443,31 @@ __device__ __forceinline__ void load16_masked(const Launch& L, uint64_t q0, cons
 
 // Loads the wave's 512-word step at grid position c0 of a UTF-16 string [lo, hi) into x
 // (words outside the string read as 0); returns whether it lies wholly inside.
-__device__ __forceinline__ bool wave_load16(const Launch& L, uint64_t c0, uint64_t lo, uint64_t hi, uintptr_t alo,
-                                            uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
-  const uint64_t q0 = c0 + 8ull * lane;
+__device__ __forceinline__ bool wave_load16(const uint8_t* base, uint32_t c0, uint32_t lo, uint32_t hi,
+                                            uintptr_t alo, uintptr_t ahi, uint32_t lane, uint32_t x[4]) {
+  const uint32_t q0 = c0 + 8u * lane;
   const bool full = c0 >= lo && c0 + 512 <= hi;  // every lane's chunk (the same test per lane)
   if (full) {
-    const uint4 v = *reinterpret_cast<const uint4*>(L.base + 2 * q0);
+    const uint4 v = *reinterpret_cast<const uint4*>(base + 2 * q0);
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
   } else {
     uint32_t m[4];
-    word_masks(q0, lo, hi, m);
-    load16_masked(L, q0, m, alo, ahi, x);
+    word_masks32(q0, lo, hi, m);
+    x[0] = x[1] = x[2] = x[3] = 0;
+    if ((m[0] | m[1] | m[2] | m[3]) != 0) {
+      const uintptr_t a = (uintptr_t)(base + 2 * q0);
+      if (a >= alo && a + 16 <= ahi) {
+        const uint4 v = *reinterpret_cast<const uint4*>(a);
+        x[0] = v.x & m[0]; x[1] = v.y & m[1]; x[2] = v.z & m[2]; x[3] = v.w & m[3];
+      } else {
+        const uint16_t* w = reinterpret_cast<const uint16_t*>(base);
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+          const uint32_t q = q0 + i;
+          if (q >= lo && q < hi) x[i >> 1] |= (uint32_t)w[q] << (16 * (i & 1));
+        }
+      }
+    }
   }
   return full;
 }
@@ -450,19 +483,21 @@ __device__ __forceinline__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, u
   L.base = reinterpret_cast<const uint8_t*>((uintptr_t)in & ~(uintptr_t)15);
   L.mis = ((uintptr_t)in & 15) / 2;
   L.n = n;
-  const uint64_t lo = L.mis, hi = L.mis + n;
-  uint64_t running = 0;
+  // 32-bit positions, offsets and capacity, as in wave_u8_to_u16 (output <= 3n bytes)
+  const uint32_t lo = (uint32_t)L.mis, hi = (uint32_t)(L.mis + n);
+  const int32_t cap32 = cap > 0x3FFFFFFFull ? 0x3FFFFFFF : (int32_t)cap;
+  uint32_t running = 0;
   uint32_t carry = 0;  // high half: the word before the chunk
   uint64_t err = NO_ERR;
   uint32_t xn[4];
-  bool fulln = wave_load16(L, 0, lo, hi, alo, ahi, lane, xn);
-  for (uint64_t c0 = 0; c0 <= hi; c0 += 512) {
-    const uint64_t q0 = c0 + 8ull * lane;
+  bool fulln = wave_load16(L.base, 0, lo, hi, alo, ahi, lane, xn);
+  for (uint32_t c0 = 0; c0 <= hi; c0 += 512) {
+    const uint32_t q0 = c0 + 8u * lane;
     const bool full = fulln;
     uint32_t x[4] = {xn[0], xn[1], xn[2], xn[3]};
-    if (c0 + 512 <= hi) fulln = wave_load16(L, c0 + 512, lo, hi, alo, ahi, lane, xn);
+    if (c0 + 512 <= hi) fulln = wave_load16(L.base, c0 + 512, lo, hi, alo, ahi, lane, xn);
     uint32_t m[4];
-    if (!full) word_masks(q0, lo, hi, m);
+    if (!full) word_masks32(q0, lo, hi, m);
     const uint32_t cnt = full ? count16(x, nullptr) : count16(x, m);
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t tot = __shfl(incl, 63, 64);
@@ -471,7 +506,7 @@ __device__ __forceinline__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, u
     const bool det = full ? chunk_u16_to_u8(x, xprev, nullptr, stage + PAD + (incl - cnt), stage + DUMP)
                           : chunk_u16_to_u8(x, xprev, m, stage + PAD + (incl - cnt), stage + DUMP);
     __builtin_amdgcn_wave_barrier();
-    store_span<uint8_t>(stage, PAD, tot, out, running, cap, lane, 64);
+    store_span<uint8_t, int32_t>(stage, PAD, tot, out, (int32_t)running, cap32, lane, 64);
     __builtin_amdgcn_wave_barrier();
     if (__any(det)) {
       uint64_t e = NO_ERR;
@@ -489,11 +524,11 @@ __device__ __forceinline__ void wave_u16_to_u8(const uint16_t* in, uint64_t n, u
   }
   if (err != NO_ERR) {
     uint64_t acc = 0;
-    for (uint64_t c0 = 0; c0 < lo + err; c0 += 512) {
+    for (uint64_t c0 = 0; c0 < L.mis + err; c0 += 512) {
       const uint64_t q0 = c0 + 8ull * lane;
       uint32_t x[4], m[4];
       load16(L, q0, x);
-      word_masks(q0, lo, lo + err, m);
+      word_masks(q0, L.mis, L.mis + err, m);
       acc += count16(x, m);
     }
     acc = wave_sum_u64(acc);
@@ -683,9 +718,8 @@ __global__ void __launch_bounds__(BWG) __attribute__((amdgpu_waves_per_eu(4))) k
 // and the longest strings start first.  Waves past the lists' end exit; the list
 // lengths are read through the scalar cache, so those waves leave quickly.  (A
 // persistent loop over the lists instead needs more than 96 VGPRs and spills.)  At
-// most 80 VGPRs: six waves per SIMD, with 32 bytes of spill (2-3 % faster on the
-// 200,000-string batch than five waves without spill; eight waves spill 112 bytes and
-// are 15 % slower).
+// most 80 VGPRs: six waves per SIMD, which the walkers' 32-bit positions fit without
+// spill (five waves per SIMD measured 2-4 % slower than six).
 constexpr int SMALL_WG = 256;
 __global__ void __launch_bounds__(SMALL_WG) __attribute__((amdgpu_waves_per_eu(6))) k_batch_small(BatchArgs A) {
   constexpr int NW = SMALL_WG / 64;

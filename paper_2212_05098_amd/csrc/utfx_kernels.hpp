@@ -60,14 +60,10 @@ __device__ __forceinline__ uint32_t load8_prev(const Launch& L, uint64_t q0) {
   return r;
 }
 
-// Byte masks (0xFF per byte) of the chunk's grid positions in [lo, hi).
-__device__ __forceinline__ void range_masks(uint64_t q0, uint64_t lo, uint64_t hi, uint32_t m[4]) {
-  // byte i of the chunk is in range iff a <= i < b; per byte, with a bias of 0x80 so
-  // that no subtraction borrows into the next byte: (i | 0x80) - a keeps bit 7 iff
-  // i >= a, and (b | 0x80) - (i + 1) keeps it iff i < b
-  const int64_t a64 = (int64_t)lo - (int64_t)q0, b64 = (int64_t)hi - (int64_t)q0;
-  const uint32_t a = a64 <= 0 ? 0u : (a64 >= 16 ? 16u : (uint32_t)a64);
-  const uint32_t b = b64 <= 0 ? 0u : (b64 >= 16 ? 16u : (uint32_t)b64);
+// Byte masks (0xFF per byte) of the chunk bytes a <= i < b (0 <= a, b <= 16).
+__device__ __forceinline__ void byte_masks_ab(uint32_t a, uint32_t b, uint32_t m[4]) {
+  // per byte, with a bias of 0x80 so that no subtraction borrows into the next byte:
+  // (i | 0x80) - a keeps bit 7 iff i >= a, and (b | 0x80) - (i + 1) keeps it iff i < b
   const uint32_t A = a * 0x01010101u, B = (b * 0x01010101u) | HI;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -75,6 +71,23 @@ __device__ __forceinline__ void range_masks(uint64_t q0, uint64_t lo, uint64_t h
     const uint32_t in = ((idx | HI) - A) & (B - (idx + 0x01010101u)) & HI;
     m[k] = (in >> 7) * 0xFFu;
   }
+}
+
+// Byte masks (0xFF per byte) of the chunk's grid positions in [lo, hi).
+__device__ __forceinline__ void range_masks(uint64_t q0, uint64_t lo, uint64_t hi, uint32_t m[4]) {
+  const int64_t a64 = (int64_t)lo - (int64_t)q0, b64 = (int64_t)hi - (int64_t)q0;
+  const uint32_t a = a64 <= 0 ? 0u : (a64 >= 16 ? 16u : (uint32_t)a64);
+  const uint32_t b = b64 <= 0 ? 0u : (b64 >= 16 ? 16u : (uint32_t)b64);
+  byte_masks_ab(a, b, m);
+}
+
+// range_masks in 32-bit arithmetic, for positions below 2^31 (one wave walking one
+// string).
+__device__ __forceinline__ void range_masks32(uint32_t q0, uint32_t lo, uint32_t hi, uint32_t m[4]) {
+  const int32_t a32 = (int32_t)lo - (int32_t)q0, b32 = (int32_t)hi - (int32_t)q0;
+  const uint32_t a = a32 <= 0 ? 0u : (a32 >= 16 ? 16u : (uint32_t)a32);
+  const uint32_t b = b32 <= 0 ? 0u : (b32 >= 16 ? 16u : (uint32_t)b32);
+  byte_masks_ab(a, b, m);
 }
 
 // ================================================================ UTF-8 classification

@@ -36,18 +36,25 @@ __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t first) {
 // (0 <= l < total) goes to out[base + l].  16-byte chunks aligned to the destination
 // are gathered from the stage with dword reads and a byte funnel shift; elements at or
 // beyond cap are never stored.  The stage must hold 16 readable bytes past s0 + total.
-template <typename U>
-__device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t total, U* out, uint64_t base,
-                                           uint64_t cap, uint32_t tid, uint32_t nthr, bool swap16 = false) {
+// I: the signed type of destination indices (32-bit where base + total and cap are
+// known to stay below 2^31).
+template <typename T>
+struct NoDeduce {
+  typedef T type;
+};
+template <typename U, typename I = int64_t>
+__device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t total, U* out,
+                                           typename NoDeduce<I>::type base, typename NoDeduce<I>::type cap,
+                                           uint32_t tid, uint32_t nthr, bool swap16 = false) {
   constexpr uint32_t PER = 16 / sizeof(U);
-  const uint32_t d = (uint32_t)((((uintptr_t)out / sizeof(U)) + base) & (PER - 1));
+  const uint32_t d = ((uint32_t)((uintptr_t)out / sizeof(U)) + (uint32_t)base) & (PER - 1);
   const uint32_t nch = (d + total + PER - 1) / PER;
-  const int64_t g_first = (int64_t)base - (int64_t)d;
+  const I g_first = base - (I)d;
   const uint32_t* s32 = reinterpret_cast<const uint32_t*>(stage);
   for (uint32_t k = tid; k < nch; k += nthr) {
-    const int64_t g0 = g_first + (int64_t)(k * PER);
+    const I g0 = g_first + (I)(k * PER);
     const uint32_t l0 = k * PER;  // chunk covers elements l0 - d .. l0 - d + PER - 1
-    if (l0 >= d && l0 + PER <= d + total && g0 + (int64_t)PER <= (int64_t)cap) {
+    if (l0 >= d && l0 + PER <= d + total && g0 + (I)PER <= cap) {
       const uint32_t b0 = (s0 + l0 - d) * sizeof(U);
       const uint32_t w0 = b0 >> 2, sh = b0 & 3;
       const uint32_t v0 = s32[w0], v1 = s32[w0 + 1], v2 = s32[w0 + 2], v3 = s32[w0 + 3], v4 = s32[w0 + 4];
@@ -67,11 +74,11 @@ __device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t
       // An edge chunk: its elements i_lo <= i < i_hi lie in the span and in [0, cap).
       // They are gathered like a whole chunk (s0 >= d, so the window starts inside the
       // stage; it ends within 20 bytes past the span) and stored one by one.
-      int64_t a = (int64_t)d - (int64_t)l0, b = (int64_t)d + (int64_t)total - (int64_t)l0;
+      I a = (I)d - (I)l0, b = (I)d + (I)total - (I)l0;
       a = a > -g0 ? a : -g0;
-      b = b < (int64_t)cap - g0 ? b : (int64_t)cap - g0;
-      const uint32_t i_lo = a <= 0 ? 0u : (a >= (int64_t)PER ? PER : (uint32_t)a);
-      const uint32_t i_hi = b <= 0 ? 0u : (b >= (int64_t)PER ? PER : (uint32_t)b);
+      b = b < cap - g0 ? b : cap - g0;
+      const uint32_t i_lo = a <= 0 ? 0u : (a >= (I)PER ? PER : (uint32_t)a);
+      const uint32_t i_hi = b <= 0 ? 0u : (b >= (I)PER ? PER : (uint32_t)b);
       if (i_lo < i_hi) {
         const uint32_t b0 = (s0 + l0 - d) * sizeof(U);
         const uint32_t w0 = b0 >> 2, sh = b0 & 3;
@@ -85,7 +92,7 @@ __device__ __forceinline__ void store_span(const U* stage, uint32_t s0, uint32_t
         for (uint32_t i = 0; i < PER; ++i) {
           if (i >= i_lo && i < i_hi) {
             const uint32_t word = o[(i * sizeof(U)) >> 2];
-            out[g0 + (int64_t)i] = (U)(word >> (8 * ((i * sizeof(U)) & 3)));
+            out[g0 + (I)i] = (U)(word >> (8 * ((i * sizeof(U)) & 3)));
           }
         }
       }
@@ -170,9 +177,9 @@ __device__ __forceinline__ uint32_t spill8(uint32_t Cp) {
 // inside).  x: the chunk; xp: the 4 bytes before it; off: the chunk's formula offset
 // relative to the stage's PAD slot.  Returns the slot after the chunk's last word (LIM
 // for a chunk that lies past the stage); *det reports a detected error nearby.
-template <uint32_t PAD, uint32_t LIM, uint32_t DUMP>
-__device__ __forceinline__ uint32_t chunk_u8_to_u16(const uint32_t x[4], uint32_t xp, bool full, uint64_t q0,
-                                                    uint64_t lo, uint64_t hi, uint32_t off, uint16_t* stage,
+template <uint32_t PAD, uint32_t LIM, uint32_t DUMP, typename P = uint64_t>
+__device__ __forceinline__ uint32_t chunk_u8_to_u16(const uint32_t x[4], uint32_t xp, bool full, P q0, P lo, P hi,
+                                                    uint32_t off, uint16_t* stage,
                                                     uint32_t* first, uint32_t* det_out,
                                                     const uint32_t* mE = nullptr) {
   Chunk8 ch;
@@ -189,7 +196,8 @@ __device__ __forceinline__ uint32_t chunk_u8_to_u16(const uint32_t x[4], uint32_
     } else {
       range_masks(q0, lo, hi, inE);
     }
-    const int64_t t = (int64_t)hi - (int64_t)q0;
+    typedef typename std::make_signed<P>::type SP;
+    const SP t = (SP)hi - (SP)q0;
     const uint32_t tt = (t >= 0 && t < 16) ? (uint32_t)t : 16u;
 #pragma unroll
     for (int k = 0; k < 4; ++k) inD[k] = inE[k] | ((tt >> 2) == (uint32_t)k ? 0xFFu << (8 * (tt & 3)) : 0u);
@@ -472,13 +480,10 @@ __device__ __forceinline__ void pk_enc16s(uint32_t X, uint32_t P, uint32_t c_lo,
   v_hi = c_hi == 3 ? t3h : (c_hi == 2 ? t2h : (X >> 16));
 }
 
-// 16-bit lane masks (0xFFFF) of the chunk's word positions q0 + j in [lo, hi), as
-// four dwords of two words each; the per-lane bias of 0x8000 keeps the subtractions
-// from borrowing across lanes (see range_masks).
-__device__ __forceinline__ void word_masks(uint64_t q0, uint64_t lo, uint64_t hi, uint32_t m[4]) {
-  const int64_t a64 = (int64_t)lo - (int64_t)q0, b64 = (int64_t)hi - (int64_t)q0;
-  const uint32_t a = a64 <= 0 ? 0u : (a64 >= 8 ? 8u : (uint32_t)a64);
-  const uint32_t b = b64 <= 0 ? 0u : (b64 >= 8 ? 8u : (uint32_t)b64);
+// 16-bit lane masks (0xFFFF) of the chunk words a <= j < b (0 <= a, b <= 8), as four
+// dwords of two words each; the per-lane bias of 0x8000 keeps the subtractions from
+// borrowing across lanes (see byte_masks_ab).
+__device__ __forceinline__ void word_masks_ab(uint32_t a, uint32_t b, uint32_t m[4]) {
   const uint32_t A = a * 0x00010001u, B = (b * 0x00010001u) | 0x80008000u;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -486,6 +491,22 @@ __device__ __forceinline__ void word_masks(uint64_t q0, uint64_t lo, uint64_t hi
     const uint32_t in = ((idx | 0x80008000u) - A) & (B - (idx + 0x00010001u)) & 0x80008000u;
     m[k] = (in >> 15) * 0xFFFFu;
   }
+}
+
+// Word masks of the chunk's word positions q0 + j in [lo, hi).
+__device__ __forceinline__ void word_masks(uint64_t q0, uint64_t lo, uint64_t hi, uint32_t m[4]) {
+  const int64_t a64 = (int64_t)lo - (int64_t)q0, b64 = (int64_t)hi - (int64_t)q0;
+  const uint32_t a = a64 <= 0 ? 0u : (a64 >= 8 ? 8u : (uint32_t)a64);
+  const uint32_t b = b64 <= 0 ? 0u : (b64 >= 8 ? 8u : (uint32_t)b64);
+  word_masks_ab(a, b, m);
+}
+
+// word_masks in 32-bit arithmetic, for positions below 2^31.
+__device__ __forceinline__ void word_masks32(uint32_t q0, uint32_t lo, uint32_t hi, uint32_t m[4]) {
+  const int32_t a32 = (int32_t)lo - (int32_t)q0, b32 = (int32_t)hi - (int32_t)q0;
+  const uint32_t a = a32 <= 0 ? 0u : (a32 >= 8 ? 8u : (uint32_t)a32);
+  const uint32_t b = b32 <= 0 ? 0u : (b32 >= 8 ? 8u : (uint32_t)b32);
+  word_masks_ab(a, b, m);
 }
 
 // Output bytes of a chunk of 8 words; with word masks, words outside count 0.

@@ -23,6 +23,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,9 +32,21 @@ SOURCES = ("csrc/utfx.hip", "csrc/utfx_kernels.hpp", "csrc/utfx_device.hpp", "cs
 COPY_KERNEL = "copyBuffer"
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
+def code_text(text: str) -> str:
+    """C++ source text without its comments and with every run of whitespace reduced to
+    one space: what decides the compiled code, so that editing a comment leaves the
+    summaries valid.  (The kernel sources hold no comment markers inside string or
+    character literals, which this does not parse.)"""
+    return " ".join(_COMMENT.sub(" ", text).split())
+
+
 def source_hash() -> str:
-    """Hash of what decides the profiled kernels: their sources, the compiler flags and
-    the tuning cache that picks their launch shapes."""
+    """Hash of what decides the profiled kernels: their sources' code (comments and
+    layout left out), the compiler flags and the tuning cache that picks their launch
+    shapes."""
     from . import build as B
 
     h = hashlib.sha256()
@@ -41,7 +54,10 @@ def source_hash() -> str:
         p = os.path.join(HERE, rel)
         if os.path.exists(p):
             with open(p, "rb") as f:
-                h.update(rel.encode() + b"\0" + f.read())
+                data = f.read()
+            if not rel.endswith(".json"):
+                data = code_text(data.decode("utf-8")).encode("utf-8")
+            h.update(rel.encode() + b"\0" + data)
     h.update(b"flags\0" + " ".join(B.HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 

@@ -88,3 +88,11 @@ def test_counters_per_input_and_rates(tmp_path):
     # another kernel chosen by name
     other = profsum.counters_text(str(tmp_path / "c"), "cmd", ["x"], input_kib=1.0, kernels=("k_other",))
     assert "k_other [x]: 1 launches" in other and "k_u8_to_u16" not in other.split("\n", 1)[1]
+
+
+def test_code_text_ignores_comments_and_layout():
+    a = "int f(int x) {  // the length\n  return x + 1; /* one more\n word */\n}\n"
+    b = "int f(int x) {\n  // a longer comment\n  // over two lines\n  return x   +   1;\n}"
+    c = "int f(int x) { return x + 2; }"
+    assert profsum.code_text(a) == profsum.code_text(b) == "int f(int x) { return x + 1; }"
+    assert profsum.code_text(c) != profsum.code_text(a)
