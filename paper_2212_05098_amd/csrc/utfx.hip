@@ -936,6 +936,8 @@ utfx_status utfx_set_tuning(utfx_ctx* c, int op, uint32_t tile_bytes, uint32_t t
 
 utfx_status utfx_set_batch_tuning(utfx_ctx* c, uint32_t wave_max_units, uint32_t large_tiles_per_segment,
                                   uint32_t large_wgs_per_cu) {
+  // the wave walkers keep positions and output offsets in 32 bits, which this upper
+  // bound on the strings they take keeps far below 2^31
   if (!c || wave_max_units < 1024 || wave_max_units > (1u << 18) ||
       (large_tiles_per_segment != 2 && large_tiles_per_segment != 4) || large_wgs_per_cu < 1 || large_wgs_per_cu > 2)
     return UTFX_E_INVALID_ARG;

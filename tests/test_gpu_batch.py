@@ -206,3 +206,6 @@ def test_batch_tunings_same_results(tuning):
         run_and_check(c, b.arena, b.in_off, b.in_len, b.direction, caps, rng)
         with pytest.raises(utfx.UtfxError):
             c.set_batch_tuning(512, 4, 2)
+        # the wave walkers keep positions in 32 bits on the strength of this bound
+        with pytest.raises(utfx.UtfxError):
+            c.set_batch_tuning((1 << 18) + 1, 4, 2)
